@@ -1,0 +1,76 @@
+"""Helpers shared by the tests (layout only: no multiply arithmetic)."""
+from __future__ import annotations
+
+import numpy as np
+
+from workloads import BlockMatrix
+
+
+def to_dense(M: BlockMatrix) -> np.ndarray:
+    D = np.zeros((M.n_rows, M.n_cols), dtype=np.float64)
+    b = M.b
+    for t in range(M.nnz):
+        i, j = int(M.I[t]), int(M.J[t])
+        D[i * b:(i + 1) * b, j * b:(j + 1) * b] = M.V[t]
+    return D
+
+
+def positions(M: BlockMatrix) -> np.ndarray:
+    """Row-major block positions I * nb_cols + J (int64)."""
+    return M.I.astype(np.int64) * M.nb_cols + M.J.astype(np.int64)
+
+
+def make(n_rows, n_cols, b, I, J, V) -> BlockMatrix:
+    I = np.asarray(I, np.int32)
+    J = np.asarray(J, np.int32)
+    order = np.lexsort((J, I))
+    V = np.asarray(V, np.float64).reshape(len(I), b, b)
+    return BlockMatrix(n_rows, n_cols, b, I[order], J[order], np.ascontiguousarray(V[order]))
+
+
+def identity(nb: int, b: int) -> BlockMatrix:
+    I = np.arange(nb, dtype=np.int32)
+    V = np.broadcast_to(np.eye(b), (nb, b, b)).copy()
+    return BlockMatrix(nb * b, nb * b, b, I, I.copy(), V)
+
+
+def block_permutation(sigma: np.ndarray, b: int) -> BlockMatrix:
+    """P with identity blocks at (sigma[j], j): (P A) moves block row j to sigma[j]."""
+    nb = len(sigma)
+    I = np.asarray(sigma, np.int32)
+    J = np.arange(nb, dtype=np.int32)
+    V = np.broadcast_to(np.eye(b), (nb, b, b)).copy()
+    return make(nb * b, nb * b, b, I, J, V)
+
+
+def random_pattern(rng, nbr, nbc, fill, b, rect_ok=True) -> BlockMatrix:
+    total = nbr * nbc
+    cnt = int(round(fill * total))
+    pos = np.sort(rng.choice(total, size=cnt, replace=False)) if cnt else np.zeros(0, np.int64)
+    I = (pos // nbc).astype(np.int32)
+    J = (pos % nbc).astype(np.int32)
+    V = rng.standard_normal((cnt, b, b))
+    return BlockMatrix(nbr * b, nbc * b, b, I, J, V)
+
+
+def compare(C_ref: BlockMatrix, C: BlockMatrix, absAB: BlockMatrix | None = None):
+    """Pattern equality (bool) and componentwise / normwise errors of C vs C_ref.
+
+    Componentwise error is |C - C_ref| / (|A||B|) (0/0 := 0); normwise is
+    ||C - C_ref||_F / ||C_ref||_F.
+    """
+    same = (C_ref.nnz == C.nnz and np.array_equal(positions(C_ref), positions(C)))
+    if not same:
+        return False, np.inf, np.inf, np.inf
+    d = C.V - C_ref.V
+    e_max = float(np.abs(d).max()) if d.size else 0.0
+    nrm = float(np.linalg.norm(C_ref.V))
+    e_f = float(np.linalg.norm(d)) / nrm if nrm > 0 else float(np.linalg.norm(d))
+    e_cw = 0.0
+    if absAB is not None and d.size:
+        den = absAB.V
+        num = np.abs(d)
+        with np.errstate(divide="ignore", invalid="ignore"):
+            r = np.where(den > 0, num / np.where(den > 0, den, 1.0), np.where(num > 0, np.inf, 0.0))
+        e_cw = float(r.max())
+    return True, e_max, e_f, e_cw
