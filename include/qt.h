@@ -1,0 +1,161 @@
+/*
+ * qt.h -- quadtree block-sparse matrix multiply on AMD MI355X (gfx950).
+ *
+ * C ABI of libqt.so. Every entry point returns a qt_status, never aborts and
+ * never lets a C++ exception cross this boundary; on failure the output
+ * handle is left NULL, nothing leaks, and qt_last_error() describes the
+ * failure (thread-local string).
+ *
+ * The operation (Rubensson & Rudberg, arXiv:1501.07800):
+ *   - A matrix is a sparse quadtree (Sec. 3.1): each internal node has four
+ *     children, any of which may be NIL (a zero submatrix that is neither
+ *     stored nor addressed); the dimension halves at every level; the lowest
+ *     level holds block-sparse leaves (Sec. 4.1): a leaf is an lb x lb grid
+ *     of b x b blocks where only nonzero blocks are stored.
+ *   - C = A*B follows Algorithm 1 (Sec. 3): NIL times anything is NIL, leaves
+ *     are multiplied block by block, and C_mn = A_m1 B_1n + A_m2 B_2n at every
+ *     level above (Algorithm 2 gives the sum's structure: a block of C exists
+ *     iff at least one product contributes to it).
+ *   - Handles are immutable once created, like registered chunks (Sec. 2):
+ *     several threads may use one handle as an input at the same time.
+ *
+ * Conventions shared by all calls:
+ *   - `stream` is a hipStream_t (NULL = the default stream). Work is queued
+ *     on it; calls return before it completes except where a call says it
+ *     synchronizes. Device memory of a handle is allocated stream-ordered on
+ *     the stream that created it and released on that stream by qt_free.
+ *   - Blocks are row-major inside a block (entry (r, c) at r*b + c).
+ *   - Device pointers are HIP device pointers on the current device.
+ */
+#ifndef QT_H
+#define QT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct qt_matrix qt_matrix;   /* opaque, immutable after creation */
+typedef struct qt_plan qt_plan;       /* opaque batched-multiply plan */
+
+typedef enum {
+    QT_OK = 0,
+    QT_ERR_ARG = 1,          /* bad pointer, negative size, index out of range */
+    QT_ERR_SHAPE = 2,        /* dimensions / block size / leaf size do not fit */
+    QT_ERR_DUPLICATE = 3,    /* the same (I, J) block given twice */
+    QT_ERR_OOM = 4,          /* a device or host allocation failed */
+    QT_ERR_DEVICE = 5,       /* a HIP call or a kernel reported an error */
+    QT_ERR_UNSUPPORTED = 6   /* a size or mode this build does not handle */
+} qt_status;
+
+typedef enum {
+    QT_F64 = 0,              /* fp64 inputs, fp64 MFMA, fp64 C */
+    QT_F32 = 1,              /* inputs rounded to fp32 (RNE), fp32 MFMA, fp32 C */
+    QT_BF16X3 = 2            /* inputs split into bf16 hi + lo; hi*hi + hi*lo + lo*hi
+                                per block product in fp32 MFMA, summed in fp64; fp64 C */
+} qt_prec;
+
+typedef enum { QT_MEM_HOST = 0, QT_MEM_DEVICE = 1 } qt_mem;
+
+/*
+ * Build a matrix from a list of nonzero blocks (Sec. 3.1 and 4.1).
+ *
+ * n_rows, n_cols: scalar dimensions; both multiples of block_size.
+ * block_size:     b, the side of a block. This build runs b in {16, 32, 64}.
+ * leaf_size:      side of a leaf; leaf_size / b must be a power of two <= 8.
+ * nblocks:        number of blocks listed (0 gives an all-NIL matrix).
+ * I, J:           block row / column of each block, 0 <= I < n_rows/b,
+ *                 0 <= J < n_cols/b; any order; no (I, J) twice.
+ * values:         nblocks * b * b fp64 values, block t at values + t*b*b.
+ * where:          whether I, J, values are host or device memory.
+ * The arrays are copied; the caller keeps ownership. Synchronizes `stream`
+ * (validation reads back an error flag). The matrix is padded to a square of
+ * side leaf_size * 2^L, the smallest that covers both dimensions.
+ * Errors: ARG (NULL pointer, negative size, I/J out of range), SHAPE (b or
+ * leaf rejected, dimension not a multiple of b), DUPLICATE, OOM, DEVICE.
+ */
+qt_status qt_build(int64_t n_rows, int64_t n_cols, int32_t block_size, int32_t leaf_size,
+                   int64_t nblocks, const int32_t* I, const int32_t* J, const double* values,
+                   qt_mem where, void* stream, qt_matrix** out);
+
+/*
+ * C = A * B (Algorithm 1). A and B may be the same handle.
+ *
+ * Both operands must have the same b and leaf size, and A's column count must
+ * equal B's row count (else SHAPE). The symbolic phase walks both quadtrees
+ * level by level from the roots, skipping every pair with a NIL operand, and
+ * lists the block products of every C block in ascending inner index k; the
+ * numeric phase runs one MFMA block GEMM per C block, accumulating in
+ * registers, and stores each C block once. The result's value type follows
+ * `prec` (F64 and BF16X3 give fp64 C, F32 gives fp32 C).
+ * Synchronizes `stream` once, to read the number of C blocks before C's
+ * values are allocated.
+ * Errors: ARG, SHAPE, OOM, DEVICE, UNSUPPORTED (more than 2^31 - 1 products).
+ */
+qt_status qt_multiply(const qt_matrix* A, const qt_matrix* B, qt_prec prec,
+                      void* stream, qt_matrix** C);
+
+/*
+ * Describe a matrix. Any output pointer may be NULL. nblocks is the number
+ * of stored (nonzero) blocks; value_type is QT_F64 or QT_F32.
+ */
+qt_status qt_info(const qt_matrix* M, int64_t* n_rows, int64_t* n_cols, int32_t* block_size,
+                  int32_t* leaf_size, int64_t* nblocks, qt_prec* value_type);
+
+/*
+ * Copy a matrix out as a block list sorted by (I, J), row-major.
+ * I, J: nblocks int32 each; values: nblocks*b*b entries of out_type
+ * (QT_F64 -> double, QT_F32 -> float; rounding to nearest even when the
+ * stored type is wider). `where` says whether the three arrays are host or
+ * device memory. Synchronizes `stream` when `where` is QT_MEM_HOST.
+ * Errors: ARG, UNSUPPORTED (out_type QT_BF16X3), OOM, DEVICE.
+ */
+qt_status qt_to_blocks(const qt_matrix* M, int32_t* I, int32_t* J, void* values,
+                       qt_prec out_type, qt_mem where, void* stream);
+
+/*
+ * Counters of the multiply that produced C (Sec. 5): pairs[l] is the number
+ * of (A node, B node) pairs with both present at quadtree level l
+ * (0 = root .. n_levels-1 = leaf level), i.e. the multiply tasks of
+ * Algorithm 1 at that level; *products is the number of block products.
+ * At most max_levels entries are written. For a matrix from qt_build all
+ * counters are zero. Errors: ARG.
+ */
+qt_status qt_stats(const qt_matrix* C, int64_t* pairs, int32_t max_levels, int32_t* n_levels,
+                   int64_t* products);
+
+/*
+ * Prepare the operand forms a multiply at `prec` reads (fp32 copy, bf16
+ * hi/lo split) so that a later timed multiply does not build them. Optional:
+ * qt_multiply builds them on first use. Thread-safe. Errors: OOM, DEVICE.
+ */
+qt_status qt_prepare(const qt_matrix* M, qt_prec prec, void* stream);
+
+/* Release a handle (NULL is ignored). Its device memory is released in
+ * order on the stream that created it. */
+void qt_free(qt_matrix* M);
+
+/* Per-phase GPU timing of qt_multiply, from HIP events recorded on the
+ * multiply's stream. qt_profile(1) starts recording (and clears totals),
+ * qt_profile(0) stops. qt_profile_read synchronizes on the recorded events
+ * and returns the summed milliseconds of the symbolic phase (traversal and
+ * product lists) and of the numeric kernel, the number of multiplies timed,
+ * and the summed block products and C blocks of those multiplies.
+ * Any output pointer may be NULL. */
+qt_status qt_profile(int enable);
+qt_status qt_profile_read(double* symbolic_ms, double* numeric_ms, int64_t* calls,
+                          int64_t* products, int64_t* c_blocks);
+
+/* Text of the last error on this thread ("" if none). */
+const char* qt_last_error(void);
+
+/* Library version string. */
+const char* qt_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* QT_H */

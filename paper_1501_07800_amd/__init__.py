@@ -1,0 +1,209 @@
+"""Quadtree block-sparse matrix multiply on AMD MI355X (gfx950).
+
+A thin ctypes binding over ``libqt.so``; every step of the multiply runs in
+the library's HIP kernels. The entry points mirror ``include/qt.h``:
+
+    build(n_rows, n_cols, b, leaf, I, J, V)  -> Matrix      (qt_build)
+    multiply(A, B, prec="f64")               -> Matrix      (qt_multiply)
+    Matrix.to_blocks(dtype)                  -> (I, J, V)   (qt_to_blocks)
+    Matrix.info(), Matrix.stats(), prepare(M, prec)
+
+Block lists may be numpy arrays (host memory) or torch tensors on the GPU
+(device memory); streams are torch streams (the current stream by default).
+Importing the package loads the library and raises if it is missing: there is
+no other implementation to fall back to.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libqt.so")
+
+QT_OK, QT_ERR_ARG, QT_ERR_SHAPE, QT_ERR_DUPLICATE, QT_ERR_OOM, QT_ERR_DEVICE, QT_ERR_UNSUPPORTED = range(7)
+PREC = {"f64": 0, "f32": 1, "bf16x3": 2}
+PREC_NAME = {v: k for k, v in PREC.items()}
+MEM_HOST, MEM_DEVICE = 0, 1
+
+STATUS = {0: "ok", 1: "invalid argument", 2: "shape", 3: "duplicate block", 4: "out of memory",
+          5: "device error", 6: "unsupported"}
+
+
+class QtError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with `python paper_1501_07800_amd/csrc/build.py`")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, i64, i32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32
+    i64p, i32p = ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int32)
+    lib.qt_build.restype = ctypes.c_int
+    lib.qt_build.argtypes = [i64, i64, i32, i32, i64, vp, vp, vp, ctypes.c_int, vp, ctypes.POINTER(vp)]
+    lib.qt_multiply.restype = ctypes.c_int
+    lib.qt_multiply.argtypes = [vp, vp, ctypes.c_int, vp, ctypes.POINTER(vp)]
+    lib.qt_info.restype = ctypes.c_int
+    lib.qt_info.argtypes = [vp, i64p, i64p, i32p, i32p, i64p, ctypes.POINTER(ctypes.c_int)]
+    lib.qt_to_blocks.restype = ctypes.c_int
+    lib.qt_to_blocks.argtypes = [vp, vp, vp, vp, ctypes.c_int, ctypes.c_int, vp]
+    lib.qt_stats.restype = ctypes.c_int
+    lib.qt_stats.argtypes = [vp, i64p, i32, i32p, i64p]
+    lib.qt_prepare.restype = ctypes.c_int
+    lib.qt_prepare.argtypes = [vp, ctypes.c_int, vp]
+    lib.qt_free.restype = None
+    lib.qt_free.argtypes = [vp]
+    lib.qt_profile.restype = ctypes.c_int
+    lib.qt_profile.argtypes = [ctypes.c_int]
+    lib.qt_profile_read.restype = ctypes.c_int
+    lib.qt_profile_read.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
+                                    i64p, i64p, i64p]
+    lib.qt_last_error.restype = ctypes.c_char_p
+    lib.qt_last_error.argtypes = []
+    lib.qt_version.restype = ctypes.c_char_p
+    lib.qt_version.argtypes = []
+    return lib
+
+
+lib = _load()
+
+EXPORTS = ("qt_build", "qt_multiply", "qt_info", "qt_to_blocks", "qt_stats", "qt_prepare", "qt_free",
+           "qt_profile", "qt_profile_read", "qt_last_error", "qt_version")
+
+
+def _check(status: int):
+    if status != QT_OK:
+        raise QtError(status, lib.qt_last_error().decode(errors="replace"))
+
+
+def _stream_ptr(stream):
+    if stream is None:
+        import torch
+        if not torch.cuda.is_available():
+            return None
+        stream = torch.cuda.current_stream()
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+def _is_torch(x) -> bool:
+    return type(x).__module__.startswith("torch")
+
+
+class Matrix:
+    """Owning wrapper of a qt_matrix handle (freed with qt_free)."""
+
+    def __init__(self, handle: int):
+        self._h = ctypes.c_void_p(handle)
+
+    @property
+    def handle(self):
+        return self._h
+
+    def free(self):
+        if self._h is not None and self._h.value:
+            lib.qt_free(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+    def info(self) -> dict:
+        r, c, n = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+        b, leaf, vt = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int()
+        _check(lib.qt_info(self._h, ctypes.byref(r), ctypes.byref(c), ctypes.byref(b), ctypes.byref(leaf),
+                           ctypes.byref(n), ctypes.byref(vt)))
+        return {"n_rows": r.value, "n_cols": c.value, "b": b.value, "leaf": leaf.value, "nblocks": n.value,
+                "value_type": PREC_NAME[vt.value]}
+
+    @property
+    def nblocks(self) -> int:
+        return self.info()["nblocks"]
+
+    def stats(self) -> dict:
+        pairs = (ctypes.c_int64 * 64)()
+        nl, prods = ctypes.c_int32(), ctypes.c_int64()
+        _check(lib.qt_stats(self._h, pairs, 64, ctypes.byref(nl), ctypes.byref(prods)))
+        return {"pairs": np.array(pairs[:nl.value], np.int64), "products": prods.value}
+
+    def to_blocks(self, dtype: str = "f64", stream=None):
+        """Copy out as (I, J, V) numpy arrays sorted by (I, J)."""
+        inf = self.info()
+        n, b = inf["nblocks"], inf["b"]
+        I = np.empty(n, np.int32)
+        J = np.empty(n, np.int32)
+        V = np.empty((n, b, b), np.float64 if dtype == "f64" else np.float32)
+        _check(lib.qt_to_blocks(self._h, I.ctypes.data, J.ctypes.data, V.ctypes.data, PREC[dtype], MEM_HOST,
+                                _stream_ptr(stream)))
+        return I, J, V
+
+    def to_blocks_device(self, I, J, V, dtype: str = "f64", stream=None):
+        """Copy out into caller-provided torch device tensors (no host sync)."""
+        _check(lib.qt_to_blocks(self._h, I.data_ptr(), J.data_ptr(), V.data_ptr(), PREC[dtype], MEM_DEVICE,
+                                _stream_ptr(stream)))
+
+
+def build(n_rows: int, n_cols: int, b: int, leaf: int, I, J, V, stream=None) -> Matrix:
+    """qt_build from a block list (numpy arrays: host; torch GPU tensors: device)."""
+    out = ctypes.c_void_p()
+    n = int(I.shape[0])
+    if _is_torch(I):
+        assert I.dtype.__str__() == "torch.int32" and J.dtype.__str__() == "torch.int32"
+        assert str(V.dtype) == "torch.float64" and V.is_contiguous()
+        where = MEM_DEVICE if I.is_cuda else MEM_HOST
+        pI, pJ, pV = I.data_ptr(), J.data_ptr(), V.data_ptr()
+        keep = (I, J, V)
+    else:
+        I = np.ascontiguousarray(I, np.int32)
+        J = np.ascontiguousarray(J, np.int32)
+        V = np.ascontiguousarray(V, np.float64)
+        where = MEM_HOST
+        pI, pJ, pV = I.ctypes.data, J.ctypes.data, V.ctypes.data
+        keep = (I, J, V)
+    _check(lib.qt_build(n_rows, n_cols, b, leaf, n, pI if n else None, pJ if n else None, pV if n else None,
+                        where, _stream_ptr(stream), ctypes.byref(out)))
+    del keep
+    return Matrix(out.value)
+
+
+def from_blockmatrix(M, leaf: int, stream=None) -> Matrix:
+    """qt_build from a ``workloads.BlockMatrix`` (host arrays)."""
+    return build(M.n_rows, M.n_cols, M.b, leaf, M.I, M.J, M.V, stream=stream)
+
+
+def multiply(A: Matrix, B: Matrix, prec: str = "f64", stream=None) -> Matrix:
+    """qt_multiply: C = A*B at precision "f64", "f32" or "bf16x3"."""
+    out = ctypes.c_void_p()
+    _check(lib.qt_multiply(A.handle, B.handle, PREC[prec], _stream_ptr(stream), ctypes.byref(out)))
+    return Matrix(out.value)
+
+
+def prepare(M: Matrix, prec: str, stream=None):
+    """qt_prepare: build the operand forms a multiply at ``prec`` reads."""
+    _check(lib.qt_prepare(M.handle, PREC[prec], _stream_ptr(stream)))
+
+
+def profile(enable: bool):
+    _check(lib.qt_profile(1 if enable else 0))
+
+
+def profile_read() -> dict:
+    a, b = ctypes.c_double(), ctypes.c_double()
+    calls, prods, cb = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+    _check(lib.qt_profile_read(ctypes.byref(a), ctypes.byref(b), ctypes.byref(calls), ctypes.byref(prods),
+                               ctypes.byref(cb)))
+    return {"symbolic_ms": a.value, "numeric_ms": b.value, "calls": calls.value, "products": prods.value,
+            "c_blocks": cb.value}
+
+
+def version() -> str:
+    return lib.qt_version().decode()

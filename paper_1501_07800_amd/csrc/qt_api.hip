@@ -1,0 +1,208 @@
+// Exported C entry points: argument checks, exception-to-status mapping,
+// per-phase event timing.
+#include "qt_internal.h"
+
+#include <cstdio>
+
+namespace qt {
+
+static thread_local std::string t_last_error;
+
+void set_last_error(const std::string& m) { t_last_error = m; }
+
+qt_matrix* build(int64_t, int64_t, int32_t, int32_t, int64_t, const int32_t*, const int32_t*, const double*,
+                 qt_mem, hipStream_t);
+qt_matrix* multiply(qt_matrix*, qt_matrix*, qt_prec, hipStream_t);
+void to_blocks(const qt_matrix*, int32_t*, int32_t*, void*, qt_prec, qt_mem, hipStream_t);
+
+// ------------------------------------------------------------ profiling
+
+static std::mutex g_prof_mu;
+static bool g_prof_on = false;
+static std::vector<PhaseEvents> g_prof_events;
+static double g_prof_sym = 0, g_prof_num = 0;
+static int64_t g_prof_calls = 0, g_prof_products = 0, g_prof_cblocks = 0;
+
+bool profiling_on() {
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    return g_prof_on;
+}
+
+void profile_push(const PhaseEvents& ev) {
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    g_prof_events.push_back(ev);
+}
+
+static void profile_drain() {
+    for (auto& ev : g_prof_events) {
+        QT_HIP(hipEventSynchronize(ev.e2));
+        float a = 0, b = 0;
+        QT_HIP(hipEventElapsedTime(&a, ev.e0, ev.e1));
+        QT_HIP(hipEventElapsedTime(&b, ev.e1, ev.e2));
+        g_prof_sym += a;
+        g_prof_num += b;
+        g_prof_calls += 1;
+        g_prof_products += ev.products;
+        g_prof_cblocks += ev.cblocks;
+        (void)hipEventDestroy(ev.e0);
+        (void)hipEventDestroy(ev.e1);
+        (void)hipEventDestroy(ev.e2);
+    }
+    g_prof_events.clear();
+}
+
+}  // namespace qt
+
+using namespace qt;
+
+#define QT_GUARD_BEGIN \
+    try {              \
+        set_last_error("");
+#define QT_GUARD_END                                         \
+    }                                                        \
+    catch (const qt::Error& e) {                             \
+        set_last_error(e.what());                            \
+        return e.status;                                     \
+    }                                                        \
+    catch (const std::bad_alloc&) {                          \
+        set_last_error("host allocation failed");            \
+        return QT_ERR_OOM;                                   \
+    }                                                        \
+    catch (const std::exception& e) {                        \
+        set_last_error(e.what());                            \
+        return QT_ERR_DEVICE;                                \
+    }                                                        \
+    catch (...) {                                            \
+        set_last_error("unknown error");                     \
+        return QT_ERR_DEVICE;                                \
+    }
+
+extern "C" {
+
+qt_status qt_build(int64_t n_rows, int64_t n_cols, int32_t block_size, int32_t leaf_size, int64_t nblocks,
+                   const int32_t* I, const int32_t* J, const double* values, qt_mem where, void* stream,
+                   qt_matrix** out) {
+    if (!out) {
+        set_last_error("NULL output handle");
+        return QT_ERR_ARG;
+    }
+    *out = nullptr;
+    QT_GUARD_BEGIN
+    *out = build(n_rows, n_cols, block_size, leaf_size, nblocks, I, J, values, where, (hipStream_t)stream);
+    return QT_OK;
+    QT_GUARD_END
+}
+
+qt_status qt_multiply(const qt_matrix* A, const qt_matrix* B, qt_prec prec, void* stream, qt_matrix** C) {
+    if (!C) {
+        set_last_error("NULL output handle");
+        return QT_ERR_ARG;
+    }
+    *C = nullptr;
+    if (!A || !B) {
+        set_last_error("NULL operand");
+        return QT_ERR_ARG;
+    }
+    QT_GUARD_BEGIN
+    *C = multiply(const_cast<qt_matrix*>(A), const_cast<qt_matrix*>(B), prec, (hipStream_t)stream);
+    return QT_OK;
+    QT_GUARD_END
+}
+
+qt_status qt_info(const qt_matrix* M, int64_t* n_rows, int64_t* n_cols, int32_t* block_size, int32_t* leaf_size,
+                  int64_t* nblocks, qt_prec* value_type) {
+    if (!M) {
+        set_last_error("NULL matrix");
+        return QT_ERR_ARG;
+    }
+    if (n_rows) *n_rows = M->n_rows;
+    if (n_cols) *n_cols = M->n_cols;
+    if (block_size) *block_size = M->b;
+    if (leaf_size) *leaf_size = M->leaf;
+    if (nblocks) *nblocks = M->nblocks;
+    if (value_type) *value_type = M->vtype;
+    return QT_OK;
+}
+
+qt_status qt_to_blocks(const qt_matrix* M, int32_t* I, int32_t* J, void* values, qt_prec out_type, qt_mem where,
+                       void* stream) {
+    if (!M) {
+        set_last_error("NULL matrix");
+        return QT_ERR_ARG;
+    }
+    QT_GUARD_BEGIN
+    to_blocks(M, I, J, values, out_type, where, (hipStream_t)stream);
+    return QT_OK;
+    QT_GUARD_END
+}
+
+qt_status qt_stats(const qt_matrix* C, int64_t* pairs, int32_t max_levels, int32_t* n_levels, int64_t* products) {
+    if (!C || max_levels < 0 || (max_levels > 0 && !pairs)) {
+        set_last_error("bad argument");
+        return QT_ERR_ARG;
+    }
+    const int32_t nl = C->L + 1;
+    if (n_levels) *n_levels = nl;
+    for (int32_t l = 0; l < nl && l < max_levels; ++l) pairs[l] = (l < (int32_t)C->pairs.size()) ? C->pairs[l] : 0;
+    if (products) *products = C->products;
+    return QT_OK;
+}
+
+qt_status qt_prepare(const qt_matrix* M, qt_prec prec, void* stream) {
+    if (!M) {
+        set_last_error("NULL matrix");
+        return QT_ERR_ARG;
+    }
+    QT_GUARD_BEGIN
+    qt_matrix* m = const_cast<qt_matrix*>(M);
+    hipStream_t s = (hipStream_t)stream;
+    if (prec == QT_F64)
+        operand_f64(m, s);
+    else if (prec == QT_F32)
+        operand_f32(m, s);
+    else if (prec == QT_BF16X3)
+        operand_bf16(m, s);
+    else
+        fail(QT_ERR_ARG, "unknown precision");
+    build_histograms(m, s);
+    return QT_OK;
+    QT_GUARD_END
+}
+
+void qt_free(qt_matrix* M) {
+    try {
+        delete M;
+    } catch (...) {
+    }
+}
+
+qt_status qt_profile(int enable) {
+    QT_GUARD_BEGIN
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    profile_drain();
+    g_prof_on = enable != 0;
+    g_prof_sym = g_prof_num = 0;
+    g_prof_calls = g_prof_products = g_prof_cblocks = 0;
+    return QT_OK;
+    QT_GUARD_END
+}
+
+qt_status qt_profile_read(double* symbolic_ms, double* numeric_ms, int64_t* calls, int64_t* products,
+                          int64_t* c_blocks) {
+    QT_GUARD_BEGIN
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    profile_drain();
+    if (symbolic_ms) *symbolic_ms = g_prof_sym;
+    if (numeric_ms) *numeric_ms = g_prof_num;
+    if (calls) *calls = g_prof_calls;
+    if (products) *products = g_prof_products;
+    if (c_blocks) *c_blocks = g_prof_cblocks;
+    return QT_OK;
+    QT_GUARD_END
+}
+
+const char* qt_last_error(void) { return t_last_error.c_str(); }
+
+const char* qt_version(void) { return "qt 0.1 (gfx950)"; }
+
+}  // extern "C"

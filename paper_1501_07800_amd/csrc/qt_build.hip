@@ -1,0 +1,508 @@
+// Building a quadtree matrix from a block list, copying it back out, and the
+// derived operand forms (fp32 copy, bf16 hi/lo split) and count histograms.
+//
+// Representation (Sec. 3.1 and 4.1 of the paper): blocks sorted by Morton
+// key, so every quadtree node covers a contiguous run; leaves are lb x lb
+// block grids stored as three 64-bit occupancy masks plus the index of their
+// first block; every level above holds a 4-entry child table per node, -1
+// marking a NIL child. Nodes carry no global offsets, only their Morton key.
+#include "qt_internal.h"
+#include "qt_morton.h"
+
+#include <algorithm>
+#include <set>
+
+namespace qt {
+
+// ------------------------------------------------------------ allocation
+
+static std::mutex g_pool_mu;
+static std::set<int> g_pool_ready;
+
+static void ensure_pool() {
+    int dev = 0;
+    QT_HIP(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lk(g_pool_mu);
+    if (g_pool_ready.count(dev)) return;
+    hipMemPool_t pool;
+    QT_HIP(hipDeviceGetDefaultMemPool(&pool, dev));
+    uint64_t thr = ~0ull;
+    QT_HIP(hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr));
+    g_pool_ready.insert(dev);
+}
+
+void* dev_alloc(size_t bytes, hipStream_t s) {
+    ensure_pool();
+    void* p = nullptr;
+    hipError_t e = hipMallocAsync(&p, bytes, s);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        hip_check(e, "hipMallocAsync");
+    }
+    return p;
+}
+
+void dev_free(void* p, hipStream_t s) {
+    if (p) (void)hipFreeAsync(p, s);
+}
+
+// --------------------------------------------------------------- kernels
+
+__global__ void k_fill_i32(int32_t* p, int64_t n, int32_t v) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+__global__ void k_build_keys(const int32_t* __restrict__ I, const int32_t* __restrict__ J, int64_t n,
+                             int64_t nbr, int64_t nbc, uint64_t* __restrict__ keys,
+                             int32_t* __restrict__ perm, int32_t* __restrict__ err) {
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n) return;
+    int32_t i = I[t], j = J[t];
+    if (i < 0 || j < 0 || i >= nbr || j >= nbc) {
+        atomicOr(err, 1);
+        keys[t] = (uint64_t)t;
+    } else {
+        keys[t] = morton_key((uint32_t)i, (uint32_t)j);
+    }
+    perm[t] = (int32_t)t;
+}
+
+__global__ void k_build_dups(const uint64_t* __restrict__ keys, int64_t n, int32_t* __restrict__ err) {
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= 1 && t < n && keys[t] == keys[t - 1]) atomicOr(err, 2);
+}
+
+// dst block t = src block perm[t]; one workgroup copies one block.
+template <class T>
+__global__ void k_gather_blocks(const T* __restrict__ src, const int32_t* __restrict__ perm, int64_t n,
+                                int bb, T* __restrict__ dst) {
+    for (int64_t t = blockIdx.x; t < n; t += gridDim.x) {
+        const T* s = src + (size_t)perm[t] * bb;
+        T* d = dst + (size_t)t * bb;
+        for (int e = threadIdx.x; e < bb; e += blockDim.x) d[e] = s[e];
+    }
+}
+
+__global__ void k_run_flags(const uint64_t* __restrict__ keys, int64_t n, int shift, int32_t* __restrict__ flags) {
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n) return;
+    flags[t] = (t == 0 || (keys[t] >> shift) != (keys[t - 1] >> shift)) ? 1 : 0;
+}
+
+// The first block of every leaf fills the leaf's base, key and masks.
+__global__ void k_leaf_fill(const uint64_t* __restrict__ keys, int64_t n, int lb_log,
+                            const int32_t* __restrict__ flags, const int32_t* __restrict__ ex,
+                            int32_t* __restrict__ base, uint64_t* __restrict__ lkey,
+                            uint64_t* __restrict__ mo, uint64_t* __restrict__ rm, uint64_t* __restrict__ cm) {
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n || !flags[t]) return;
+    const int shift = 2 * lb_log;
+    const int lb = 1 << lb_log;
+    const uint64_t lk = keys[t] >> shift;
+    const int32_t li = ex[t];
+    uint64_t m0 = 0, m1 = 0, m2 = 0;
+    for (int64_t u = t; u < n && (keys[u] >> shift) == lk; ++u) {
+        uint32_t q = (uint32_t)(keys[u] & ((1ull << shift) - 1));
+        uint32_t r = morton_row(q), c = morton_col(q);
+        m0 |= 1ull << q;
+        m1 |= 1ull << (r * lb + c);
+        m2 |= 1ull << (c * lb + r);
+    }
+    base[li] = (int32_t)t;
+    lkey[li] = lk;
+    mo[li] = m0;
+    rm[li] = m1;
+    cm[li] = m2;
+}
+
+// Parents of a sorted, unique list of child keys.
+__global__ void k_parent_fill(const uint64_t* __restrict__ ck, int64_t nc, const int32_t* __restrict__ flags,
+                              const int32_t* __restrict__ ex, int32_t* __restrict__ child,
+                              uint64_t* __restrict__ pkey) {
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nc) return;
+    int32_t p = ex[t + 1] - 1;
+    child[4 * p + (int)(ck[t] & 3)] = (int32_t)t;
+    if (flags[t]) pkey[p] = ck[t] >> 2;
+}
+
+__global__ void k_hist(const uint64_t* __restrict__ keys, int64_t n, int32_t* __restrict__ rowcnt,
+                       int32_t* __restrict__ colcnt) {
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n) return;
+    uint64_t k = keys[t];
+    atomicAdd(rowcnt + morton_row(k), 1);
+    atomicAdd(colcnt + morton_col(k), 1);
+}
+
+__global__ void k_f64_to_f32(const double* __restrict__ s, int64_t n, float* __restrict__ d) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) d[i] = __double2float_rn(s[i]);
+}
+
+__global__ void k_f32_to_f64(const float* __restrict__ s, int64_t n, double* __restrict__ d) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) d[i] = (double)s[i];
+}
+
+// Round a binary32 value to bfloat16, nearest even, on the bit pattern.
+__device__ inline uint16_t bf16_round(float x) {
+    uint32_t u = __float_as_uint(x);
+    if ((u & 0x7F800000u) == 0x7F800000u && (u & 0x007FFFFFu)) return (uint16_t)((u >> 16) | 0x40);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+__device__ inline float bf16_to_f32(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+// hi = bf16(a32), lo = bf16(a32 - hi) per entry, row-major and transposed.
+template <class T>
+__global__ void k_bf16_split(const T* __restrict__ src, int64_t nblk, int b, uint16_t* __restrict__ hi,
+                             uint16_t* __restrict__ lo, uint16_t* __restrict__ hi_t, uint16_t* __restrict__ lo_t) {
+    const int64_t bb = (int64_t)b * b;
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nblk * bb) return;
+    float a = (float)src[i];   // fp64 -> fp32 rounds to nearest even
+    uint16_t h = bf16_round(a);
+    uint16_t l = bf16_round(a - bf16_to_f32(h));
+    int64_t t = i / bb;
+    int e = (int)(i - t * bb);
+    int r = e / b, c = e - r * b;
+    hi[i] = h;
+    lo[i] = l;
+    hi_t[t * bb + (int64_t)c * b + r] = h;
+    lo_t[t * bb + (int64_t)c * b + r] = l;
+}
+
+__global__ void k_rowmajor_keys(const uint64_t* __restrict__ bkey, int64_t n, int64_t nbc,
+                                uint64_t* __restrict__ rk, int32_t* __restrict__ perm) {
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n) return;
+    rk[t] = (uint64_t)morton_row(bkey[t]) * (uint64_t)nbc + morton_col(bkey[t]);
+    perm[t] = (int32_t)t;
+}
+
+__global__ void k_coords(const uint64_t* __restrict__ bkey, const int32_t* __restrict__ perm, int64_t n,
+                         int32_t* __restrict__ I, int32_t* __restrict__ J) {
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n) return;
+    uint64_t k = bkey[perm[t]];
+    I[t] = (int32_t)morton_row(k);
+    J[t] = (int32_t)morton_col(k);
+}
+
+template <class S, class D>
+__global__ void k_gather_convert(const S* __restrict__ src, const int32_t* __restrict__ perm, int64_t n, int bb,
+                                 D* __restrict__ dst) {
+    for (int64_t t = blockIdx.x; t < n; t += gridDim.x) {
+        const S* s = src + (size_t)perm[t] * bb;
+        D* d = dst + (size_t)t * bb;
+        for (int e = threadIdx.x; e < bb; e += blockDim.x) d[e] = (D)s[e];
+    }
+}
+
+template <>
+__global__ void k_gather_convert<double, float>(const double* __restrict__ src, const int32_t* __restrict__ perm,
+                                                int64_t n, int bb, float* __restrict__ dst) {
+    for (int64_t t = blockIdx.x; t < n; t += gridDim.x) {
+        const double* s = src + (size_t)perm[t] * bb;
+        float* d = dst + (size_t)t * bb;
+        for (int e = threadIdx.x; e < bb; e += blockDim.x) d[e] = __double2float_rn(s[e]);
+    }
+}
+
+// ------------------------------------------------------------- helpers
+
+static inline unsigned grid_for(int64_t n, int T = 256) {
+    int64_t g = (n + T - 1) / T;
+    return (unsigned)std::max<int64_t>(g, 1);
+}
+
+static inline unsigned block_grid(int64_t n) {
+    return (unsigned)std::max<int64_t>(1, std::min<int64_t>(n, 1 << 20));
+}
+
+template <class T>
+static T read_scalar(const T* dptr, hipStream_t s) {
+    T v{};
+    QT_HIP(hipMemcpyAsync(&v, dptr, sizeof(T), hipMemcpyDeviceToHost, s));
+    QT_HIP(hipStreamSynchronize(s));
+    return v;
+}
+
+uint64_t morton2(uint32_t r, uint32_t c) { return morton_key(r, c); }
+
+static int ilog2(int64_t x) {
+    int l = 0;
+    while ((int64_t(1) << l) < x) ++l;
+    return l;
+}
+
+// ------------------------------------------------------------ histograms
+
+void build_histograms(qt_matrix* M, hipStream_t s) {
+    if (M->hist.ready) return;
+    Histograms h;
+    h.rowcnt.resize(M->L + 1);
+    h.colcnt.resize(M->L + 1);
+    const int64_t nb_pad = (int64_t)M->lb << M->L;
+    int64_t total = 2 * nb_pad;
+    for (int l = 0; l <= M->L; ++l) total += 2 * (int64_t(1) << l);
+    DBuf<int32_t> d(total, s);
+    QT_HIP(hipMemsetAsync(d.p, 0, total * sizeof(int32_t), s));
+    int64_t off = 0;
+    std::vector<int64_t> offs;
+    for (int l = 0; l <= M->L; ++l) {
+        const int64_t side = int64_t(1) << l;
+        const uint64_t* keys = (l < M->L) ? M->levels[l].key.p : M->leaves.key.p;
+        const int64_t n = (l < M->L) ? M->levels[l].n : M->leaves.n;
+        offs.push_back(off);
+        if (n > 0) {
+            k_hist<<<grid_for(n), 256, 0, s>>>(keys, n, d.p + off, d.p + off + side);
+            QT_LAUNCH("k_hist");
+        }
+        off += 2 * side;
+    }
+    if (M->nblocks > 0) {
+        k_hist<<<grid_for(M->nblocks), 256, 0, s>>>(M->bkey.p, M->nblocks, d.p + off, d.p + off + nb_pad);
+        QT_LAUNCH("k_hist");
+    }
+    std::vector<int32_t> host(total);
+    QT_HIP(hipMemcpyAsync(host.data(), d.p, total * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    QT_HIP(hipStreamSynchronize(s));
+    for (int l = 0; l <= M->L; ++l) {
+        const int64_t side = int64_t(1) << l;
+        h.rowcnt[l].assign(host.begin() + offs[l], host.begin() + offs[l] + side);
+        h.colcnt[l].assign(host.begin() + offs[l] + side, host.begin() + offs[l] + 2 * side);
+    }
+    h.blk_row.assign(host.begin() + off, host.begin() + off + nb_pad);
+    h.blk_col.assign(host.begin() + off + nb_pad, host.begin() + off + 2 * nb_pad);
+    h.ready = true;
+    M->hist = std::move(h);
+}
+
+// ----------------------------------------------------- operand forms
+
+const double* operand_f64(qt_matrix* M, hipStream_t s) {
+    if (M->vtype == QT_F64) return M->v64.p;
+    std::lock_guard<std::mutex> lk(M->mu);
+    if (!M->v64_cache.p && M->nblocks > 0) {
+        const int64_t n = M->nblocks * (int64_t)M->b * M->b;
+        M->v64_cache.alloc(n, s);
+        k_f32_to_f64<<<grid_for(n), 256, 0, s>>>(M->v32.p, n, M->v64_cache.p);
+        QT_LAUNCH("k_f32_to_f64");
+    }
+    return M->v64_cache.p;
+}
+
+const float* operand_f32(qt_matrix* M, hipStream_t s) {
+    std::lock_guard<std::mutex> lk(M->mu);
+    if (!M->v32.p && M->nblocks > 0) {
+        const int64_t n = M->nblocks * (int64_t)M->b * M->b;
+        M->v32.alloc(n, s);
+        k_f64_to_f32<<<grid_for(n), 256, 0, s>>>(M->v64.p, n, M->v32.p);
+        QT_LAUNCH("k_f64_to_f32");
+    }
+    return M->v32.p;
+}
+
+void operand_bf16(qt_matrix* M, hipStream_t s) {
+    std::lock_guard<std::mutex> lk(M->mu);
+    if (M->bf_hi.p || M->nblocks == 0) return;
+    const int64_t n = M->nblocks * (int64_t)M->b * M->b;
+    M->bf_hi.alloc(n, s);
+    M->bf_lo.alloc(n, s);
+    M->bf_hi_t.alloc(n, s);
+    M->bf_lo_t.alloc(n, s);
+    if (M->vtype == QT_F64)
+        k_bf16_split<double><<<grid_for(n), 256, 0, s>>>(M->v64.p, M->nblocks, M->b, M->bf_hi.p, M->bf_lo.p,
+                                                         M->bf_hi_t.p, M->bf_lo_t.p);
+    else
+        k_bf16_split<float><<<grid_for(n), 256, 0, s>>>(M->v32.p, M->nblocks, M->b, M->bf_hi.p, M->bf_lo.p,
+                                                        M->bf_hi_t.p, M->bf_lo_t.p);
+    QT_LAUNCH("k_bf16_split");
+}
+
+// ----------------------------------------------------------------- build
+
+void build_tree_levels(qt_matrix* M, hipStream_t s);
+
+qt_matrix* build(int64_t n_rows, int64_t n_cols, int32_t b, int32_t leaf, int64_t nblocks, const int32_t* I,
+                 const int32_t* J, const double* values, qt_mem where, hipStream_t s) {
+    if (n_rows < 0 || n_cols < 0 || nblocks < 0) fail(QT_ERR_ARG, "negative size");
+    if (where != QT_MEM_HOST && where != QT_MEM_DEVICE) fail(QT_ERR_ARG, "bad memory kind");
+    if (nblocks > 0 && (!I || !J || !values)) fail(QT_ERR_ARG, "NULL block list");
+    if (b != 16 && b != 32 && b != 64) fail(QT_ERR_SHAPE, "block size must be 16, 32 or 64");
+    if (leaf <= 0 || leaf % b) fail(QT_ERR_SHAPE, "leaf size must be a positive multiple of the block size");
+    const int lb = leaf / b;
+    if (lb & (lb - 1)) fail(QT_ERR_SHAPE, "leaf size / block size must be a power of two");
+    if (lb > 8) fail(QT_ERR_SHAPE, "leaf size / block size must be at most 8");
+    if (n_rows % b || n_cols % b) fail(QT_ERR_SHAPE, "dimensions must be multiples of the block size");
+    const int64_t nbr = n_rows / b, nbc = n_cols / b;
+    if (nbr > (int64_t(1) << 30) || nbc > (int64_t(1) << 30)) fail(QT_ERR_UNSUPPORTED, "too many blocks per side");
+    if (nblocks > (int64_t(1) << 31) - 2) fail(QT_ERR_UNSUPPORTED, "too many blocks");
+
+    std::unique_ptr<qt_matrix> M(new qt_matrix);
+    M->n_rows = n_rows;
+    M->n_cols = n_cols;
+    M->b = b;
+    M->leaf = leaf;
+    M->lb = lb;
+    M->lb_log = ilog2(lb);
+    int64_t side = lb;
+    int L = 0;
+    while (side < std::max<int64_t>(std::max<int64_t>(nbr, nbc), 1)) {
+        side *= 2;
+        ++L;
+    }
+    M->L = L;
+    M->vtype = QT_F64;
+    M->nblocks = nblocks;
+    M->stream = s;
+    QT_HIP(hipGetDevice(&M->device));
+    M->levels.resize(L);
+    const int bb = b * b;
+
+    if (nblocks == 0) {
+        build_histograms(M.get(), s);
+        return M.release();
+    }
+
+    // operands on the device
+    DBuf<int32_t> dI, dJ;
+    DBuf<double> dV;
+    const int32_t* pI = I;
+    const int32_t* pJ = J;
+    const double* pV = values;
+    if (where == QT_MEM_HOST) {
+        dI.alloc(nblocks, s);
+        dJ.alloc(nblocks, s);
+        dV.alloc((size_t)nblocks * bb, s);
+        QT_HIP(hipMemcpyAsync(dI.p, I, nblocks * sizeof(int32_t), hipMemcpyHostToDevice, s));
+        QT_HIP(hipMemcpyAsync(dJ.p, J, nblocks * sizeof(int32_t), hipMemcpyHostToDevice, s));
+        QT_HIP(hipMemcpyAsync(dV.p, values, (size_t)nblocks * bb * sizeof(double), hipMemcpyHostToDevice, s));
+        pI = dI.p;
+        pJ = dJ.p;
+        pV = dV.p;
+    }
+
+    int64_t npow2 = 1;
+    while (npow2 < nblocks) npow2 <<= 1;
+    DBuf<uint64_t> keys(npow2, s);
+    DBuf<int32_t> perm(npow2, s);
+    DBuf<int32_t> derr(1, s);
+    QT_HIP(hipMemsetAsync(derr.p, 0, sizeof(int32_t), s));
+    k_build_keys<<<grid_for(nblocks), 256, 0, s>>>(pI, pJ, nblocks, nbr, nbc, keys.p, perm.p, derr.p);
+    QT_LAUNCH("k_build_keys");
+    bitonic_sort(keys.p, perm.p, nblocks, s);
+    k_build_dups<<<grid_for(nblocks), 256, 0, s>>>(keys.p, nblocks, derr.p);
+    QT_LAUNCH("k_build_dups");
+    const int32_t err = read_scalar(derr.p, s);
+    if (err & 1) fail(QT_ERR_ARG, "block index out of range");
+    if (err & 2) fail(QT_ERR_DUPLICATE, "the same (I, J) block is listed twice");
+
+    M->v64.alloc((size_t)nblocks * bb, s);
+    k_gather_blocks<double><<<block_grid(nblocks), 256, 0, s>>>(pV, perm.p, nblocks, bb, M->v64.p);
+    QT_LAUNCH("k_gather_blocks");
+    M->bkey = std::move(keys);   // first nblocks entries are the sorted keys
+    build_tree_levels(M.get(), s);
+    build_histograms(M.get(), s);
+    QT_HIP(hipStreamSynchronize(s));
+    return M.release();
+}
+
+// Leaves and levels above, from the sorted block keys of M.
+void build_tree_levels(qt_matrix* M, hipStream_t s) {
+    const int64_t n = M->nblocks;
+    const int shift = 2 * M->lb_log;
+    DBuf<int32_t> flags(n, s), ex(n + 1, s), tmp(scan_tmp_elems(n) + 1, s);
+    k_run_flags<<<grid_for(n), 256, 0, s>>>(M->bkey.p, n, shift, flags.p);
+    QT_LAUNCH("k_run_flags");
+    exclusive_scan(flags.p, ex.p, n, tmp.p, s);
+    const int32_t nleaves = read_scalar(ex.p + n, s);
+    LeafLevel& lv = M->leaves;
+    lv.n = nleaves;
+    lv.base.alloc(nleaves, s);
+    lv.key.alloc(nleaves, s);
+    lv.mask_mo.alloc(nleaves, s);
+    lv.mask_rm.alloc(nleaves, s);
+    lv.mask_cm.alloc(nleaves, s);
+    k_leaf_fill<<<grid_for(n), 256, 0, s>>>(M->bkey.p, n, M->lb_log, flags.p, ex.p, lv.base.p, lv.key.p,
+                                            lv.mask_mo.p, lv.mask_rm.p, lv.mask_cm.p);
+    QT_LAUNCH("k_leaf_fill");
+
+    const uint64_t* ck = lv.key.p;
+    int64_t nc = nleaves;
+    for (int l = M->L - 1; l >= 0; --l) {
+        DBuf<int32_t> f(nc, s), e(nc + 1, s), t2(scan_tmp_elems(nc) + 1, s);
+        k_run_flags<<<grid_for(nc), 256, 0, s>>>(ck, nc, 2, f.p);
+        QT_LAUNCH("k_run_flags");
+        exclusive_scan(f.p, e.p, nc, t2.p, s);
+        const int32_t np = read_scalar(e.p + nc, s);
+        TreeLevel& tl = M->levels[l];
+        tl.n = np;
+        tl.child.alloc(4 * (int64_t)np, s);
+        tl.key.alloc(np, s);
+        k_fill_i32<<<grid_for(4 * (int64_t)np), 256, 0, s>>>(tl.child.p, 4 * (int64_t)np, -1);
+        QT_LAUNCH("k_fill_i32");
+        k_parent_fill<<<grid_for(nc), 256, 0, s>>>(ck, nc, f.p, e.p, tl.child.p, tl.key.p);
+        QT_LAUNCH("k_parent_fill");
+        ck = tl.key.p;
+        nc = np;
+    }
+}
+
+// ------------------------------------------------------------ copy out
+
+void to_blocks(const qt_matrix* M, int32_t* I, int32_t* J, void* values, qt_prec out_type, qt_mem where,
+               hipStream_t s) {
+    if (out_type != QT_F64 && out_type != QT_F32) fail(QT_ERR_UNSUPPORTED, "output type must be F64 or F32");
+    if (where != QT_MEM_HOST && where != QT_MEM_DEVICE) fail(QT_ERR_ARG, "bad memory kind");
+    const int64_t n = M->nblocks;
+    if (n == 0) return;
+    if (!I || !J || !values) fail(QT_ERR_ARG, "NULL output array");
+    const int bb = M->b * M->b;
+    const int64_t nbc = M->n_cols / M->b;
+    int64_t npow2 = 1;
+    while (npow2 < n) npow2 <<= 1;
+    DBuf<uint64_t> rk(npow2, s);
+    DBuf<int32_t> perm(npow2, s);
+    k_rowmajor_keys<<<grid_for(n), 256, 0, s>>>(M->bkey.p, n, nbc, rk.p, perm.p);
+    QT_LAUNCH("k_rowmajor_keys");
+    bitonic_sort(rk.p, perm.p, n, s);
+    const size_t vbytes = (size_t)n * bb * (out_type == QT_F64 ? sizeof(double) : sizeof(float));
+    DBuf<int32_t> tI, tJ;
+    DBuf<char> tV;
+    int32_t* oI = I;
+    int32_t* oJ = J;
+    void* oV = values;
+    if (where == QT_MEM_HOST) {
+        tI.alloc(n, s);
+        tJ.alloc(n, s);
+        tV.alloc(vbytes, s);
+        oI = tI.p;
+        oJ = tJ.p;
+        oV = tV.p;
+    }
+    k_coords<<<grid_for(n), 256, 0, s>>>(M->bkey.p, perm.p, n, oI, oJ);
+    QT_LAUNCH("k_coords");
+    const unsigned g = block_grid(n);
+    if (M->vtype == QT_F64 && out_type == QT_F64)
+        k_gather_convert<double, double><<<g, 256, 0, s>>>(M->v64.p, perm.p, n, bb, (double*)oV);
+    else if (M->vtype == QT_F64)
+        k_gather_convert<double, float><<<g, 256, 0, s>>>(M->v64.p, perm.p, n, bb, (float*)oV);
+    else if (out_type == QT_F64)
+        k_gather_convert<float, double><<<g, 256, 0, s>>>(M->v32.p, perm.p, n, bb, (double*)oV);
+    else
+        k_gather_convert<float, float><<<g, 256, 0, s>>>(M->v32.p, perm.p, n, bb, (float*)oV);
+    QT_LAUNCH("k_gather_convert");
+    if (where == QT_MEM_HOST) {
+        QT_HIP(hipMemcpyAsync(I, oI, n * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        QT_HIP(hipMemcpyAsync(J, oJ, n * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        QT_HIP(hipMemcpyAsync(values, oV, vbytes, hipMemcpyDeviceToHost, s));
+        QT_HIP(hipStreamSynchronize(s));
+    }
+}
+
+}  // namespace qt

@@ -1,0 +1,207 @@
+// Internal declarations of libqt: handle layout, device buffers, error plumbing.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstring>
+#include <memory>
+#include <mutex>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "qt.h"
+
+namespace qt {
+
+// ---------------------------------------------------------------- errors
+
+struct Error : std::runtime_error {
+    qt_status status;
+    Error(qt_status s, const std::string& m) : std::runtime_error(m), status(s) {}
+};
+
+[[noreturn]] inline void fail(qt_status s, const std::string& m) { throw Error(s, m); }
+
+inline void hip_check(hipError_t e, const char* what) {
+    if (e == hipSuccess) return;
+    if (e == hipErrorOutOfMemory) fail(QT_ERR_OOM, std::string(what) + ": out of device memory");
+    fail(QT_ERR_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define QT_HIP(call) ::qt::hip_check((call), #call)
+#define QT_LAUNCH(what) ::qt::hip_check(hipGetLastError(), what)
+
+void set_last_error(const std::string& m);
+
+// ------------------------------------------------------- device buffers
+
+// Stream-ordered device allocation (hipMallocAsync from the device's default
+// pool, whose release threshold is raised so freed memory is reused).
+void* dev_alloc(size_t bytes, hipStream_t s);
+void dev_free(void* p, hipStream_t s);
+
+// Owning device buffer; released stream-ordered on the stream it was made on.
+// A DBuf may also be a non-owning view into memory owned elsewhere (an arena).
+template <class T>
+struct DBuf {
+    T* p = nullptr;
+    size_t n = 0;
+    hipStream_t s = nullptr;
+    bool own = true;
+    DBuf() = default;
+    DBuf(size_t count, hipStream_t st) { alloc(count, st); }
+    void alloc(size_t count, hipStream_t st) {
+        release();
+        s = st;
+        n = count;
+        p = count ? static_cast<T*>(dev_alloc(count * sizeof(T), st)) : nullptr;
+    }
+    void view(void* ptr, size_t count) {
+        release();
+        p = static_cast<T*>(ptr);
+        n = count;
+        own = false;
+    }
+    void release() {
+        if (p && own) dev_free(p, s);
+        p = nullptr;
+        n = 0;
+        own = true;
+    }
+    ~DBuf() { release(); }
+    DBuf(const DBuf&) = delete;
+    DBuf& operator=(const DBuf&) = delete;
+    DBuf(DBuf&& o) noexcept : p(o.p), n(o.n), s(o.s), own(o.own) { o.p = nullptr; o.n = 0; o.own = true; }
+    DBuf& operator=(DBuf&& o) noexcept {
+        if (this != &o) {
+            release();
+            p = o.p; n = o.n; s = o.s; own = o.own;
+            o.p = nullptr; o.n = 0; o.own = true;
+        }
+        return *this;
+    }
+};
+
+// ------------------------------------------------------------ the handle
+
+// One quadtree level above the leaves: n nodes, child[4*i + q] is the index
+// of child q = 2*m + n of node i in the next level, or -1 for NIL.
+// key[i] is the node's Morton index at this level (row bits interleaved above
+// column bits, so q is the lowest two bits of the child's key).
+struct TreeLevel {
+    int32_t n = 0;
+    DBuf<int32_t> child;
+    DBuf<uint64_t> key;
+};
+
+// Leaves (the lowest level): n leaves; for leaf i the stored blocks are
+// base[i] .. base[i] + popcount(mask_mo[i]) - 1 in Morton order.
+//   mask_mo: bit q set iff the block at local Morton index q is present
+//   mask_rm: bit (r*lb + c) set iff local block (r, c) is present (row-major)
+//   mask_cm: bit (c*lb + r) set iff local block (r, c) is present (column-major)
+struct LeafLevel {
+    int32_t n = 0;
+    DBuf<int32_t> base;
+    DBuf<uint64_t> mask_mo, mask_rm, mask_cm;
+    DBuf<uint64_t> key;
+};
+
+// Host copies of per-level node counts by row and by column, used to count
+// multiply pairs exactly before any device work: the pairs at level l of
+// A*B are sum_k colcnt_A[l][k] * rowcnt_B[l][k] (every pair of present nodes
+// A(i,k), B(k,j) is reached, since all their ancestors are present).
+struct Histograms {
+    bool ready = false;
+    std::vector<std::vector<int32_t>> rowcnt, colcnt;   // levels 0..L (leaf level)
+    std::vector<int32_t> blk_row, blk_col;              // block level
+};
+
+}  // namespace qt
+
+struct qt_matrix {
+    int64_t n_rows = 0, n_cols = 0;
+    int32_t b = 0, leaf = 0, lb = 0, lb_log = 0;
+    int32_t L = 0;            // leaf level index (root = 0); padded side = leaf * 2^L
+    qt_prec vtype = QT_F64;   // stored value type (QT_F64 or QT_F32)
+    int64_t nblocks = 0;
+    int device = 0;
+    hipStream_t stream = nullptr;
+
+    qt::DBuf<uint64_t> bkey;  // Morton key of each block, ascending
+    qt::DBuf<int32_t> bI, bJ; // block coordinates in Morton order
+    qt::DBuf<double> v64;     // values (fp64), Morton order, when vtype == QT_F64
+    qt::DBuf<float> v32;      // values (fp32), when vtype == QT_F32 or prepared
+
+    std::vector<qt::TreeLevel> levels;   // levels 0 .. L-1
+    qt::LeafLevel leaves;                // level L
+    qt::DBuf<char> arena;                // owns the tree arrays of a multiply result;
+                                         // for such a matrix the DBufs below view into it
+
+    // derived operand forms (built on demand, guarded by mu)
+    std::mutex mu;
+    qt::DBuf<uint16_t> bf_hi, bf_lo;     // bf16 split, row-major per block
+    qt::DBuf<uint16_t> bf_hi_t, bf_lo_t; // same, each block transposed
+    qt::DBuf<double> v64_cache;          // fp64 copy when vtype == QT_F32
+    qt::Histograms hist;
+
+    // counters of the multiply that produced this matrix
+    std::vector<int64_t> pairs;
+    int64_t products = 0;
+};
+
+namespace qt {
+
+// scan.hip -----------------------------------------------------------------
+// Exclusive prefix sum of n int32 counts into out[0..n], out[n] = total.
+// tmp must come from scan_tmp_elems(n).
+size_t scan_tmp_elems(int64_t n);
+void exclusive_scan(const int32_t* in, int32_t* out, int64_t n, int32_t* tmp, hipStream_t s);
+void exclusive_scan(const int64_t* in, int64_t* out, int64_t n, int64_t* tmp, hipStream_t s);
+
+// Sub-allocation of one device allocation: offsets are planned on the host
+// (256-byte aligned) before the single allocation is made.
+struct ArenaPlan {
+    size_t bytes = 0;
+    size_t take(size_t n) {
+        size_t off = bytes;
+        bytes += (n + 255) & ~size_t(255);
+        return off;
+    }
+};
+
+// sort.hip -----------------------------------------------------------------
+// Sort n (key, value) pairs by key, ascending (keys assumed distinct for a
+// unique order; equal keys are kept adjacent). Buffers of length npow2 >= n.
+void bitonic_sort(uint64_t* keys, int32_t* vals, int64_t n, hipStream_t s);
+
+// build.hip ----------------------------------------------------------------
+void build_histograms(qt_matrix* M, hipStream_t s);   // fills M->hist (synchronizes)
+const double* operand_f64(qt_matrix* M, hipStream_t s);
+const float* operand_f32(qt_matrix* M, hipStream_t s);
+void operand_bf16(qt_matrix* M, hipStream_t s);
+uint64_t morton2(uint32_t r, uint32_t c);
+
+// numeric.hip --------------------------------------------------------------
+struct NumericArgs {
+    int b;
+    qt_prec prec;
+    const void* A;            // fp64 or fp32 blocks of A
+    const void* B;
+    const uint16_t* Ahi; const uint16_t* Alo;    // bf16 split of A (row-major blocks)
+    const uint16_t* Bhi_t; const uint16_t* Blo_t; // bf16 split of B (transposed blocks)
+    const int32_t* prodA;     // per product: block index into A
+    const int32_t* prodB;     // per product: block index into B
+    const int32_t* seg;       // nseg + 1 offsets into the product lists
+    int32_t nseg;
+    void* C;                  // fp64 or fp32 C blocks, one per segment
+};
+void launch_numeric(const NumericArgs& a, hipStream_t s);
+
+// profiling ----------------------------------------------------------------
+bool profiling_on();
+struct PhaseEvents { hipEvent_t e0, e1, e2; int64_t products, cblocks; };
+void profile_push(const PhaseEvents& ev);
+
+}  // namespace qt

@@ -1,0 +1,746 @@
+// C = A*B: symbolic traversal of both quadtrees, then the numeric kernel.
+//
+// Algorithm 1 of the paper recurses from the roots: a pair of present nodes
+// (A_mk, B_kn) spawns the eight child pairs (A_m'k', B_k'n'), pairs with a
+// NIL operand are dropped, and at the leaves the block-sparse leaf multiply
+// runs; Algorithm 2 then sums the products landing on the same C node.
+//
+// On the GPU the recursion runs breadth-first, one level per step, with the
+// frontier of pairs grouped by the C node they contribute to and, inside a
+// group, in ascending inner index k. One wavefront owns one C node:
+//   count: it counts, for each of the four child quadrants (m, n), the child
+//          pairs present(A_m0) & present(B_0n) + present(A_m1) & present(B_1n)
+//          over its pairs, giving (child pairs, child C nodes) packed in an
+//          int64;
+//   scan:  one exclusive scan of those packed counts gives every C node the
+//          place of its child pairs and child C nodes in the next level;
+//   fill:  it writes its child pairs, quadrant by quadrant, pairs in order and
+//          k' = 0 before k' = 1 (child k = 2k + k'), so the new frontier is
+//          again grouped by C node with k ascending; quadrants without pairs
+//          are NIL children and get no node.
+// The small top levels run in one workgroup (one launch for all of them); the
+// remaining levels take three launches each.
+//
+// The leaf step gives a C leaf one wavefront whose lanes are the lb x lb
+// blocks of the leaf: lane (i, j) counts popcount(rowmask_A(i) & colmask_B(j))
+// over the leaf pairs of the C leaf, then lists its products, pair by pair,
+// k ascending. The result is the product list of every C block with C blocks
+// in Morton order -- which is also C's block order, so no sort is needed, and
+// since the order of products inside a C block does not depend on the leaf
+// size, neither does the result.
+//
+// The number of pairs at every level and the number of block products are
+// known on the host before any launch (from per-level row/column counts of
+// both operands), so all buffers are sized up front in two allocations (the
+// result's tree, and scratch); the single synchronization reads back how many
+// C blocks there are before C's values are allocated.
+#include "qt_internal.h"
+#include "qt_morton.h"
+
+#include <algorithm>
+#include <map>
+
+namespace qt {
+
+// ------------------------------------------------------------- helpers
+
+__device__ __forceinline__ int64_t pack2(int32_t lo, int32_t hi) {
+    return (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+}
+__device__ __forceinline__ int32_t lo32(int64_t v) { return (int32_t)(uint32_t)((uint64_t)v & 0xffffffffu); }
+__device__ __forceinline__ int32_t hi32(int64_t v) { return (int32_t)((uint64_t)v >> 32); }
+
+__device__ __forceinline__ uint64_t lanes_below(int lane) { return lane ? (~0ull >> (64 - lane)) : 0ull; }
+
+__device__ __forceinline__ int wave_sum(int x) {
+#pragma unroll
+    for (int d = 32; d > 0; d >>= 1) x += __shfl_xor(x, d, 64);
+    return x;
+}
+
+__device__ __forceinline__ uint64_t wave_or(uint64_t x) {
+#pragma unroll
+    for (int d = 32; d > 0; d >>= 1) x |= __shfl_xor(x, d, 64);
+    return x;
+}
+
+__device__ __forceinline__ int wave_excl_scan(int x, int lane) {
+    int v = x;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        int y = __shfl_up(v, d, 64);
+        if (lane >= d) v += y;
+    }
+    return v - x;
+}
+
+__device__ __forceinline__ int4 load_children(const int32_t* tab, int32_t node) {
+    return *reinterpret_cast<const int4*>(tab + 4 * (int64_t)node);
+}
+
+// bits k of row r of an lb x lb occupancy mask stored row-major
+__device__ __forceinline__ uint32_t mask_row(uint64_t m, int r, int lb) {
+    return (uint32_t)((m >> (r * lb)) & ((1ull << lb) - 1));
+}
+
+// ------------------------------------------------- one level of the tree
+
+struct TreeStep {
+    // this level
+    const int32_t* fa;        // A node of each pair
+    const int32_t* fb;        // B node of each pair
+    const int32_t* cseg;      // pairs of C node c: cseg[c] .. cseg[c+1]-1
+    const uint64_t* ckey;     // Morton key of C node c
+    const int32_t* ncount;    // number of C nodes (device)
+    const int32_t* Ach;       // child tables of A and B at this level
+    const int32_t* Bch;
+    int64_t* cnt;             // per C node: (child pairs, child C nodes)
+    int4* tot4;               // per C node: child pairs per quadrant
+    int64_t* off;             // exclusive scan of cnt; off[ncap] = totals
+    int32_t ncap;             // bound on C nodes (= pairs at this level)
+    // next level
+    int32_t* nfa;
+    int32_t* nfb;
+    int32_t* ncseg;
+    uint64_t* nckey;
+    int32_t* cchild;          // C's child table at this level (4 per node)
+    int32_t* ncount_next;
+    int32_t np_next;          // pairs at the next level (known exactly)
+    int32_t* check;           // device total of child pairs, for the host check
+};
+
+__device__ void tree_count_node(const TreeStep& st, int32_t c, int lane) {
+    if (c >= *st.ncount) {
+        if (lane == 0) st.cnt[c] = 0;
+        return;
+    }
+    const int32_t s0 = st.cseg[c], len = st.cseg[c + 1] - s0;
+    int t0 = 0, t1 = 0, t2 = 0, t3 = 0;
+    for (int32_t base = 0; base < len; base += 64) {
+        if (base + lane < len) {
+            const int32_t p = s0 + base + lane;
+            const int4 a = load_children(st.Ach, st.fa[p]);   // A child (m, k) at 2m + k
+            const int4 b = load_children(st.Bch, st.fb[p]);   // B child (k, n) at 2k + n
+            t0 += (a.x >= 0 && b.x >= 0) + (a.y >= 0 && b.z >= 0);
+            t1 += (a.x >= 0 && b.y >= 0) + (a.y >= 0 && b.w >= 0);
+            t2 += (a.z >= 0 && b.x >= 0) + (a.w >= 0 && b.z >= 0);
+            t3 += (a.z >= 0 && b.y >= 0) + (a.w >= 0 && b.w >= 0);
+        }
+    }
+    t0 = wave_sum(t0);
+    t1 = wave_sum(t1);
+    t2 = wave_sum(t2);
+    t3 = wave_sum(t3);
+    if (lane == 0) {
+        st.cnt[c] = pack2(t0 + t1 + t2 + t3, (t0 > 0) + (t1 > 0) + (t2 > 0) + (t3 > 0));
+        st.tot4[c] = make_int4(t0, t1, t2, t3);
+    }
+}
+
+__device__ void tree_fill_node(const TreeStep& st, int32_t c, int lane) {
+    if (c == 0 && lane == 0) {
+        const int64_t T = st.off[st.ncap];
+        const int32_t nc_next = hi32(T);
+        *st.ncount_next = nc_next;
+        if (nc_next <= st.np_next) st.ncseg[nc_next] = st.np_next;
+        *st.check = lo32(T);
+    }
+    if (c >= *st.ncount) return;
+    const int64_t o = st.off[c];
+    const int4 t4 = st.tot4[c];
+    const int t[4] = {t4.x, t4.y, t4.z, t4.w};
+    int run[4], cid[4];
+    int pr = lo32(o), ci = hi32(o);
+#pragma unroll
+    for (int mn = 0; mn < 4; ++mn) {
+        run[mn] = pr;
+        pr += t[mn];
+        cid[mn] = t[mn] > 0 ? ci++ : -1;
+    }
+    if (lane < 4) {
+        int my_c = -1, my_run = 0;
+#pragma unroll
+        for (int mn = 0; mn < 4; ++mn)
+            if (mn == lane) {
+                my_c = cid[mn];
+                my_run = run[mn];
+            }
+        st.cchild[4 * (int64_t)c + lane] = my_c;
+        if (my_c >= 0 && my_c < st.np_next) {
+            st.nckey[my_c] = st.ckey[c] * 4 + (uint64_t)lane;
+            st.ncseg[my_c] = my_run;
+        }
+    }
+    const int32_t s0 = st.cseg[c], len = st.cseg[c + 1] - s0;
+    const uint64_t below = lanes_below(lane);
+    for (int32_t base = 0; base < len; base += 64) {
+        const bool act = base + lane < len;
+        int4 a = make_int4(-1, -1, -1, -1), b = make_int4(-1, -1, -1, -1);
+        if (act) {
+            const int32_t p = s0 + base + lane;
+            a = load_children(st.Ach, st.fa[p]);
+            b = load_children(st.Bch, st.fb[p]);
+        }
+        const int av[4] = {a.x, a.y, a.z, a.w};
+        const int bv[4] = {b.x, b.y, b.z, b.w};
+#pragma unroll
+        for (int mn = 0; mn < 4; ++mn) {
+            const int m = mn >> 1, n = mn & 1;
+            const bool e0 = av[2 * m] >= 0 && bv[n] >= 0;           // k' = 0
+            const bool e1 = av[2 * m + 1] >= 0 && bv[2 + n] >= 0;   // k' = 1
+            const uint64_t m0 = __ballot(e0), m1 = __ballot(e1);
+            int out = run[mn] + __popcll(m0 & below) + __popcll(m1 & below);
+            if (e0) {
+                if (out < st.np_next) {
+                    st.nfa[out] = av[2 * m];
+                    st.nfb[out] = bv[n];
+                }
+                ++out;
+            }
+            if (e1 && out < st.np_next) {
+                st.nfa[out] = av[2 * m + 1];
+                st.nfb[out] = bv[2 + n];
+            }
+            run[mn] += __popcll(m0) + __popcll(m1);
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void k_tree_count(TreeStep st) {
+    const int32_t c = (int32_t)((blockIdx.x * 256u + threadIdx.x) >> 6);
+    if (c < st.ncap) tree_count_node(st, c, threadIdx.x & 63);
+}
+
+__global__ __launch_bounds__(256) void k_tree_fill(TreeStep st) {
+    const int32_t c = (int32_t)((blockIdx.x * 256u + threadIdx.x) >> 6);
+    if (c < st.ncap) tree_fill_node(st, c, threadIdx.x & 63);
+}
+
+// Level-0 frontier: the pair of roots, one C node.
+struct RootInit {
+    int32_t* fa;
+    int32_t* fb;
+    int32_t* cseg;
+    uint64_t* ckey;
+    int32_t* ncount;
+};
+
+__device__ void root_init(const RootInit& r) {
+    r.fa[0] = 0;
+    r.fb[0] = 0;
+    r.cseg[0] = 0;
+    r.cseg[1] = 1;
+    r.ckey[0] = 0;
+    r.ncount[0] = 1;
+}
+
+__global__ void k_root_init(RootInit r) { root_init(r); }
+
+// The top levels in one workgroup: count, workgroup scan, fill, per level.
+constexpr int TOP_THREADS = 1024;
+constexpr int TOP_MAX_LEVELS = 12;
+constexpr int32_t TOP_MAX_PAIRS = 512;
+
+struct TopArgs {
+    RootInit root;
+    int32_t nlev;
+    TreeStep step[TOP_MAX_LEVELS];
+};
+
+__device__ __forceinline__ void wg_sync() {
+    __threadfence();
+    __syncthreads();
+    __threadfence();
+}
+
+__device__ void wg_scan_i64(const int64_t* in, int64_t* out, int32_t n, int64_t* lds_waves) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    int64_t carry = 0;
+    for (int32_t base = 0; base <= n; base += TOP_THREADS) {
+        const int32_t i = base + threadIdx.x;
+        const int64_t v = (i < n) ? in[i] : 0;
+        int64_t x = v;
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            int64_t y = __shfl_up(x, d, 64);
+            if (lane >= d) x += y;
+        }
+        if (lane == 63) lds_waves[wave] = x;
+        __syncthreads();
+        int64_t before = 0, all = 0;
+        for (int w = 0; w < TOP_THREADS / 64; ++w) {
+            const int64_t t = lds_waves[w];
+            if (w < wave) before += t;
+            all += t;
+        }
+        if (i <= n) out[i] = carry + before + x - v;
+        carry += all;
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(TOP_THREADS) void k_tree_top(TopArgs args) {
+    __shared__ int64_t lds_waves[TOP_THREADS / 64];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (threadIdx.x == 0) root_init(args.root);
+    wg_sync();
+    for (int l = 0; l < args.nlev; ++l) {
+        const TreeStep& st = args.step[l];
+        for (int32_t c = wave; c < st.ncap; c += TOP_THREADS / 64) tree_count_node(st, c, lane);
+        wg_sync();
+        wg_scan_i64(st.cnt, st.off, st.ncap, lds_waves);
+        wg_sync();
+        for (int32_t c = wave; c < st.ncap; c += TOP_THREADS / 64) tree_fill_node(st, c, lane);
+        wg_sync();
+    }
+}
+
+// ------------------------------------------------------ the leaf step
+
+struct LeafStep {
+    const int32_t* fa;        // A leaf of each leaf pair
+    const int32_t* fb;        // B leaf of each leaf pair
+    const int32_t* cseg;
+    const uint64_t* ckey;
+    const int32_t* ncount;
+    int32_t ncap;
+    int lb_log;
+    const uint64_t* Arm;      // A leaves: row-major masks
+    const uint64_t* Bcm;      // B leaves: column-major masks
+    const uint64_t* Amo;      // Morton-order masks (rank of a block in its leaf)
+    const uint64_t* Bmo;
+    const int32_t* Abase;
+    const int32_t* Bbase;
+    int64_t* cnt;             // per C leaf: (products, C blocks)
+    int64_t* off;
+    int32_t* prodA;
+    int32_t* prodB;
+    int32_t P;
+    uint64_t* cbkey;          // C block keys, Morton order
+    int32_t* cbseg;           // first product of each C block
+    int32_t cap;              // bound on C blocks
+    int32_t* lbase;           // C leaves: first block, masks
+    uint64_t* lmo;
+    uint64_t* lrm;
+    uint64_t* lcm;
+    int32_t* nblocks_out;
+    int32_t* check;
+};
+
+// Lane q (a block of the C leaf, local Morton index) counts its products.
+__device__ int leaf_lane_count(const LeafStep& st, int32_t s0, int32_t len, int lane, int i, int j, int lb,
+                               bool on) {
+    int cnt = 0;
+    for (int32_t base = 0; base < len; base += 64) {
+        const int32_t nb = min(64, len - base);
+        uint64_t ra = 0, cb = 0;
+        if (lane < nb) {
+            ra = st.Arm[st.fa[s0 + base + lane]];
+            cb = st.Bcm[st.fb[s0 + base + lane]];
+        }
+        for (int t = 0; t < nb; ++t) {
+            const uint64_t rat = __shfl(ra, t, 64);
+            const uint64_t cbt = __shfl(cb, t, 64);
+            if (on) cnt += __popc(mask_row(rat, i, lb) & mask_row(cbt, j, lb));
+        }
+    }
+    return cnt;
+}
+
+__device__ void leaf_count_node(const LeafStep& st, int32_t c, int lane) {
+    if (c >= *st.ncount) {
+        if (lane == 0) st.cnt[c] = 0;
+        return;
+    }
+    const int lb = 1 << st.lb_log;
+    const bool on = lane < lb * lb;
+    const int i = (int)morton_row((uint64_t)lane), j = (int)morton_col((uint64_t)lane);
+    const int32_t s0 = st.cseg[c], len = st.cseg[c + 1] - s0;
+    const int cnt = leaf_lane_count(st, s0, len, lane, i, j, lb, on);
+    const uint64_t em = __ballot(cnt > 0);
+    const int tot = wave_sum(cnt);
+    if (lane == 0) st.cnt[c] = pack2(tot, __popcll(em));
+}
+
+__device__ void leaf_fill_node(const LeafStep& st, int32_t c, int lane) {
+    if (c == 0 && lane == 0) {
+        const int64_t T = st.off[st.ncap];
+        const int32_t nb = hi32(T);
+        *st.nblocks_out = nb;
+        if (nb <= st.cap) st.cbseg[nb] = lo32(T);
+        *st.check = lo32(T);
+    }
+    if (c >= *st.ncount) return;
+    const int lb = 1 << st.lb_log;
+    const bool on = lane < lb * lb;
+    const int i = (int)morton_row((uint64_t)lane), j = (int)morton_col((uint64_t)lane);
+    const int32_t s0 = st.cseg[c], len = st.cseg[c + 1] - s0;
+    const int cnt = leaf_lane_count(st, s0, len, lane, i, j, lb, on);
+    const int64_t o = st.off[c];
+    const bool exists = cnt > 0;
+    const uint64_t em = __ballot(exists);
+    const int32_t bidx = hi32(o) + __popcll(em & lanes_below(lane));
+    int32_t out = lo32(o) + wave_excl_scan(cnt, lane);
+    if (exists && bidx < st.cap) {
+        st.cbkey[bidx] = (st.ckey[c] << (2 * st.lb_log)) | (uint64_t)lane;
+        st.cbseg[bidx] = out;
+    }
+    for (int32_t base = 0; base < len; base += 64) {
+        const int32_t nb = min(64, len - base);
+        uint64_t ra = 0, cb = 0, amo = 0, bmo = 0;
+        int32_t ab = 0, bb = 0;
+        if (lane < nb) {
+            const int32_t a = st.fa[s0 + base + lane], b = st.fb[s0 + base + lane];
+            ra = st.Arm[a];
+            cb = st.Bcm[b];
+            amo = st.Amo[a];
+            bmo = st.Bmo[b];
+            ab = st.Abase[a];
+            bb = st.Bbase[b];
+        }
+        for (int t = 0; t < nb; ++t) {
+            const uint64_t rat = __shfl(ra, t, 64);
+            const uint64_t cbt = __shfl(cb, t, 64);
+            const uint64_t amot = __shfl(amo, t, 64);
+            const uint64_t bmot = __shfl(bmo, t, 64);
+            const int32_t abt = __shfl(ab, t, 64);
+            const int32_t bbt = __shfl(bb, t, 64);
+            uint32_t m = on ? (mask_row(rat, i, lb) & mask_row(cbt, j, lb)) : 0u;
+            while (m) {
+                const int k = __ffs(m) - 1;
+                m &= m - 1;
+                const uint32_t qa = (uint32_t)morton_key((uint32_t)i, (uint32_t)k);
+                const uint32_t qb = (uint32_t)morton_key((uint32_t)k, (uint32_t)j);
+                if (out < st.P) {
+                    st.prodA[out] = abt + __popcll(amot & ((1ull << qa) - 1));
+                    st.prodB[out] = bbt + __popcll(bmot & ((1ull << qb) - 1));
+                }
+                ++out;
+            }
+        }
+    }
+    const uint64_t rm = wave_or(exists ? (1ull << (i * lb + j)) : 0ull);
+    const uint64_t cm = wave_or(exists ? (1ull << (j * lb + i)) : 0ull);
+    if (lane == 0) {
+        st.lbase[c] = hi32(o);
+        st.lmo[c] = em;
+        st.lrm[c] = rm;
+        st.lcm[c] = cm;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_leaf_count(LeafStep st) {
+    const int32_t c = (int32_t)((blockIdx.x * 256u + threadIdx.x) >> 6);
+    if (c < st.ncap) leaf_count_node(st, c, threadIdx.x & 63);
+}
+
+__global__ __launch_bounds__(256) void k_leaf_fill(LeafStep st) {
+    const int32_t c = (int32_t)((blockIdx.x * 256u + threadIdx.x) >> 6);
+    if (c < st.ncap) leaf_fill_node(st, c, threadIdx.x & 63);
+}
+
+// ----------------------------------------------------------- host side
+
+static inline unsigned waves_grid(int64_t nwaves) {
+    return (unsigned)std::max<int64_t>((nwaves + 3) / 4, 1);
+}
+
+// A device-resident child table {0, -1, -1, -1}: the single node of a level
+// added above a shallower operand so both trees have the same depth (the
+// shallower matrix sits in the top-left quadrant at every added level).
+static std::mutex g_lift_mu;
+static std::map<int, int32_t*> g_lift;
+
+static const int32_t* lift_table() {
+    int dev = 0;
+    QT_HIP(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lk(g_lift_mu);
+    auto it = g_lift.find(dev);
+    if (it != g_lift.end()) return it->second;
+    int32_t* p = nullptr;
+    QT_HIP(hipMalloc(&p, 4 * sizeof(int32_t)));
+    const int32_t h[4] = {0, -1, -1, -1};
+    QT_HIP(hipMemcpy(p, h, sizeof(h), hipMemcpyHostToDevice));
+    g_lift[dev] = p;
+    return p;
+}
+
+static const std::vector<int32_t>& unit_hist() {
+    static const std::vector<int32_t> one(1, 1);
+    return one;
+}
+
+static int64_t dot_counts(const std::vector<int32_t>& a, const std::vector<int32_t>& b) {
+    const size_t n = std::min(a.size(), b.size());
+    int64_t s = 0;
+    for (size_t k = 0; k < n; ++k) s += (int64_t)a[k] * b[k];
+    return s;
+}
+
+static const int64_t kMaxI32 = (int64_t(1) << 31) - 2;
+
+static qt_matrix* new_result(const qt_matrix* A, const qt_matrix* B, int L, qt_prec prec, hipStream_t s) {
+    std::unique_ptr<qt_matrix> C(new qt_matrix);
+    C->n_rows = A->n_rows;
+    C->n_cols = B->n_cols;
+    C->b = A->b;
+    C->leaf = A->leaf;
+    C->lb = A->lb;
+    C->lb_log = A->lb_log;
+    C->L = L;
+    C->vtype = (prec == QT_F32) ? QT_F32 : QT_F64;
+    C->nblocks = 0;
+    C->stream = s;
+    QT_HIP(hipGetDevice(&C->device));
+    C->levels.resize(L);
+    return C.release();
+}
+
+static qt_matrix* empty_result(const qt_matrix* A, const qt_matrix* B, int L, qt_prec prec, hipStream_t s) {
+    qt_matrix* C = new_result(A, B, L, prec, s);
+    C->pairs.assign(L + 1, 0);
+    C->hist.ready = true;
+    C->hist.rowcnt.resize(L + 1);
+    C->hist.colcnt.resize(L + 1);
+    for (int l = 0; l <= L; ++l) {
+        C->hist.rowcnt[l].assign(size_t(1) << l, 0);
+        C->hist.colcnt[l].assign(size_t(1) << l, 0);
+    }
+    C->hist.blk_row.assign((size_t)C->lb << L, 0);
+    C->hist.blk_col.assign((size_t)C->lb << L, 0);
+    return C;
+}
+
+qt_matrix* multiply(qt_matrix* A, qt_matrix* B, qt_prec prec, hipStream_t s) {
+    if (prec != QT_F64 && prec != QT_F32 && prec != QT_BF16X3) fail(QT_ERR_ARG, "unknown precision");
+    if (A->b != B->b || A->leaf != B->leaf) fail(QT_ERR_SHAPE, "operands differ in block or leaf size");
+    if (A->n_cols != B->n_rows) fail(QT_ERR_SHAPE, "inner dimensions differ");
+    if (prec == QT_BF16X3 && A->b == 16) fail(QT_ERR_UNSUPPORTED, "split-bf16 path needs b = 32 or 64");
+    const int L = std::max(A->L, B->L);
+    const int liftA = L - A->L, liftB = L - B->L;
+    if (A->nblocks == 0 || B->nblocks == 0) return empty_result(A, B, L, prec, s);
+
+    build_histograms(A, s);
+    build_histograms(B, s);
+
+    // exact pair counts per level and block products
+    std::vector<int64_t> pairs(L + 1);
+    for (int l = 0; l <= L; ++l) {
+        const auto& ca = (l < liftA) ? unit_hist() : A->hist.colcnt[l - liftA];
+        const auto& rb = (l < liftB) ? unit_hist() : B->hist.rowcnt[l - liftB];
+        pairs[l] = dot_counts(ca, rb);
+    }
+    const int64_t P = dot_counts(A->hist.blk_col, B->hist.blk_row);
+    const int lb_log = A->lb_log;
+    const int64_t lb2 = int64_t(1) << (2 * lb_log);
+    for (int l = 0; l <= L; ++l)
+        if (4 * pairs[l] > kMaxI32) fail(QT_ERR_UNSUPPORTED, "too many node pairs at one level");
+    if (P > kMaxI32) fail(QT_ERR_UNSUPPORTED, "too many block products");
+    if (P == 0) {
+        qt_matrix* C = empty_result(A, B, L, prec, s);
+        C->pairs = pairs;
+        return C;
+    }
+
+    // operand forms for this precision
+    NumericArgs na{};
+    na.b = A->b;
+    na.prec = prec;
+    if (prec == QT_F64) {
+        na.A = operand_f64(A, s);
+        na.B = operand_f64(B, s);
+    } else if (prec == QT_F32) {
+        na.A = operand_f32(A, s);
+        na.B = operand_f32(B, s);
+    } else {
+        operand_bf16(A, s);
+        operand_bf16(B, s);
+        na.Ahi = A->bf_hi.p;
+        na.Alo = A->bf_lo.p;
+        na.Bhi_t = B->bf_hi_t.p;
+        na.Blo_t = B->bf_lo_t.p;
+    }
+
+    // ---- plan the two allocations
+    const int64_t cap = std::min<int64_t>(P, lb2 * pairs[L]);   // bound on C blocks
+    ArenaPlan keep, tmp;   // keep: C's tree; tmp: scratch freed after the call
+    std::vector<size_t> o_child(L), o_key(L + 1);
+    for (int l = 0; l < L; ++l) o_child[l] = keep.take(4 * pairs[l] * sizeof(int32_t));
+    for (int l = 0; l <= L; ++l) o_key[l] = keep.take(pairs[l] * sizeof(uint64_t));
+    const size_t o_lbase = keep.take(pairs[L] * sizeof(int32_t));
+    const size_t o_lmo = keep.take(pairs[L] * sizeof(uint64_t));
+    const size_t o_lrm = keep.take(pairs[L] * sizeof(uint64_t));
+    const size_t o_lcm = keep.take(pairs[L] * sizeof(uint64_t));
+    const size_t o_bkey = keep.take(cap * sizeof(uint64_t));
+    std::vector<size_t> o_fa(L + 1), o_fb(L + 1), o_cseg(L + 1), o_cnt(L + 1), o_off(L + 1), o_tot(L + 1);
+    size_t scan_elems = 0;
+    for (int l = 0; l <= L; ++l) {
+        o_fa[l] = tmp.take(pairs[l] * sizeof(int32_t));
+        o_fb[l] = tmp.take(pairs[l] * sizeof(int32_t));
+        o_cseg[l] = tmp.take((pairs[l] + 1) * sizeof(int32_t));
+        o_cnt[l] = tmp.take(pairs[l] * sizeof(int64_t));
+        o_off[l] = tmp.take((pairs[l] + 1) * sizeof(int64_t));
+        o_tot[l] = tmp.take(pairs[l] * sizeof(int4));
+        scan_elems = std::max(scan_elems, scan_tmp_elems(pairs[l]));
+    }
+    const size_t o_scan = tmp.take((scan_elems + 1) * sizeof(int64_t));
+    const size_t o_prodA = tmp.take(P * sizeof(int32_t));
+    const size_t o_prodB = tmp.take(P * sizeof(int32_t));
+    const size_t o_cbseg = tmp.take((cap + 1) * sizeof(int32_t));
+    const size_t o_count = tmp.take((2 * L + 4) * sizeof(int32_t));
+
+    std::unique_ptr<qt_matrix> C(new_result(A, B, L, prec, s));
+    C->pairs = pairs;
+    C->products = P;
+    C->arena.alloc(keep.bytes, s);
+    DBuf<char> scratch(tmp.bytes, s);
+    char* K = C->arena.p;
+    char* W = scratch.p;
+    auto at = [](char* base, size_t off) { return (void*)(base + off); };
+    int32_t* dcount = (int32_t*)at(W, o_count);   // [0..L] C nodes per level, [L+1] C blocks, then checks
+
+    const bool prof = profiling_on();
+    PhaseEvents ev{};
+    if (prof) {
+        QT_HIP(hipEventCreate(&ev.e0));
+        QT_HIP(hipEventCreate(&ev.e1));
+        QT_HIP(hipEventCreate(&ev.e2));
+        QT_HIP(hipEventRecord(ev.e0, s));
+    }
+
+    const int32_t* lift = (liftA > 0 || liftB > 0) ? lift_table() : nullptr;
+    auto tree_step = [&](int l) {
+        TreeStep st{};
+        st.fa = (const int32_t*)at(W, o_fa[l]);
+        st.fb = (const int32_t*)at(W, o_fb[l]);
+        st.cseg = (const int32_t*)at(W, o_cseg[l]);
+        st.ckey = (const uint64_t*)at(K, o_key[l]);
+        st.ncount = dcount + l;
+        st.Ach = (l < liftA) ? lift : A->levels[l - liftA].child.p;
+        st.Bch = (l < liftB) ? lift : B->levels[l - liftB].child.p;
+        st.cnt = (int64_t*)at(W, o_cnt[l]);
+        st.tot4 = (int4*)at(W, o_tot[l]);
+        st.off = (int64_t*)at(W, o_off[l]);
+        st.ncap = (int32_t)pairs[l];
+        st.nfa = (int32_t*)at(W, o_fa[l + 1]);
+        st.nfb = (int32_t*)at(W, o_fb[l + 1]);
+        st.ncseg = (int32_t*)at(W, o_cseg[l + 1]);
+        st.nckey = (uint64_t*)at(K, o_key[l + 1]);
+        st.cchild = (int32_t*)at(K, o_child[l]);
+        st.ncount_next = dcount + l + 1;
+        st.np_next = (int32_t)pairs[l + 1];
+        st.check = dcount + L + 2 + l;
+        return st;
+    };
+    RootInit root{(int32_t*)at(W, o_fa[0]), (int32_t*)at(W, o_fb[0]), (int32_t*)at(W, o_cseg[0]),
+                  (uint64_t*)at(K, o_key[0]), dcount};
+
+    // top levels in one workgroup, while the frontier stays small
+    int ltop = 0;
+    while (ltop < L && ltop < TOP_MAX_LEVELS && pairs[ltop] <= TOP_MAX_PAIRS && pairs[ltop + 1] <= TOP_MAX_PAIRS)
+        ++ltop;
+    if (ltop > 0) {
+        TopArgs ta{};
+        ta.root = root;
+        ta.nlev = ltop;
+        for (int l = 0; l < ltop; ++l) ta.step[l] = tree_step(l);
+        k_tree_top<<<1, TOP_THREADS, 0, s>>>(ta);
+        QT_LAUNCH("k_tree_top");
+    } else {
+        k_root_init<<<1, 1, 0, s>>>(root);
+        QT_LAUNCH("k_root_init");
+    }
+    int64_t* scan_tmp = (int64_t*)at(W, o_scan);
+    for (int l = ltop; l < L; ++l) {
+        const TreeStep st = tree_step(l);
+        k_tree_count<<<waves_grid(pairs[l]), 256, 0, s>>>(st);
+        QT_LAUNCH("k_tree_count");
+        exclusive_scan(st.cnt, st.off, pairs[l], scan_tmp, s);
+        k_tree_fill<<<waves_grid(pairs[l]), 256, 0, s>>>(st);
+        QT_LAUNCH("k_tree_fill");
+    }
+
+    // leaf step
+    LeafStep ls{};
+    ls.fa = (const int32_t*)at(W, o_fa[L]);
+    ls.fb = (const int32_t*)at(W, o_fb[L]);
+    ls.cseg = (const int32_t*)at(W, o_cseg[L]);
+    ls.ckey = (const uint64_t*)at(K, o_key[L]);
+    ls.ncount = dcount + L;
+    ls.ncap = (int32_t)pairs[L];
+    ls.lb_log = lb_log;
+    ls.Arm = A->leaves.mask_rm.p;
+    ls.Bcm = B->leaves.mask_cm.p;
+    ls.Amo = A->leaves.mask_mo.p;
+    ls.Bmo = B->leaves.mask_mo.p;
+    ls.Abase = A->leaves.base.p;
+    ls.Bbase = B->leaves.base.p;
+    ls.cnt = (int64_t*)at(W, o_cnt[L]);
+    ls.off = (int64_t*)at(W, o_off[L]);
+    ls.prodA = (int32_t*)at(W, o_prodA);
+    ls.prodB = (int32_t*)at(W, o_prodB);
+    ls.P = (int32_t)P;
+    ls.cbkey = (uint64_t*)at(K, o_bkey);
+    ls.cbseg = (int32_t*)at(W, o_cbseg);
+    ls.cap = (int32_t)cap;
+    ls.lbase = (int32_t*)at(K, o_lbase);
+    ls.lmo = (uint64_t*)at(K, o_lmo);
+    ls.lrm = (uint64_t*)at(K, o_lrm);
+    ls.lcm = (uint64_t*)at(K, o_lcm);
+    ls.nblocks_out = dcount + L + 1;
+    ls.check = dcount + 2 * L + 2;
+    k_leaf_count<<<waves_grid(pairs[L]), 256, 0, s>>>(ls);
+    QT_LAUNCH("k_leaf_count");
+    exclusive_scan(ls.cnt, ls.off, pairs[L], scan_tmp, s);
+    k_leaf_fill<<<waves_grid(pairs[L]), 256, 0, s>>>(ls);
+    QT_LAUNCH("k_leaf_fill");
+    if (prof) QT_HIP(hipEventRecord(ev.e1, s));
+
+    // the one synchronization: node and block counts of C
+    std::vector<int32_t> hc(2 * L + 4);
+    QT_HIP(hipMemcpyAsync(hc.data(), dcount, hc.size() * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    QT_HIP(hipStreamSynchronize(s));
+    for (int l = 0; l <= L; ++l) {
+        const int64_t expect = (l < L) ? pairs[l + 1] : P;
+        if (hc[L + 2 + l] != expect) fail(QT_ERR_DEVICE, "symbolic phase: pair count mismatch");
+    }
+    const int32_t nnzC = hc[L + 1];
+    if (nnzC <= 0 || nnzC > cap) fail(QT_ERR_DEVICE, "symbolic phase: C block count out of range");
+
+    // C's tree: views into its arena
+    for (int l = 0; l < L; ++l) {
+        C->levels[l].n = hc[l];
+        C->levels[l].child.view(at(K, o_child[l]), 4 * (size_t)hc[l]);
+        C->levels[l].key.view(at(K, o_key[l]), hc[l]);
+    }
+    LeafLevel& CL = C->leaves;
+    CL.n = hc[L];
+    CL.key.view(at(K, o_key[L]), hc[L]);
+    CL.base.view(at(K, o_lbase), hc[L]);
+    CL.mask_mo.view(at(K, o_lmo), hc[L]);
+    CL.mask_rm.view(at(K, o_lrm), hc[L]);
+    CL.mask_cm.view(at(K, o_lcm), hc[L]);
+    C->bkey.view(at(K, o_bkey), nnzC);
+    C->nblocks = nnzC;
+
+    const size_t bb = (size_t)C->b * C->b;
+    if (prec == QT_F32)
+        C->v32.alloc(nnzC * bb, s);
+    else
+        C->v64.alloc(nnzC * bb, s);
+    na.prodA = ls.prodA;
+    na.prodB = ls.prodB;
+    na.seg = ls.cbseg;
+    na.nseg = nnzC;
+    na.C = (prec == QT_F32) ? (void*)C->v32.p : (void*)C->v64.p;
+    launch_numeric(na, s);
+    if (prof) {
+        QT_HIP(hipEventRecord(ev.e2, s));
+        ev.products = P;
+        ev.cblocks = nnzC;
+        profile_push(ev);
+    }
+    return C.release();
+}
+
+}  // namespace qt

@@ -1,0 +1,257 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle.
+
+Patterns must match exactly. FP64 values must be within 1e-12 of the oracle
+componentwise, relative to |A||B|, and normwise. The FP32 and split-BF16
+paths are held to a-priori bounds derived from their roundings:
+  fp32:    (k*b + 2) * 2^-24 * (|A||B|)_ij   (k = products in the C block)
+  bf16x3:  (3*2^-16 + (3b + 4) * 2^-24) * (|A||B|)_ij
+"""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as wl
+from tests._util import compare, positions, random_pattern
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-12
+
+
+@pytest.fixture(scope="module")
+def qt():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1501_07800_amd as q
+    return q
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+def gpu_multiply(qt, A, B, leaf, prec="f64", same=False):
+    hA = qt.from_blockmatrix(A, leaf)
+    hB = hA if same else qt.from_blockmatrix(B, leaf)
+    hC = qt.multiply(hA, hB, prec)
+    I, J, V = hC.to_blocks("f64")
+    st = hC.stats()
+    C = wl.BlockMatrix(A.n_rows, B.n_cols, A.b, I, J, V)
+    return C, st, hC
+
+
+def check_f64(qt, A, B, leaf, same=False, check_counts=True):
+    _say("f64", A.n_rows, A.n_cols, B.n_cols, "b", A.b, "leaf", leaf, "nnz", A.nnz, B.nnz)
+    ref, ost = oracle.multiply(A, B, leaf)
+    absAB, _ = oracle.multiply(A, B, leaf, use_abs=True)
+    C, st, _ = gpu_multiply(qt, A, B, leaf, "f64", same)
+    same_pat, e_max, e_f, e_cw = compare(ref, C, absAB)
+    assert same_pat, (ref.nnz, C.nnz)
+    assert e_cw <= TOL64, e_cw
+    assert e_f <= TOL64, e_f
+    assert st["products"] == ost.block_products
+    if check_counts:
+        assert st["pairs"].tolist() == ost.mul_tasks.tolist()
+    return ref, C
+
+
+def test_round_trip_bit_exact(qt):
+    rng = np.random.default_rng(0)
+    for b, leaf, nbr, nbc in ((16, 64, 13, 21), (32, 256, 40, 9), (64, 64, 5, 5)):
+        A = random_pattern(rng, nbr, nbc, 0.3, b)
+        _say("round trip", b, leaf, nbr, nbc)
+        h = qt.from_blockmatrix(A, leaf)
+        I, J, V = h.to_blocks("f64")
+        assert np.array_equal(I, A.I) and np.array_equal(J, A.J) and np.array_equal(V, A.V)
+        I, J, V32 = h.to_blocks("f32")
+        assert np.array_equal(V32, A.V.astype(np.float32))
+        assert h.info()["nblocks"] == A.nnz
+
+
+def test_round_trip_device_arrays(qt):
+    import torch
+    rng = np.random.default_rng(1)
+    A = random_pattern(rng, 30, 30, 0.2, 32)
+    perm = rng.permutation(A.nnz)            # any input order
+    dev = torch.device("cuda")
+    I = torch.from_numpy(A.I[perm].copy()).to(dev)
+    J = torch.from_numpy(A.J[perm].copy()).to(dev)
+    V = torch.from_numpy(A.V[perm].copy()).to(dev)
+    h = qt.build(A.n_rows, A.n_cols, 32, 128, I, J, V)
+    oI = torch.empty_like(I)
+    oJ = torch.empty_like(J)
+    oV = torch.empty_like(V)
+    h.to_blocks_device(oI, oJ, oV)
+    torch.cuda.synchronize()
+    assert np.array_equal(oI.cpu().numpy(), A.I)
+    assert np.array_equal(oJ.cpu().numpy(), A.J)
+    assert np.array_equal(oV.cpu().numpy(), A.V)
+
+
+def test_build_errors(qt):
+    b = 16
+    V = np.ones((2, b, b))
+    with pytest.raises(qt.QtError) as e:
+        qt.build(64, 64, b, 32, np.array([0, 4], np.int32), np.array([0, 0], np.int32), V)
+    assert e.value.status == qt.QT_ERR_ARG
+    with pytest.raises(qt.QtError) as e:
+        qt.build(64, 64, b, 32, np.array([1, 1], np.int32), np.array([2, 2], np.int32), V)
+    assert e.value.status == qt.QT_ERR_DUPLICATE
+    A = qt.build(64, 48, b, 32, np.array([0], np.int32), np.array([0], np.int32), V[:1])
+    B = qt.build(64, 64, b, 32, np.array([0], np.int32), np.array([0], np.int32), V[:1])
+    with pytest.raises(qt.QtError) as e:
+        qt.multiply(A, B)                     # 48 columns vs 64 rows
+    assert e.value.status == qt.QT_ERR_SHAPE
+    C = qt.build(48, 48, b, 16, np.array([0], np.int32), np.array([0], np.int32), V[:1])
+    with pytest.raises(qt.QtError) as e:
+        qt.multiply(A, C)                     # leaf sizes differ
+    assert e.value.status == qt.QT_ERR_SHAPE
+
+
+def test_banded1024_f64(qt):
+    A = wl.config("banded1024")
+    ref, C = check_f64(qt, A, A, 256, same=True)
+    assert C.nnz == 374
+
+
+@pytest.mark.parametrize("b", [16, 32, 64])
+@pytest.mark.parametrize("lb", [1, 2, 8])
+def test_random_shapes_f64(qt, b, lb):
+    rng = np.random.default_rng(10 * b + lb)
+    # rectangular, dimensions not multiples of the leaf (ragged tail)
+    nbr, nbk, nbc = (37, 29, 45) if b < 64 else (19, 13, 23)
+    for fill in (0.03, 0.25):
+        A = random_pattern(rng, nbr, nbk, fill, b)
+        B = random_pattern(rng, nbk, nbc, fill, b)
+        check_f64(qt, A, B, lb * b)
+
+
+def test_depth_mismatch_f64(qt):
+    rng = np.random.default_rng(3)
+    A = random_pattern(rng, 3, 70, 0.5, 32)      # wide: deeper tree than A's row count needs
+    B = random_pattern(rng, 70, 2, 0.5, 32)      # tall: deeper than its column count needs
+    check_f64(qt, A, B, 64)                      # C is 3 x 2 blocks, both operands deeper than C
+    X = random_pattern(rng, 2, 3, 0.8, 32)       # shallow times deep
+    check_f64(qt, X, A, 64)
+    check_f64(qt, B, X, 64)                      # deep times shallow
+
+
+def test_leaf_size_independent_bitwise(qt):
+    rng = np.random.default_rng(4)
+    A = random_pattern(rng, 96, 96, 0.06, 32)
+    outs = []
+    for leaf in (32, 64, 128, 256):
+        C, _, _ = gpu_multiply(qt, A, A, leaf, "f64", same=True)
+        outs.append(C)
+    for C in outs[1:]:
+        assert np.array_equal(positions(C), positions(outs[0]))
+        assert np.array_equal(C.V, outs[0].V)
+
+
+def test_empty_and_degenerate(qt):
+    rng = np.random.default_rng(5)
+    A = random_pattern(rng, 8, 8, 0.3, 32)
+    Z = random_pattern(rng, 8, 8, 0.0, 32)
+    for X, Y in ((A, Z), (Z, A), (Z, Z)):
+        C, st, h = gpu_multiply(qt, X, Y, 64)
+        assert C.nnz == 0 and st["products"] == 0
+    # no shared inner index: every pair of leaves is present but no block product exists
+    A1 = wl.BlockMatrix(8 * 32, 8 * 32, 32, np.array([0], np.int32), np.array([1], np.int32), np.ones((1, 32, 32)))
+    B1 = wl.BlockMatrix(8 * 32, 8 * 32, 32, np.array([0], np.int32), np.array([0], np.int32), np.ones((1, 32, 32)))
+    C, st, _ = gpu_multiply(qt, A1, B1, 256)
+    assert C.nnz == 0
+    # a single block
+    one = random_pattern(rng, 1, 1, 1.0, 64)
+    check_f64(qt, one, one, 64)
+
+
+def test_chained_product_f64(qt):
+    """C = A*A, then D = C*A, with C used as an operand (its own tree)."""
+    rng = np.random.default_rng(6)
+    A = random_pattern(rng, 40, 40, 0.05, 32)
+    ref_C, _ = oracle.multiply(A, A, 128)
+    ref_D, _ = oracle.multiply(ref_C, A, 128)
+    absC, _ = oracle.multiply(A, A, 128, use_abs=True)
+    absD, _ = oracle.multiply(absC, A, 128, use_abs=True)
+    hA = qt.from_blockmatrix(A, 128)
+    hC = qt.multiply(hA, hA)
+    hD = qt.multiply(hC, hA)
+    I, J, V = hD.to_blocks()
+    D = wl.BlockMatrix(A.n_rows, A.n_cols, 32, I, J, V)
+    same, _, e_f, e_cw = compare(ref_D, D, absD)
+    assert same and e_cw <= TOL64
+
+
+def test_decay_small_f64(qt):
+    A = wl.decay3d(1024, 25.0, 16, 32, seed=7)
+    check_f64(qt, A, A, 256, same=True)
+
+
+def test_random_small_f64(qt):
+    A = wl.random_blocks(512, 512, int(0.02 * 512 * 512), 32, seed=8)
+    check_f64(qt, A, A, 128, same=True)
+
+
+def _bound_check(C, ref, absAB, rel):
+    same, e_max, e_f, e_cw = compare(ref, C, absAB)
+    assert same
+    return e_cw, e_f
+
+
+def test_f32_random(qt):
+    for b in (16, 32, 64):
+        rng = np.random.default_rng(20 + b)
+        A = random_pattern(rng, 40, 40, 0.1, b)
+        B = random_pattern(rng, 40, 40, 0.1, b)
+        _say("f32 b", b)
+        ref, _ = oracle.multiply(A, B, 4 * b)
+        absAB, _ = oracle.multiply(A, B, 4 * b, use_abs=True)
+        C, st, h = gpu_multiply(qt, A, B, 4 * b, "f32")
+        assert h.info()["value_type"] == "f32"
+        kmax = int(np.bincount(A.I, minlength=40).max())
+        same, e_max, e_f, e_cw = compare(ref, C, absAB)
+        assert same
+        assert e_cw <= (kmax * b + 2) * 2.0 ** -24, e_cw
+        assert e_f < 1e-6
+
+
+def test_bf16x3_random(qt):
+    for b in (32, 64):
+        rng = np.random.default_rng(30 + b)
+        A = random_pattern(rng, 30, 30, 0.15, b)
+        B = random_pattern(rng, 30, 30, 0.15, b)
+        _say("bf16x3 b", b)
+        ref, _ = oracle.multiply(A, B, 2 * b)
+        absAB, _ = oracle.multiply(A, B, 2 * b, use_abs=True)
+        C, st, h = gpu_multiply(qt, A, B, 2 * b, "bf16x3")
+        assert h.info()["value_type"] == "f64"
+        same, e_max, e_f, e_cw = compare(ref, C, absAB)
+        assert same
+        assert e_cw <= 3 * 2.0 ** -16 + (3 * b + 4) * 2.0 ** -24, e_cw
+        assert e_f < 2e-5
+    with pytest.raises(qt.QtError) as e:
+        X = qt.from_blockmatrix(random_pattern(np.random.default_rng(0), 4, 4, 0.5, 16), 32)
+        qt.multiply(X, X, "bf16x3")
+    assert e.value.status == qt.QT_ERR_UNSUPPORTED
+
+
+def test_bf16x3_split_form_is_what_is_computed(qt):
+    """The split path equals the fp64 product of the split operands up to fp32
+    accumulation inside one block product: dropping a cross term or a wrong
+    split would exceed this much tighter bound."""
+    from oracle.precision import split_bf16, with_values
+    b = 32
+    rng = np.random.default_rng(41)
+    A = random_pattern(rng, 24, 24, 0.2, b)
+    hi, lo = split_bf16(A.V)
+    Ah, Al = with_values(A, hi), with_values(A, lo)
+    hh, _ = oracle.multiply(Ah, Ah, 4 * b)
+    hl, _ = oracle.multiply(Ah, Al, 4 * b)
+    lh, _ = oracle.multiply(Al, Ah, 4 * b)
+    absAB, _ = oracle.multiply(A, A, 4 * b, use_abs=True)
+    ref = wl.BlockMatrix(A.n_rows, A.n_cols, b, hh.I, hh.J, hh.V + hl.V + lh.V)
+    C, _, _ = gpu_multiply(qt, A, A, 4 * b, "bf16x3", same=True)
+    same, e_max, e_f, e_cw = compare(ref, C, absAB)
+    assert same
+    assert e_cw <= 1.05 * (3 * b + 4) * 2.0 ** -24, e_cw
