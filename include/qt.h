@@ -137,6 +137,61 @@ qt_status qt_prepare(const qt_matrix* M, qt_prec prec, void* stream);
  * order on the stream that created it. */
 void qt_free(qt_matrix* M);
 
+/*
+ * Batched multiplies (many independent C_i = A_i * B_i, one block size).
+ *
+ * qt_plan_create runs the symbolic phase (the quadtree traversal of
+ * Algorithm 1, Sec. 3) of every problem now -- it synchronizes `stream` and
+ * allocates every C_i -- and lays the numeric work of all problems out as one
+ * work list: problems by decreasing block products, C blocks of a problem in
+ * Morton order.
+ *   count:  number of problems (>= 1); A[i], B[i] as for qt_multiply (same
+ *           block size across the batch; leaf sizes may differ per problem).
+ * Errors: ARG, SHAPE, OOM, DEVICE, UNSUPPORTED.
+ *
+ * qt_plan_execute computes every C_i: one kernel launch (plus a one-thread
+ * counter reset for the persistent schedules) that allocates nothing and does
+ * not synchronize. With use_graph != 0 the first call captures that launch
+ * sequence into a HIP graph and every call replays it on `stream`; with
+ * use_graph == 0 the kernels are launched directly. Executions on one plan
+ * must not overlap (they share the plan's work counter and the C_i).
+ *
+ * qt_plan_tune times every schedule of the batch kernel (flat grid;
+ * persistent with 1, 4 or 16 C-block tiles per grab) on this plan, `reps`
+ * runs each, keeps the fastest and reports it in *schedule; ms (may be NULL)
+ * receives QT_PLAN_SCHEDULES mean times. It computes the C_i as a side effect
+ * and synchronizes `stream`.
+ *
+ * qt_plan_set_schedule picks a schedule directly (e.g. one tuned earlier).
+ *
+ * qt_plan_result returns C_i, owned by the plan: valid until
+ * qt_plan_destroy, and qt_free on it does nothing. qt_plan_info reports the
+ * number of work items (C-block tiles), block products and the schedule.
+ * qt_plan_destroy waits for the plan's last execution and releases all of it.
+ */
+#define QT_PLAN_SCHEDULES 4
+qt_status qt_plan_create(int32_t count, const qt_matrix* const* A, const qt_matrix* const* B, qt_prec prec,
+                         void* stream, qt_plan** plan);
+qt_status qt_plan_execute(qt_plan* plan, void* stream, int use_graph);
+qt_status qt_plan_tune(qt_plan* plan, void* stream, int reps, int32_t* schedule, float* ms);
+qt_status qt_plan_set_schedule(qt_plan* plan, int32_t schedule);   /* 0 .. QT_PLAN_SCHEDULES-1; ARG if not */
+qt_status qt_plan_result(const qt_plan* plan, int32_t i, qt_matrix** C);
+qt_status qt_plan_info(const qt_plan* plan, int64_t* work_items, int64_t* products, int32_t* schedule);
+void qt_plan_destroy(qt_plan* plan);
+
+/*
+ * Leaf-size tuner. Rebuilds A and B at every leaf size b, 2b, 4b, 8b and
+ * times the full qt_multiply (`reps` runs each) at precision `prec`; returns
+ * the fastest leaf size in *best_leaf. The leaf size only changes the
+ * symbolic phase (how many quadtree levels are walked before the block-sparse
+ * leaves, Sec. 4.1 and Sec. 5): the products and the result are the same at
+ * every leaf size. leaves / ms (may be NULL) receive up to max_out tried
+ * sizes and their mean times; *n_tried how many were tried. Synchronizes.
+ * Errors: ARG, SHAPE, OOM, DEVICE.
+ */
+qt_status qt_tune_leaf(const qt_matrix* A, const qt_matrix* B, qt_prec prec, void* stream, int reps,
+                       int32_t* best_leaf, int32_t* leaves, float* ms, int32_t max_out, int32_t* n_tried);
+
 /* Per-phase GPU timing of qt_multiply, from HIP events recorded on the
  * multiply's stream. qt_profile(1) starts recording (and clears totals),
  * qt_profile(0) stops. qt_profile_read synchronizes on the recorded events

@@ -63,6 +63,23 @@ def _load():
     lib.qt_profile_read.restype = ctypes.c_int
     lib.qt_profile_read.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
                                     i64p, i64p, i64p]
+    lib.qt_plan_create.restype = ctypes.c_int
+    lib.qt_plan_create.argtypes = [i32, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.c_int, vp, ctypes.POINTER(vp)]
+    lib.qt_plan_execute.restype = ctypes.c_int
+    lib.qt_plan_execute.argtypes = [vp, vp, ctypes.c_int]
+    lib.qt_plan_tune.restype = ctypes.c_int
+    lib.qt_plan_tune.argtypes = [vp, vp, ctypes.c_int, i32p, ctypes.POINTER(ctypes.c_float)]
+    lib.qt_plan_set_schedule.restype = ctypes.c_int
+    lib.qt_plan_set_schedule.argtypes = [vp, i32]
+    lib.qt_plan_result.restype = ctypes.c_int
+    lib.qt_plan_result.argtypes = [vp, i32, ctypes.POINTER(vp)]
+    lib.qt_plan_info.restype = ctypes.c_int
+    lib.qt_plan_info.argtypes = [vp, i64p, i64p, i32p]
+    lib.qt_plan_destroy.restype = None
+    lib.qt_plan_destroy.argtypes = [vp]
+    lib.qt_tune_leaf.restype = ctypes.c_int
+    lib.qt_tune_leaf.argtypes = [vp, vp, ctypes.c_int, vp, ctypes.c_int, i32p, i32p, ctypes.POINTER(ctypes.c_float),
+                                 i32, i32p]
     lib.qt_last_error.restype = ctypes.c_char_p
     lib.qt_last_error.argtypes = []
     lib.qt_version.restype = ctypes.c_char_p
@@ -73,7 +90,9 @@ def _load():
 lib = _load()
 
 EXPORTS = ("qt_build", "qt_multiply", "qt_info", "qt_to_blocks", "qt_stats", "qt_prepare", "qt_free",
-           "qt_profile", "qt_profile_read", "qt_last_error", "qt_version")
+           "qt_plan_create", "qt_plan_execute", "qt_plan_tune", "qt_plan_set_schedule", "qt_plan_result", "qt_plan_info",
+           "qt_plan_destroy", "qt_tune_leaf", "qt_profile", "qt_profile_read", "qt_last_error", "qt_version")
+PLAN_SCHEDULES = ("flat", "persistent-1", "persistent-4", "persistent-16")
 
 
 def _check(status: int):
@@ -185,6 +204,75 @@ def multiply(A: Matrix, B: Matrix, prec: str = "f64", stream=None) -> Matrix:
     out = ctypes.c_void_p()
     _check(lib.qt_multiply(A.handle, B.handle, PREC[prec], _stream_ptr(stream), ctypes.byref(out)))
     return Matrix(out.value)
+
+
+class _Borrowed(Matrix):
+    """A result handle owned by a Plan (never freed through this wrapper)."""
+
+    def __init__(self, handle: int, plan):
+        super().__init__(handle)
+        self._plan = plan          # keeps the plan alive while the handle is used
+
+    def free(self):
+        self._h = None
+
+
+class Plan:
+    """qt_plan_*: many independent C_i = A_i * B_i, numeric phase in one launch."""
+
+    def __init__(self, As, Bs, prec: str = "f64", stream=None):
+        n = len(As)
+        arrA = (ctypes.c_void_p * n)(*[a.handle.value for a in As])
+        arrB = (ctypes.c_void_p * n)(*[b.handle.value for b in Bs])
+        out = ctypes.c_void_p()
+        _check(lib.qt_plan_create(n, arrA, arrB, PREC[prec], _stream_ptr(stream), ctypes.byref(out)))
+        self._h = out
+        self.count = n
+        self._keep = (list(As), list(Bs))
+
+    def execute(self, stream=None, graph: bool = True):
+        _check(lib.qt_plan_execute(self._h, _stream_ptr(stream), 1 if graph else 0))
+
+    def tune(self, reps: int = 3, stream=None):
+        sched = ctypes.c_int32()
+        ms = (ctypes.c_float * 4)()
+        _check(lib.qt_plan_tune(self._h, _stream_ptr(stream), reps, ctypes.byref(sched), ms))
+        return PLAN_SCHEDULES[sched.value], {PLAN_SCHEDULES[i]: ms[i] for i in range(4)}
+
+    def set_schedule(self, name: str):
+        _check(lib.qt_plan_set_schedule(self._h, PLAN_SCHEDULES.index(name)))
+
+    def result(self, i: int) -> Matrix:
+        out = ctypes.c_void_p()
+        _check(lib.qt_plan_result(self._h, i, ctypes.byref(out)))
+        return _Borrowed(out.value, self)
+
+    def info(self) -> dict:
+        items, prods, sched = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int32()
+        _check(lib.qt_plan_info(self._h, ctypes.byref(items), ctypes.byref(prods), ctypes.byref(sched)))
+        return {"work_items": items.value, "products": prods.value, "schedule": PLAN_SCHEDULES[sched.value]}
+
+    def destroy(self):
+        if self._h is not None and self._h.value:
+            lib.qt_plan_destroy(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+
+def tune_leaf(A: Matrix, B: Matrix, prec: str = "f64", reps: int = 3, stream=None):
+    """qt_tune_leaf: fastest leaf size for C = A*B, with the tried sizes' times (ms)."""
+    best = ctypes.c_int32()
+    leaves = (ctypes.c_int32 * 8)()
+    ms = (ctypes.c_float * 8)()
+    n = ctypes.c_int32()
+    _check(lib.qt_tune_leaf(A.handle, B.handle, PREC[prec], _stream_ptr(stream), reps, ctypes.byref(best), leaves,
+                            ms, 8, ctypes.byref(n)))
+    return best.value, {leaves[i]: ms[i] for i in range(n.value)}
 
 
 def prepare(M: Matrix, prec: str, stream=None):

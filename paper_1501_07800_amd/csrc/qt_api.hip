@@ -14,6 +14,16 @@ qt_matrix* build(int64_t, int64_t, int32_t, int32_t, int64_t, const int32_t*, co
                  qt_mem, hipStream_t);
 qt_matrix* multiply(qt_matrix*, qt_matrix*, qt_prec, hipStream_t);
 void to_blocks(const qt_matrix*, int32_t*, int32_t*, void*, qt_prec, qt_mem, hipStream_t);
+qt_plan* plan_create(int32_t, const qt_matrix* const*, const qt_matrix* const*, qt_prec, hipStream_t);
+void plan_execute(qt_plan*, hipStream_t, int);
+int plan_tune(qt_plan*, hipStream_t, int, float*);
+int32_t tune_leaf(const qt_matrix*, const qt_matrix*, qt_prec, hipStream_t, int, int32_t*, float*, int32_t,
+                  int32_t*);
+int32_t plan_count(const qt_plan*);
+qt_matrix* plan_result(const qt_plan*, int32_t);
+void plan_info(const qt_plan*, int64_t*, int64_t*, int32_t*);
+void plan_destroy(qt_plan*);
+void plan_set_schedule(qt_plan*, int32_t);
 
 // ------------------------------------------------------------ profiling
 
@@ -170,6 +180,7 @@ qt_status qt_prepare(const qt_matrix* M, qt_prec prec, void* stream) {
 }
 
 void qt_free(qt_matrix* M) {
+    if (M && M->plan_owned) return;   // released by qt_plan_destroy
     try {
         delete M;
     } catch (...) {
@@ -197,6 +208,89 @@ qt_status qt_profile_read(double* symbolic_ms, double* numeric_ms, int64_t* call
     if (calls) *calls = g_prof_calls;
     if (products) *products = g_prof_products;
     if (c_blocks) *c_blocks = g_prof_cblocks;
+    return QT_OK;
+    QT_GUARD_END
+}
+
+qt_status qt_plan_create(int32_t count, const qt_matrix* const* A, const qt_matrix* const* B, qt_prec prec,
+                         void* stream, qt_plan** plan) {
+    if (!plan) {
+        set_last_error("NULL output handle");
+        return QT_ERR_ARG;
+    }
+    *plan = nullptr;
+    QT_GUARD_BEGIN
+    *plan = plan_create(count, A, B, prec, (hipStream_t)stream);
+    return QT_OK;
+    QT_GUARD_END
+}
+
+qt_status qt_plan_execute(qt_plan* plan, void* stream, int use_graph) {
+    if (!plan) {
+        set_last_error("NULL plan");
+        return QT_ERR_ARG;
+    }
+    QT_GUARD_BEGIN
+    plan_execute(plan, (hipStream_t)stream, use_graph);
+    return QT_OK;
+    QT_GUARD_END
+}
+
+qt_status qt_plan_tune(qt_plan* plan, void* stream, int reps, int32_t* schedule, float* ms) {
+    if (!plan) {
+        set_last_error("NULL plan");
+        return QT_ERR_ARG;
+    }
+    QT_GUARD_BEGIN
+    const int v = plan_tune(plan, (hipStream_t)stream, reps, ms);
+    if (schedule) *schedule = v;
+    return QT_OK;
+    QT_GUARD_END
+}
+
+qt_status qt_plan_set_schedule(qt_plan* plan, int32_t schedule) {
+    if (!plan || schedule < 0 || schedule >= kBatchVariants) {
+        set_last_error("bad plan or schedule");
+        return QT_ERR_ARG;
+    }
+    plan_set_schedule(plan, schedule);
+    return QT_OK;
+}
+
+qt_status qt_plan_result(const qt_plan* plan, int32_t i, qt_matrix** C) {
+    if (!plan || !C || i < 0 || i >= plan_count(plan)) {
+        set_last_error("bad plan, index or output");
+        if (C) *C = nullptr;
+        return QT_ERR_ARG;
+    }
+    *C = plan_result(plan, i);
+    return QT_OK;
+}
+
+qt_status qt_plan_info(const qt_plan* plan, int64_t* work_items, int64_t* products, int32_t* schedule) {
+    if (!plan) {
+        set_last_error("NULL plan");
+        return QT_ERR_ARG;
+    }
+    plan_info(plan, work_items, products, schedule);
+    return QT_OK;
+}
+
+void qt_plan_destroy(qt_plan* plan) {
+    try {
+        plan_destroy(plan);
+    } catch (...) {
+    }
+}
+
+qt_status qt_tune_leaf(const qt_matrix* A, const qt_matrix* B, qt_prec prec, void* stream, int reps,
+                       int32_t* best_leaf, int32_t* leaves, float* ms, int32_t max_out, int32_t* n_tried) {
+    if (!A || !B || !best_leaf || max_out < 0) {
+        set_last_error("bad argument");
+        return QT_ERR_ARG;
+    }
+    QT_GUARD_BEGIN
+    *best_leaf = tune_leaf(A, B, prec, (hipStream_t)stream, reps, leaves, ms, max_out, n_tried);
     return QT_OK;
     QT_GUARD_END
 }

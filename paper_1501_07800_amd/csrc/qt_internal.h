@@ -149,6 +149,7 @@ struct qt_matrix {
     // counters of the multiply that produced this matrix
     std::vector<int64_t> pairs;
     int64_t products = 0;
+    bool plan_owned = false;  // a batch plan's result: released with the plan
 };
 
 namespace qt {
@@ -199,9 +200,46 @@ struct NumericArgs {
 };
 void launch_numeric(const NumericArgs& a, hipStream_t s);
 
+// One problem of a batch, as the batch kernels read it (device memory).
+struct BatchProblem {
+    const void* A;            // fp64 / fp32 operands
+    const void* B;
+    const uint16_t* Ahi; const uint16_t* Alo;     // split-bf16 operands
+    const uint16_t* Bhi_t; const uint16_t* Blo_t;
+    const int32_t* prodA;
+    const int32_t* prodB;
+    const int32_t* seg;
+    void* C;
+};
+struct BatchLaunch {
+    int b = 0;
+    qt_prec prec = QT_F64;
+    int variant = 0;          // 0 flat grid; 1, 2, 3 persistent with 1, 4, 16 items per grab
+    const BatchProblem* probs = nullptr;
+    const int64_t* item_base = nullptr;   // nprob + 1 prefix offsets of work items
+    int32_t nprob = 0;
+    int64_t total_items = 0;
+    unsigned long long* counter = nullptr;
+    int persistent_grid = 0;
+};
+void launch_batch(const BatchLaunch& L, hipStream_t s);
+int batch_persistent_grid(int b, qt_prec prec);
+constexpr int kBatchVariants = 4;
+
 // profiling ----------------------------------------------------------------
 bool profiling_on();
 struct PhaseEvents { hipEvent_t e0, e1, e2; int64_t products, cblocks; };
 void profile_push(const PhaseEvents& ev);
+
+// multiply.hip -------------------------------------------------------------
+struct SymbolicOut {
+    std::unique_ptr<qt_matrix> C;
+    DBuf<char> scratch;       // product lists and other symbolic buffers
+    NumericArgs na{};         // ready for launch_numeric (na.nseg C blocks)
+    PhaseEvents ev{};
+    bool prof = false;
+};
+void symbolic(qt_matrix* A, qt_matrix* B, qt_prec prec, hipStream_t s, SymbolicOut& out,
+              bool allow_profile = true);
 
 }  // namespace qt

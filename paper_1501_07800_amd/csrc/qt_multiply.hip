@@ -511,14 +511,22 @@ static qt_matrix* empty_result(const qt_matrix* A, const qt_matrix* B, int L, qt
     return C;
 }
 
-qt_matrix* multiply(qt_matrix* A, qt_matrix* B, qt_prec prec, hipStream_t s) {
+// Symbolic phase of C = A*B: C's tree, block keys and (uninitialised) value
+// array, plus the product lists the numeric phase reads (kept in
+// out.scratch). Synchronizes once. out.na.nseg == 0 means C has no blocks.
+void symbolic(qt_matrix* A, qt_matrix* B, qt_prec prec, hipStream_t s, SymbolicOut& out, bool allow_profile) {
     if (prec != QT_F64 && prec != QT_F32 && prec != QT_BF16X3) fail(QT_ERR_ARG, "unknown precision");
     if (A->b != B->b || A->leaf != B->leaf) fail(QT_ERR_SHAPE, "operands differ in block or leaf size");
     if (A->n_cols != B->n_rows) fail(QT_ERR_SHAPE, "inner dimensions differ");
     if (prec == QT_BF16X3 && A->b == 16) fail(QT_ERR_UNSUPPORTED, "split-bf16 path needs b = 32 or 64");
     const int L = std::max(A->L, B->L);
     const int liftA = L - A->L, liftB = L - B->L;
-    if (A->nblocks == 0 || B->nblocks == 0) return empty_result(A, B, L, prec, s);
+    out.na = NumericArgs{};
+    out.prof = false;
+    if (A->nblocks == 0 || B->nblocks == 0) {
+        out.C.reset(empty_result(A, B, L, prec, s));
+        return;
+    }
 
     build_histograms(A, s);
     build_histograms(B, s);
@@ -537,9 +545,9 @@ qt_matrix* multiply(qt_matrix* A, qt_matrix* B, qt_prec prec, hipStream_t s) {
         if (4 * pairs[l] > kMaxI32) fail(QT_ERR_UNSUPPORTED, "too many node pairs at one level");
     if (P > kMaxI32) fail(QT_ERR_UNSUPPORTED, "too many block products");
     if (P == 0) {
-        qt_matrix* C = empty_result(A, B, L, prec, s);
-        C->pairs = pairs;
-        return C;
+        out.C.reset(empty_result(A, B, L, prec, s));
+        out.C->pairs = pairs;
+        return;
     }
 
     // operand forms for this precision
@@ -589,18 +597,19 @@ qt_matrix* multiply(qt_matrix* A, qt_matrix* B, qt_prec prec, hipStream_t s) {
     const size_t o_cbseg = tmp.take((cap + 1) * sizeof(int32_t));
     const size_t o_count = tmp.take((2 * L + 4) * sizeof(int32_t));
 
-    std::unique_ptr<qt_matrix> C(new_result(A, B, L, prec, s));
+    out.C.reset(new_result(A, B, L, prec, s));
+    qt_matrix* C = out.C.get();
     C->pairs = pairs;
     C->products = P;
     C->arena.alloc(keep.bytes, s);
-    DBuf<char> scratch(tmp.bytes, s);
+    out.scratch.alloc(tmp.bytes, s);
     char* K = C->arena.p;
-    char* W = scratch.p;
+    char* W = out.scratch.p;
     auto at = [](char* base, size_t off) { return (void*)(base + off); };
     int32_t* dcount = (int32_t*)at(W, o_count);   // [0..L] C nodes per level, [L+1] C blocks, then checks
 
-    const bool prof = profiling_on();
-    PhaseEvents ev{};
+    const bool prof = out.prof = allow_profile && profiling_on();
+    PhaseEvents& ev = out.ev;
     if (prof) {
         QT_HIP(hipEventCreate(&ev.e0));
         QT_HIP(hipEventCreate(&ev.e1));
@@ -733,14 +742,20 @@ qt_matrix* multiply(qt_matrix* A, qt_matrix* B, qt_prec prec, hipStream_t s) {
     na.seg = ls.cbseg;
     na.nseg = nnzC;
     na.C = (prec == QT_F32) ? (void*)C->v32.p : (void*)C->v64.p;
-    launch_numeric(na, s);
-    if (prof) {
-        QT_HIP(hipEventRecord(ev.e2, s));
-        ev.products = P;
-        ev.cblocks = nnzC;
-        profile_push(ev);
+    out.na = na;
+    ev.products = P;
+    ev.cblocks = nnzC;
+}
+
+qt_matrix* multiply(qt_matrix* A, qt_matrix* B, qt_prec prec, hipStream_t s) {
+    SymbolicOut sym;
+    symbolic(A, B, prec, s, sym);
+    if (sym.na.nseg > 0) launch_numeric(sym.na, s);
+    if (sym.prof) {
+        QT_HIP(hipEventRecord(sym.ev.e2, s));
+        profile_push(sym.ev);
     }
-    return C.release();
+    return sym.C.release();   // sym.scratch is released in stream order
 }
 
 }  // namespace qt

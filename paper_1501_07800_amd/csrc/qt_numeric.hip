@@ -13,9 +13,15 @@
 // values are D[4*g + i][r] (i = 0..3) for fp32, but D[4*i + g][r] for fp64
 // (the fp64 instruction interleaves the row groups; checked on gfx950 with a
 // known-input product). The inner index is a free summation variable, which
-// lets each lane read its A entries with 16-byte loads (see k_numeric), while
-// the 16 lanes of a group read 16 consecutive entries of one B row.
+// lets each lane read its A entries with 16-byte loads (see wave_block),
+// while the 16 lanes of a group read 16 consecutive entries of one B row.
+//
+// The same per-wave routines serve one multiply (k_numeric: one launch over
+// the C blocks of C) and a batch of independent multiplies (k_batch_*: one
+// launch over the C blocks of all of them).
 #include "qt_internal.h"
+
+#include <algorithm>
 
 namespace qt {
 
@@ -42,7 +48,7 @@ template <> struct Mfma<float> {
 
 // Tile geometry for block size BS: each wave computes a WT x WT tile made of
 // MT x MT 16x16 MFMA tiles; WPB waves cover one C block; a 256-thread
-// workgroup covers SPW segments; the inner dimension is walked in chunks of
+// workgroup covers SPW C blocks; the inner dimension is walked in chunks of
 // KC with KS 4-deep MFMA steps each.
 template <int BS> struct Geo {
     static constexpr int WT = BS < 32 ? BS : 32;
@@ -54,112 +60,70 @@ template <int BS> struct Geo {
     static constexpr int NCH = BS / KC;
 };
 
-// Workgroups are dispatched round-robin over the 8 XCDs (each with its own
-// L2). Remap the hardware workgroup id so that every XCD works through one
-// contiguous run of C blocks: neighbouring C blocks in Morton order share
-// A block rows and B block columns, which then stay in that XCD's L2.
-__device__ __forceinline__ int64_t xcd_remap(int64_t w, int64_t G) {
-    const int64_t q = G >> 3, r = G & 7;
-    const int64_t x = w & 7, i = w >> 3;
-    return x * q + (x < r ? x : r) + i;
-}
-
+// One wave: tile `sub` of a C block, over the products t0 .. t1-1.
 template <class T, int BS>
-__global__ __launch_bounds__(256, 2) void k_numeric(const T* __restrict__ A, const T* __restrict__ B,
-                                                 const int32_t* __restrict__ prodA,
-                                                 const int32_t* __restrict__ prodB,
-                                                 const int32_t* __restrict__ seg, int32_t nseg,
-                                                 T* __restrict__ C) {
+__device__ __forceinline__ void wave_block(const T* __restrict__ A, const T* __restrict__ B,
+                                           const int32_t* __restrict__ prodA, const int32_t* __restrict__ prodB,
+                                           int32_t t0, int32_t t1, T* __restrict__ c, int sub) {
     typedef Geo<BS> G;
     typedef typename Mfma<T>::acc acc_t;
     constexpr int VEC = 16 / sizeof(T);            // elements per 16-byte load
     constexpr int NV = G::KS / VEC;                // 16-byte loads per A row per chunk
     typedef T vec_t __attribute__((ext_vector_type(VEC)));
     const int lane = threadIdx.x & 63;
-    const int wave = threadIdx.x >> 6;
     const int r16 = lane & 15;
     const int g = lane >> 4;
-    const int sub = wave % G::WPB;
-    const int64_t wg = xcd_remap(blockIdx.x, gridDim.x);
-    const int64_t s = wg * G::SPW + wave / G::WPB;
-    if (s >= nseg) return;
     const int wm = (sub / (BS / G::WT)) * G::WT;
     const int wn = (sub % (BS / G::WT)) * G::WT;
 
-    // Step ks of a chunk gives lane group g the inner index
-    //   k = (ks / VEC) * 4*VEC + g*VEC + ks % VEC,
-    // so each 16-byte A load of a lane is VEC consecutive entries of its row
-    // and the four lane groups together read one contiguous run per row.
-    struct Ops {
-        T a[G::MT][G::KS];
-        T b[G::MT][G::KS];
-    };
-    auto load = [&](Ops& o, const T* __restrict__ a, const T* __restrict__ b, int ch) {
-#pragma unroll
-        for (int mt = 0; mt < G::MT; ++mt) {
-            const T* row = a + (wm + mt * 16 + r16) * BS + ch * G::KC + g * VEC;
-#pragma unroll
-            for (int v = 0; v < NV; ++v) {
-                const vec_t x = *reinterpret_cast<const vec_t*>(row + v * 4 * VEC);
-#pragma unroll
-                for (int e = 0; e < VEC; ++e) o.a[mt][v * VEC + e] = x[e];
-            }
-        }
-#pragma unroll
-        for (int nt = 0; nt < G::MT; ++nt)
-#pragma unroll
-            for (int v = 0; v < NV; ++v)
-#pragma unroll
-                for (int e = 0; e < VEC; ++e)
-                    o.b[nt][v * VEC + e] = b[(ch * G::KC + v * 4 * VEC + g * VEC + e) * BS + wn + nt * 16 + r16];
-    };
     acc_t acc[G::MT][G::MT];
 #pragma unroll
     for (int i = 0; i < G::MT; ++i)
 #pragma unroll
         for (int j = 0; j < G::MT; ++j) acc[i][j] = acc_t{0, 0, 0, 0};
-    auto compute = [&](const Ops& o) {
-#pragma unroll
-        for (int ks = 0; ks < G::KS; ++ks)
-#pragma unroll
-            for (int mt = 0; mt < G::MT; ++mt)
-#pragma unroll
-                for (int nt = 0; nt < G::MT; ++nt)
-                    acc[mt][nt] = Mfma<T>::step(o.a[mt][ks], o.b[nt][ks], acc[mt][nt]);
-    };
 
-    // Software pipeline over stages (product t, chunk ch): the operands of
-    // the next stage are loaded while the MFMAs of this one run; block
-    // indices are fetched one product further ahead.
-    const int32_t t0 = seg[s], t1 = seg[s + 1];
-    const int32_t nstages = (t1 - t0) * G::NCH;
-    int32_t tl = t0;
-    int chl = 0;
+    // Step ks of a chunk gives lane group g the inner index
+    //   k = (ks / VEC) * 4*VEC + g*VEC + ks % VEC,
+    // so each 16-byte A load of a lane is VEC consecutive entries of its row
+    // and the four lane groups together read one contiguous run per row.
+    // Block indices of the next product are fetched while this one runs.
     int32_t ia = prodA[t0], ib = prodB[t0];
-    int32_t ia_n = (t0 + 1 < t1) ? prodA[t0 + 1] : 0, ib_n = (t0 + 1 < t1) ? prodB[t0 + 1] : 0;
-    auto issue = [&](Ops& o) {
-        load(o, A + (size_t)ia * (BS * BS), B + (size_t)ib * (BS * BS), chl);
-        if (++chl == G::NCH) {
-            chl = 0;
-            ++tl;
-            ia = ia_n;
-            ib = ib_n;
-            if (tl + 1 < t1) {
-                ia_n = prodA[tl + 1];
-                ib_n = prodB[tl + 1];
-            }
+    for (int32_t t = t0; t < t1; ++t) {
+        const T* a = A + (size_t)ia * (BS * BS);
+        const T* b = B + (size_t)ib * (BS * BS);
+        if (t + 1 < t1) {
+            ia = prodA[t + 1];
+            ib = prodB[t + 1];
         }
-    };
-    Ops o0, o1;
-    issue(o0);
-    for (int32_t u = 0; u < nstages; u += 2) {
-        if (u + 1 < nstages) issue(o1);
-        compute(o0);
-        if (u + 1 >= nstages) break;
-        if (u + 2 < nstages) issue(o0);
-        compute(o1);
+#pragma unroll
+        for (int ch = 0; ch < G::NCH; ++ch) {
+            T ar[G::MT][G::KS], br[G::MT][G::KS];
+#pragma unroll
+            for (int mt = 0; mt < G::MT; ++mt) {
+                const T* row = a + (wm + mt * 16 + r16) * BS + ch * G::KC + g * VEC;
+#pragma unroll
+                for (int v = 0; v < NV; ++v) {
+                    const vec_t x = *reinterpret_cast<const vec_t*>(row + v * 4 * VEC);
+#pragma unroll
+                    for (int e = 0; e < VEC; ++e) ar[mt][v * VEC + e] = x[e];
+                }
+            }
+#pragma unroll
+            for (int nt = 0; nt < G::MT; ++nt)
+#pragma unroll
+                for (int v = 0; v < NV; ++v)
+#pragma unroll
+                    for (int e = 0; e < VEC; ++e)
+                        br[nt][v * VEC + e] = b[(ch * G::KC + v * 4 * VEC + g * VEC + e) * BS + wn + nt * 16 + r16];
+#pragma unroll
+            for (int ks = 0; ks < G::KS; ++ks)
+#pragma unroll
+                for (int mt = 0; mt < G::MT; ++mt)
+#pragma unroll
+                    for (int nt = 0; nt < G::MT; ++nt)
+                        acc[mt][nt] = Mfma<T>::step(ar[mt][ks], br[nt][ks], acc[mt][nt]);
+        }
     }
-    T* c = C + (size_t)s * (BS * BS);
 #pragma unroll
     for (int mt = 0; mt < G::MT; ++mt)
 #pragma unroll
@@ -182,25 +146,17 @@ __device__ __forceinline__ v8bf load8(const uint16_t* p) {
 }
 
 template <int BS>
-__global__ __launch_bounds__(256) void k_numeric_bf16x3(const uint16_t* __restrict__ Ahi,
-                                                        const uint16_t* __restrict__ Alo,
-                                                        const uint16_t* __restrict__ Bhi_t,
-                                                        const uint16_t* __restrict__ Blo_t,
-                                                        const int32_t* __restrict__ prodA,
-                                                        const int32_t* __restrict__ prodB,
-                                                        const int32_t* __restrict__ seg, int32_t nseg,
-                                                        double* __restrict__ C) {
+__device__ __forceinline__ void wave_block_bf16x3(const uint16_t* __restrict__ Ahi, const uint16_t* __restrict__ Alo,
+                                                  const uint16_t* __restrict__ Bhi_t,
+                                                  const uint16_t* __restrict__ Blo_t,
+                                                  const int32_t* __restrict__ prodA,
+                                                  const int32_t* __restrict__ prodB, int32_t t0, int32_t t1,
+                                                  double* __restrict__ c, int sub) {
     static_assert(BS == 32 || BS == 64, "split-bf16 path needs b = 32 or 64");
     constexpr int WT = 32, MT = 2;
-    constexpr int WPB = (BS / WT) * (BS / WT);
-    constexpr int SPW = 4 / WPB;
     const int lane = threadIdx.x & 63;
-    const int wave = threadIdx.x >> 6;
     const int r16 = lane & 15;
     const int g = lane >> 4;
-    const int sub = wave % WPB;
-    const int64_t s = xcd_remap(blockIdx.x, gridDim.x) * SPW + wave / WPB;
-    if (s >= nseg) return;
     const int wm = (sub / (BS / WT)) * WT;
     const int wn = (sub % (BS / WT)) * WT;
 
@@ -210,7 +166,6 @@ __global__ __launch_bounds__(256) void k_numeric_bf16x3(const uint16_t* __restri
 #pragma unroll
         for (int j = 0; j < MT; ++j) acc[i][j] = v4d{0, 0, 0, 0};
 
-    const int32_t t0 = seg[s], t1 = seg[s + 1];
     for (int32_t t = t0; t < t1; ++t) {
         const size_t oa = (size_t)prodA[t] * (BS * BS);
         const size_t ob = (size_t)prodB[t] * (BS * BS);
@@ -250,7 +205,6 @@ __global__ __launch_bounds__(256) void k_numeric_bf16x3(const uint16_t* __restri
 #pragma unroll
                 for (int i = 0; i < 4; ++i) acc[mt][nt][i] += (double)f[mt][nt][i];
     }
-    double* c = C + (size_t)s * (BS * BS);
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
@@ -258,6 +212,39 @@ __global__ __launch_bounds__(256) void k_numeric_bf16x3(const uint16_t* __restri
 #pragma unroll
             for (int i = 0; i < 4; ++i)
                 c[(wm + mt * 16 + 4 * g + i) * BS + wn + nt * 16 + r16] = acc[mt][nt][i];
+}
+
+// ------------------------------------------------------ one multiply
+
+template <class T, int BS>
+__global__ __launch_bounds__(256) void k_numeric(const T* __restrict__ A, const T* __restrict__ B,
+                                                 const int32_t* __restrict__ prodA,
+                                                 const int32_t* __restrict__ prodB,
+                                                 const int32_t* __restrict__ seg, int32_t nseg,
+                                                 T* __restrict__ C) {
+    typedef Geo<BS> G;
+    const int wave = threadIdx.x >> 6;
+    const int64_t s = (int64_t)blockIdx.x * G::SPW + wave / G::WPB;
+    if (s >= nseg) return;
+    wave_block<T, BS>(A, B, prodA, prodB, seg[s], seg[s + 1], C + (size_t)s * (BS * BS), wave % G::WPB);
+}
+
+template <int BS>
+__global__ __launch_bounds__(256) void k_numeric_bf16x3(const uint16_t* __restrict__ Ahi,
+                                                        const uint16_t* __restrict__ Alo,
+                                                        const uint16_t* __restrict__ Bhi_t,
+                                                        const uint16_t* __restrict__ Blo_t,
+                                                        const int32_t* __restrict__ prodA,
+                                                        const int32_t* __restrict__ prodB,
+                                                        const int32_t* __restrict__ seg, int32_t nseg,
+                                                        double* __restrict__ C) {
+    constexpr int WPB = (BS / 32) * (BS / 32);
+    constexpr int SPW = 4 / WPB;
+    const int wave = threadIdx.x >> 6;
+    const int64_t s = (int64_t)blockIdx.x * SPW + wave / WPB;
+    if (s >= nseg) return;
+    wave_block_bf16x3<BS>(Ahi, Alo, Bhi_t, Blo_t, prodA, prodB, seg[s], seg[s + 1], C + (size_t)s * (BS * BS),
+                          wave % WPB);
 }
 
 template <class T, int BS>
@@ -299,6 +286,157 @@ void launch_numeric(const NumericArgs& a, hipStream_t s) {
         }
     }
     fail(QT_ERR_UNSUPPORTED, "no numeric kernel for this block size and precision");
+}
+
+// ------------------------------------------------- a batch of multiplies
+//
+// Work item i of the batch is one wave's tile of one C block. Problem p owns
+// items item_base[p] .. item_base[p+1]-1 (C blocks in Morton order, WPB tiles
+// each). Two schedules:
+//   flat:       one launch whose grid covers every item (the hardware
+//               dispatcher balances the uneven problems);
+//   persistent: a grid sized to fill the GPU once; each wave takes the next
+//               CHUNK items from a counter until none are left, so every
+//               wave exits after at most total/CHUNK + 1 rounds.
+
+template <class T, int BS>
+__device__ __forceinline__ void batch_item(const BatchProblem* __restrict__ probs,
+                                           const int64_t* __restrict__ item_base, int32_t nprob, int64_t it) {
+    constexpr int WPB = Geo<BS>::WPB;
+    int32_t lo = 0, hi = nprob - 1;                  // last p with item_base[p] <= it
+    while (lo < hi) {
+        const int32_t mid = (lo + hi + 1) >> 1;
+        if (item_base[mid] <= it)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    const BatchProblem& P = probs[lo];
+    const int64_t local = it - item_base[lo];
+    const int64_t s = local / WPB;
+    const int sub = (int)(local - s * WPB);
+    wave_block<T, BS>((const T*)P.A, (const T*)P.B, P.prodA, P.prodB, P.seg[s], P.seg[s + 1],
+                      (T*)P.C + (size_t)s * (BS * BS), sub);
+}
+
+template <int BS>
+__device__ __forceinline__ void batch_item_bf16x3(const BatchProblem* __restrict__ probs,
+                                                  const int64_t* __restrict__ item_base, int32_t nprob,
+                                                  int64_t it) {
+    constexpr int WPB = (BS / 32) * (BS / 32);
+    int32_t lo = 0, hi = nprob - 1;
+    while (lo < hi) {
+        const int32_t mid = (lo + hi + 1) >> 1;
+        if (item_base[mid] <= it)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    const BatchProblem& P = probs[lo];
+    const int64_t local = it - item_base[lo];
+    const int64_t s = local / WPB;
+    const int sub = (int)(local - s * WPB);
+    wave_block_bf16x3<BS>(P.Ahi, P.Alo, P.Bhi_t, P.Blo_t, P.prodA, P.prodB, P.seg[s], P.seg[s + 1],
+                          (double*)P.C + (size_t)s * (BS * BS), sub);
+}
+
+// Item dispatch for one (precision, block size) instance.
+template <int KIND, int BS> struct Item;
+template <int BS> struct Item<0, BS> {   // fp64
+    static __device__ __forceinline__ void run(const BatchProblem* p, const int64_t* ib, int32_t n, int64_t it) {
+        batch_item<double, BS>(p, ib, n, it);
+    }
+};
+template <int BS> struct Item<1, BS> {   // fp32
+    static __device__ __forceinline__ void run(const BatchProblem* p, const int64_t* ib, int32_t n, int64_t it) {
+        batch_item<float, BS>(p, ib, n, it);
+    }
+};
+template <int BS> struct Item<2, BS> {   // split bf16
+    static __device__ __forceinline__ void run(const BatchProblem* p, const int64_t* ib, int32_t n, int64_t it) {
+        batch_item_bf16x3<BS>(p, ib, n, it);
+    }
+};
+
+template <int KIND, int BS>
+__global__ __launch_bounds__(256) void k_batch_flat(const BatchProblem* __restrict__ probs,
+                                                    const int64_t* __restrict__ item_base, int32_t nprob) {
+    const int64_t it = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (it >= item_base[nprob]) return;
+    Item<KIND, BS>::run(probs, item_base, nprob, it);
+}
+
+template <int KIND, int BS, int CHUNK>
+__global__ __launch_bounds__(256) void k_batch_persistent(const BatchProblem* __restrict__ probs,
+                                                          const int64_t* __restrict__ item_base, int32_t nprob,
+                                                          unsigned long long* __restrict__ counter) {
+    const int lane = threadIdx.x & 63;
+    const int64_t total = item_base[nprob];
+    while (true) {
+        unsigned long long base = 0;
+        if (lane == 0) base = atomicAdd(counter, (unsigned long long)CHUNK);
+        base = __shfl(base, 0, 64);
+        if ((int64_t)base >= total) break;
+        const int64_t end = min((int64_t)base + CHUNK, total);
+        for (int64_t it = (int64_t)base; it < end; ++it) Item<KIND, BS>::run(probs, item_base, nprob, it);
+    }
+}
+
+// Clears the work counter (a kernel rather than a memset, so the launch
+// sequence can be captured into a graph and replayed).
+__global__ void k_batch_reset(unsigned long long* counter) { *counter = 0ull; }
+
+template <int KIND, int BS>
+static void launch_batch_kb(const BatchLaunch& L, hipStream_t s) {
+    if (L.variant == 0) {
+        const unsigned grid = (unsigned)((L.total_items + 3) / 4);
+        k_batch_flat<KIND, BS><<<grid, 256, 0, s>>>(L.probs, L.item_base, L.nprob);
+        QT_LAUNCH("k_batch_flat");
+        return;
+    }
+    k_batch_reset<<<1, 1, 0, s>>>(L.counter);
+    QT_LAUNCH("k_batch_reset");
+    const unsigned g = (unsigned)L.persistent_grid;
+    if (L.variant == 1)
+        k_batch_persistent<KIND, BS, 1><<<g, 256, 0, s>>>(L.probs, L.item_base, L.nprob, L.counter);
+    else if (L.variant == 2)
+        k_batch_persistent<KIND, BS, 4><<<g, 256, 0, s>>>(L.probs, L.item_base, L.nprob, L.counter);
+    else
+        k_batch_persistent<KIND, BS, 16><<<g, 256, 0, s>>>(L.probs, L.item_base, L.nprob, L.counter);
+    QT_LAUNCH("k_batch_persistent");
+}
+
+template <int KIND, int BS>
+static int persistent_grid_kb() {
+    int dev = 0, cus = 0, per_cu = 0;
+    QT_HIP(hipGetDevice(&dev));
+    QT_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    QT_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch_persistent<KIND, BS, 4>, 256, 0));
+    return std::max(1, cus * std::max(1, per_cu));
+}
+
+#define QT_BATCH_DISPATCH(FN, ...)                                                  \
+    do {                                                                            \
+        const int kind = (prec == QT_F64) ? 0 : (prec == QT_F32) ? 1 : 2;           \
+        if (kind == 0 && b == 16) return FN<0, 16>(__VA_ARGS__);                    \
+        if (kind == 0 && b == 32) return FN<0, 32>(__VA_ARGS__);                    \
+        if (kind == 0 && b == 64) return FN<0, 64>(__VA_ARGS__);                    \
+        if (kind == 1 && b == 16) return FN<1, 16>(__VA_ARGS__);                    \
+        if (kind == 1 && b == 32) return FN<1, 32>(__VA_ARGS__);                    \
+        if (kind == 1 && b == 64) return FN<1, 64>(__VA_ARGS__);                    \
+        if (kind == 2 && b == 32) return FN<2, 32>(__VA_ARGS__);                    \
+        if (kind == 2 && b == 64) return FN<2, 64>(__VA_ARGS__);                    \
+        fail(QT_ERR_UNSUPPORTED, "no batch kernel for this block size and precision"); \
+    } while (0)
+
+int batch_persistent_grid(int b, qt_prec prec) { QT_BATCH_DISPATCH(persistent_grid_kb); }
+
+void launch_batch(const BatchLaunch& L, hipStream_t s) {
+    if (L.total_items <= 0) return;
+    if (L.variant < 0 || L.variant > 3) fail(QT_ERR_ARG, "unknown batch schedule");
+    const int b = L.b;
+    const qt_prec prec = L.prec;
+    QT_BATCH_DISPATCH(launch_batch_kb, L, s);
 }
 
 }  // namespace qt

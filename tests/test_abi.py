@@ -64,3 +64,19 @@ def test_build_argument_checks(args, status):
     assert rc == status, qt.lib.qt_last_error()
     assert out.value is None
     assert qt.lib.qt_last_error()
+
+
+def test_plan_and_tuner_argument_checks():
+    import paper_1501_07800_amd as qt
+    out = ctypes.c_void_p()
+    assert qt.lib.qt_plan_create(0, None, None, 0, None, ctypes.byref(out)) == qt.QT_ERR_ARG
+    assert out.value is None
+    assert qt.lib.qt_plan_create(1, None, None, 0, None, None) == qt.QT_ERR_ARG
+    assert qt.lib.qt_plan_execute(None, None, 1) == qt.QT_ERR_ARG
+    assert qt.lib.qt_plan_tune(None, None, 1, None, None) == qt.QT_ERR_ARG
+    assert qt.lib.qt_plan_set_schedule(None, 0) == qt.QT_ERR_ARG
+    assert qt.lib.qt_plan_result(None, 0, ctypes.byref(out)) == qt.QT_ERR_ARG
+    assert qt.lib.qt_plan_info(None, None, None, None) == qt.QT_ERR_ARG
+    qt.lib.qt_plan_destroy(None)
+    best = ctypes.c_int32()
+    assert qt.lib.qt_tune_leaf(None, None, 0, None, 1, ctypes.byref(best), None, None, 0, None) == qt.QT_ERR_ARG

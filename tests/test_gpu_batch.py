@@ -1,0 +1,147 @@
+"""GPU: batched multiplies (qt_plan_*) and the leaf-size tuner, through the C ABI.
+
+Every plan result must equal the single-multiply result bit for bit (the
+same per-wave block GEMM, the same product order) and match the CPU oracle
+(pattern exact, fp64 within 1e-12 relative to |A||B|). Graph replays are
+checked against direct launches several times, with other GPU work between
+replays.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as wl
+from tests._util import compare, positions, random_pattern
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def qt():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1501_07800_amd as q
+    return q
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+def _problems(b=32, seed=0):
+    rng = np.random.default_rng(seed)
+    probs = []
+    probs.append((wl.banded(40, 2, b, seed=1), wl.banded(40, 3, b, seed=2)))
+    probs.append((random_pattern(rng, 70, 70, 0.03, b), random_pattern(rng, 70, 70, 0.03, b)))
+    probs.append((wl.decay3d(256, 14.0, 16, b, seed=3), wl.decay3d(256, 14.0, 16, b, seed=4)))
+    probs.append((random_pattern(rng, 23, 57, 0.1, b), random_pattern(rng, 57, 31, 0.1, b)))   # rectangular
+    probs.append((random_pattern(rng, 5, 5, 0.0, b), random_pattern(rng, 5, 5, 0.5, b)))      # empty A
+    probs.append((random_pattern(rng, 1, 1, 1.0, b), random_pattern(rng, 1, 1, 1.0, b)))      # one block
+    probs.append((random_pattern(rng, 120, 120, 0.01, b), random_pattern(rng, 120, 120, 0.02, b)))
+    return probs
+
+
+def _blocks(h, A, B):
+    I, J, V = h.to_blocks("f64")
+    return wl.BlockMatrix(A.n_rows, B.n_cols, A.b, I, J, V)
+
+
+def _check_against_oracle(C, A, B, leaf, tol):
+    ref, _ = oracle.multiply(A, B, leaf)
+    absAB, _ = oracle.multiply(A, B, leaf, use_abs=True)
+    same, _, e_f, e_cw = compare(ref, C, absAB)
+    assert same, (ref.nnz, C.nnz)
+    assert e_cw <= tol, e_cw
+
+
+@pytest.mark.parametrize("schedule", ["flat", "persistent-1", "persistent-4", "persistent-16"])
+def test_plan_matches_single_multiplies(qt, schedule):
+    probs = _problems()
+    leaf = 128
+    hs = [(qt.from_blockmatrix(A, leaf), qt.from_blockmatrix(B, leaf)) for A, B in probs]
+    singles = [_blocks(qt.multiply(a, b), A, B) for (a, b), (A, B) in zip(hs, probs)]
+    _say("plan", schedule, len(probs), "problems")
+    plan = qt.Plan([a for a, _ in hs], [b for _, b in hs], "f64")
+    plan.set_schedule(schedule)
+    plan.execute(graph=False)
+    for i, (A, B) in enumerate(probs):
+        C = _blocks(plan.result(i), A, B)
+        assert np.array_equal(positions(C), positions(singles[i]))
+        assert np.array_equal(C.V, singles[i].V)          # bitwise: same kernel body, same order
+        _check_against_oracle(C, A, B, leaf, 1e-12)
+    inf = plan.info()
+    assert inf["schedule"] == schedule
+    assert inf["products"] == sum(oracle.product_count(A, B) for A, B in probs)
+    plan.destroy()
+
+
+def test_plan_graph_replays(qt):
+    import torch
+    probs = _problems(seed=1)
+    hs = [(qt.from_blockmatrix(A, 64), qt.from_blockmatrix(B, 64)) for A, B in probs]
+    plan = qt.Plan([a for a, _ in hs], [b for _, b in hs], "f64")
+    plan.set_schedule("persistent-4")
+    plan.execute(graph=False)
+    eager = [_blocks(plan.result(i), A, B) for i, (A, B) in enumerate(probs)]
+    other = qt.from_blockmatrix(probs[1][0], 64)
+    for rep in range(4):
+        _say("graph replay", rep)
+        junk = qt.multiply(other, other)                  # unrelated GPU work between replays
+        x = torch.ones(1 << 20, device="cuda")
+        x.mul_(2.0)
+        plan.execute(graph=True)
+        torch.cuda.synchronize()
+        for i, (A, B) in enumerate(probs):
+            C = _blocks(plan.result(i), A, B)
+            assert np.array_equal(C.V, eager[i].V), (rep, i)
+        junk.free()
+    # switching the schedule re-captures the graph
+    plan.set_schedule("flat")
+    plan.execute(graph=True)
+    for i, (A, B) in enumerate(probs):
+        assert np.array_equal(_blocks(plan.result(i), A, B).V, eager[i].V)
+    plan.destroy()
+
+
+@pytest.mark.parametrize("prec,b", [("f32", 32), ("bf16x3", 32), ("f64", 64), ("bf16x3", 64), ("f64", 16)])
+def test_plan_precisions_and_block_sizes(qt, prec, b):
+    rng = np.random.default_rng(7)
+    probs = [(random_pattern(rng, 20, 20, 0.15, b), random_pattern(rng, 20, 20, 0.15, b)),
+             (random_pattern(rng, 9, 14, 0.3, b), random_pattern(rng, 14, 6, 0.3, b))]
+    leaf = 2 * b
+    hs = [(qt.from_blockmatrix(A, leaf), qt.from_blockmatrix(B, leaf)) for A, B in probs]
+    singles = [_blocks(qt.multiply(a, bb, prec), A, B) for (a, bb), (A, B) in zip(hs, probs)]
+    _say("plan", prec, "b", b)
+    plan = qt.Plan([a for a, _ in hs], [bb for _, bb in hs], prec)
+    sched, times = plan.tune(reps=2)
+    assert sched in qt.PLAN_SCHEDULES and len(times) == 4
+    plan.execute(graph=True)
+    for i, (A, B) in enumerate(probs):
+        C = _blocks(plan.result(i), A, B)
+        assert np.array_equal(C.V, singles[i].V)
+    plan.destroy()
+
+
+def test_plan_results_outlive_handles_and_free_is_ignored(qt):
+    probs = _problems(seed=2)[:2]
+    hs = [(qt.from_blockmatrix(A, 64), qt.from_blockmatrix(B, 64)) for A, B in probs]
+    plan = qt.Plan([a for a, _ in hs], [b for _, b in hs], "f64")
+    plan.execute()
+    r = plan.result(0)
+    qt.lib.qt_free(r.handle)                              # owned by the plan: ignored
+    C = _blocks(plan.result(0), *probs[0])
+    _check_against_oracle(C, probs[0][0], probs[0][1], 64, 1e-12)
+    with pytest.raises(qt.QtError):
+        plan.result(5)
+    plan.destroy()
+
+
+def test_tune_leaf(qt):
+    A = wl.decay3d(512, 16.0, 16, 32, seed=9)
+    h = qt.from_blockmatrix(A, 32)
+    best, times = qt.tune_leaf(h, h, "f64", reps=2)
+    assert best in (32, 64, 128, 256) and set(times) == {32, 64, 128, 256}
+    hb = qt.from_blockmatrix(A, best)
+    C = _blocks(qt.multiply(hb, hb), A, A)
+    _check_against_oracle(C, A, A, best, 1e-12)

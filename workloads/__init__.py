@@ -204,29 +204,49 @@ def decay3d(natoms: int, side: float, bf_per_atom: int, b: int, seed: int,
 
 
 def _decay_with_fill(n: int, b: int, fill: float, rng) -> BlockMatrix:
-    """Decay matrix of dimension n whose block fill is within 10% of ``fill``.
+    """Decay matrix of dimension n with block fill ``fill`` (to one block).
 
-    Atoms n/16 in a cube whose side keeps the density of the 32768-function
-    decay workload; the block threshold is bisected (on a log scale) until the
-    fill lands in range.
+    n/16 atoms in a cube whose side keeps the density of the 32768-function
+    decay workload, divide-space ordered as in ``decay3d``. Instead of a
+    fixed entry threshold, the kept blocks are the round(fill * nb^2) block
+    pairs whose closest atom pair is nearest -- equivalently, the blocks with
+    the largest bound exp(-0.5 d_min^2) on their entries, so the threshold is
+    the value that gives the wanted fill. Entries exp(-0.5 d^2) * U(0.5, 1).
     """
+    from scipy.spatial import cKDTree
+
     natoms = n // 16
     side = 40.0 * (n / 32768.0) ** (1.0 / 3.0)
-    seed = int(rng.integers(0, 2**31 - 1))
-    lo, hi = -300.0, -0.01                      # log10 of the threshold
-    best = None
-    for _ in range(40):
-        mid = 0.5 * (lo + hi)
-        M = decay3d(natoms, side, 16, b, seed, threshold=10.0 ** mid)
-        f = M.nnz / float(M.nb_rows * M.nb_cols)
-        best = M
-        if abs(f - fill) <= 0.1 * fill:
+    xyz = rng.uniform(0.0, side, size=(natoms, 3))
+    xyz = xyz[divide_space_order(xyz)]
+    apb = b // 16
+    nb = n // b
+    K = int(min(nb * nb, max(nb, round(fill * nb * nb))))
+    tree = cKDTree(xyz)
+    R = side / max(1.0, nb ** 0.5)
+    while True:
+        pairs = tree.query_pairs(r=R, output_type="ndarray")
+        d = np.sqrt(((xyz[pairs[:, 0]] - xyz[pairs[:, 1]]) ** 2).sum(-1))
+        bi, bj = pairs[:, 0] // apb, pairs[:, 1] // apb
+        key = np.concatenate([bi * nb + bj, bj * nb + bi, np.arange(nb, dtype=np.int64) * (nb + 1)])
+        dd = np.concatenate([d, d, np.zeros(nb)])
+        o = np.lexsort((dd, key))
+        key, dd = key[o], dd[o]
+        first = np.concatenate([[True], key[1:] != key[:-1]])
+        ukey, dmin = key[first], dd[first]
+        if ukey.size >= K or R > 2 * side:
             break
-        if f > fill:
-            lo = mid                            # raise the threshold: fewer blocks
-        else:
-            hi = mid
-    return best
+        R *= 1.4
+    sel = np.lexsort((ukey, dmin))[:K]
+    keys = np.sort(ukey[sel])                   # row-major block order
+    I = keys // nb
+    J = keys % nb
+    ai = xyz[(I[:, None] * apb + np.arange(apb)[None, :])]
+    aj = xyz[(J[:, None] * apb + np.arange(apb)[None, :])]
+    d2 = ((ai[:, :, None, :] - aj[:, None, :, :]) ** 2).sum(-1)
+    g = np.repeat(np.repeat(np.exp(-0.5 * d2), 16, axis=1), 16, axis=2)
+    V = g * (0.5 + 0.5 * rng.random((keys.size, b, b)))
+    return _finish(n, n, b, I, J, V, {"pattern": "decay3d-fill", "fill": fill})
 
 
 def batch_mix(count: int, seed: int, b: int = 32, n_lo: int = 2048,
