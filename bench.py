@@ -47,6 +47,95 @@ def timed_steps(qt, torch, hA, prec, steps, warmup):
     return (t1 - t0), prof, last
 
 
+def bench_batch(args, qt, torch, wl):
+    """64 independent C = A*B (uneven size, fill and pattern) in one launch.
+
+    Leaf size per pattern class from the leaf tuner; the plan's schedule from
+    the plan tuner; the timed step is one graph replay of the whole batch's
+    numeric phase. Baseline: the same 64 products as 64 qt_multiply calls.
+    """
+    import math
+    prec = args.prec if args.prec != "f64" or args.batch_prec_explicit else "f32"
+    log("bench: generating the 64-problem batch (seed 5)")
+    probs = wl.batch_mix(64, 5)
+    b = probs[0][0].b
+    cache = {}
+    hs = []
+    t_tune = time.perf_counter()
+    for A, B in probs:
+        fill = max(A.nnz, 1) / float(A.nb_rows * A.nb_cols)
+        cls = (A.meta.get("pattern"), int(round(math.log2(A.nb_rows))), int(round(math.log2(fill * 1000))))
+        if cls not in cache:
+            ha, hb = qt.from_blockmatrix(A, 8 * b), qt.from_blockmatrix(B, 8 * b)
+            cache[cls], _ = qt.tune_leaf(ha, hb, prec, reps=2)
+            del ha, hb
+        leaf = cache[cls]
+        ha, hb = qt.from_blockmatrix(A, leaf), qt.from_blockmatrix(B, leaf)
+        qt.prepare(ha, prec)
+        qt.prepare(hb, prec)
+        hs.append((ha, hb))
+    torch.cuda.synchronize()
+    t_tune = time.perf_counter() - t_tune
+    log(f"bench: {len(cache)} pattern classes tuned; leaves {sorted(set(cache.values()))}")
+
+    # baseline: 64 sequential multiplies
+    for ha, hb in hs:
+        qt.multiply(ha, hb, prec).free()
+    torch.cuda.synchronize()
+    qt.profile(True)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        for ha, hb in hs:
+            qt.multiply(ha, hb, prec).free()
+    torch.cuda.synchronize()
+    t_seq = (time.perf_counter() - t0) / args.steps
+    prof = qt.profile_read()
+    qt.profile(False)
+    seq_numeric_ms = prof["numeric_ms"] / args.steps
+    P = prof["products"] // args.steps
+    flops = 2.0 * b ** 3 * P
+
+    t0 = time.perf_counter()
+    plan = qt.Plan([a for a, _ in hs], [bb for _, bb in hs], prec)
+    torch.cuda.synchronize()
+    t_plan = time.perf_counter() - t0
+    sched, sched_ms = plan.tune(reps=3)
+    for _ in range(args.warmup):
+        plan.execute(graph=True)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record()
+    for _ in range(args.steps):
+        plan.execute(graph=True)
+    e1.record()
+    torch.cuda.synchronize()
+    t_exec = (time.perf_counter() - t0) / args.steps
+    exec_ms = e0.elapsed_time(e1) / args.steps
+    assert plan.info()["products"] == P
+    value = flops / (exec_ms * 1e-3) / 1e12
+    peak = PEAK["f32"] if prec in ("f32", "bf16x3") else PEAK["f64"]
+    log(f"bench: batch {prec}: plan {value:.2f} TFLOP/s ({exec_ms:.3f} ms, schedule {sched}); "
+        f"64 sequential multiplies {flops / t_seq / 1e12:.2f} TFLOP/s end to end ({t_seq * 1e3:.3f} ms), "
+        f"numeric only {flops / (seq_numeric_ms * 1e-3) / 1e12:.2f} TFLOP/s")
+    out = {
+        "metric": METRIC, "value": value, "unit": "TFLOP/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": exec_ms, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": prec, "data": "synthetic",
+        "config": {"workload": "batch64", "problems": len(probs), "b": b, "block_products": P, "prec": prec,
+                   "op": "C_i = A_i*B_i, i = 1..64", "leaf_by_class": {str(k): v for k, v in cache.items()}},
+        "mfma_peak_frac": value / peak,
+        "plan": {"schedule": sched, "schedule_ms": sched_ms, "create_s": t_plan, "tune_s": t_tune,
+                 "host_ms_per_step": t_exec * 1e3},
+        "sequential": {"tflops_end_to_end": flops / t_seq / 1e12, "ms_per_step": t_seq * 1e3,
+                       "numeric_ms_sum": seq_numeric_ms,
+                       "numeric_tflops": flops / (seq_numeric_ms * 1e-3) / 1e12},
+        "speedup_vs_sequential": t_seq * 1e3 / exec_ms,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -72,6 +161,9 @@ def main():
         sys.exit(2)
     import paper_1501_07800_amd as qt
 
+    if args.workload == "batch64":
+        args.batch_prec_explicit = "--prec" in sys.argv
+        return bench_batch(args, qt, torch, wl)
     cfg = wl.CONFIGS[args.workload]
     leaf = args.leaf or cfg["leaf"]
     log(f"bench: generating {args.workload}")

@@ -98,6 +98,42 @@ qt_status qt_multiply(const qt_matrix* A, const qt_matrix* B, qt_prec prec,
                       void* stream, qt_matrix** C);
 
 /*
+ * C = op(A) op(B) with op(X) = X or X^T (Sec. 3.2: the transposed multiply
+ * task types C = A^T B, A B^T, A^T B^T), optionally forming only the blocks
+ * of C on or above the block diagonal. op_flags is a combination of:
+ *   QT_OP_TRANS_A  use A^T;   QT_OP_TRANS_B  use B^T;
+ *   QT_OP_UPPER    C(I, J) only for I <= J (C must be square); the traversal
+ *                  drops every quadrant strictly below the diagonal.
+ * The transposed operands are read through a block-transposed copy of their
+ * values, built on first use and kept with the handle. Otherwise as
+ * qt_multiply. Errors: ARG (unknown flag), SHAPE, OOM, DEVICE, UNSUPPORTED.
+ */
+#define QT_OP_TRANS_A 1
+#define QT_OP_TRANS_B 2
+#define QT_OP_UPPER 4
+qt_status qt_multiply_ex(const qt_matrix* A, const qt_matrix* B, int32_t op_flags, qt_prec prec, void* stream,
+                         qt_matrix** C);
+
+/*
+ * C = A + B (Algorithm 2, Sec. 3): the union of the two block patterns; a
+ * block present in both is the sum of the two (fp64), a block present in one
+ * is copied. A and B must agree in dimensions, block size and leaf size.
+ * Synchronizes `stream`. Errors: ARG, SHAPE, OOM, DEVICE, UNSUPPORTED.
+ */
+qt_status qt_add(const qt_matrix* A, const qt_matrix* B, void* stream, qt_matrix** C);
+
+/*
+ * Symmetric matrix square (Sec. 3.3): A holds the upper block triangle
+ * (blocks with I <= J; diagonal blocks stored whole) of a symmetric S; C
+ * holds the upper block triangle of S*S. S is formed once from A (the strictly
+ * upper blocks mirrored and transposed) and kept with A; the product skips
+ * every C quadrant below the diagonal, about half the block products of S*S.
+ * Errors: ARG (a block below the diagonal), SHAPE (not square), OOM, DEVICE,
+ * UNSUPPORTED (A holds fp32 values).
+ */
+qt_status qt_sysq(const qt_matrix* A, qt_prec prec, void* stream, qt_matrix** C);
+
+/*
  * Describe a matrix. Any output pointer may be NULL. nblocks is the number
  * of stored (nonzero) blocks; value_type is QT_F64 or QT_F32.
  */
@@ -109,11 +145,24 @@ qt_status qt_info(const qt_matrix* M, int64_t* n_rows, int64_t* n_cols, int32_t*
  * I, J: nblocks int32 each; values: nblocks*b*b entries of out_type
  * (QT_F64 -> double, QT_F32 -> float; rounding to nearest even when the
  * stored type is wider). `where` says whether the three arrays are host or
- * device memory. Synchronizes `stream` when `where` is QT_MEM_HOST.
+ * device memory. values may be NULL to copy out the block pattern only.
+ * Synchronizes `stream` when `where` is QT_MEM_HOST.
  * Errors: ARG, UNSUPPORTED (out_type QT_BF16X3), OOM, DEVICE.
  */
 qt_status qt_to_blocks(const qt_matrix* M, int32_t* I, int32_t* J, void* values,
                        qt_prec out_type, qt_mem where, void* stream);
+
+/*
+ * Fetch chosen blocks: for t < count, block (I[t], J[t]) is looked up by
+ * binary search over the matrix's Morton-ordered block keys and copied to
+ * values + t*b*b (as out_type, like qt_to_blocks); found[t] is 1, or 0 with
+ * a zero block when the block is not stored (a NIL block). I, J, values and
+ * found are host or device memory as `where` says; out-of-range (I, J) give
+ * found = 0. Synchronizes `stream` when `where` is QT_MEM_HOST.
+ * Errors: ARG, UNSUPPORTED (out_type QT_BF16X3), OOM, DEVICE.
+ */
+qt_status qt_get_blocks(const qt_matrix* M, int64_t count, const int32_t* I, const int32_t* J, void* values,
+                        int32_t* found, qt_prec out_type, qt_mem where, void* stream);
 
 /*
  * Counters of the multiply that produced C (Sec. 5): pairs[l] is the number

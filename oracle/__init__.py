@@ -76,6 +76,9 @@ def load(path: str):
     lib.qo_result_stats.argtypes = [ctypes.c_void_p] + [ctypes.POINTER(ctypes.c_int64)] * 4
     lib.qo_result_free.restype = None
     lib.qo_result_free.argtypes = [ctypes.c_void_p]
+    lib.qo_add.restype = ctypes.c_int
+    lib.qo_add.argtypes = [i64, i64, i64, i32p, i32p, f64p, i64, i32p, i32p, f64p, ctypes.c_int, ctypes.c_int,
+                           ctypes.POINTER(ctypes.c_void_p)]
     lib.qo_threads.restype = ctypes.c_int
     lib.qo_threads.argtypes = [ctypes.c_int]
     return lib
@@ -139,6 +142,41 @@ def multiply(A: BlockMatrix, B: BlockMatrix, leaf: int, use_abs: bool = False,
     C = BlockMatrix(A.n_rows, B.n_cols, b, I, J, V, {"from": "oracle", "leaf": leaf})
     stats = OracleStats(mul, add, nodes, int(st[0]), int(st[1]))
     return C, stats
+
+
+def _take(lib, out, rows, cols, b, meta):
+    try:
+        nnz = lib.qo_result_nnz(out)
+        nl = lib.qo_result_levels(out)
+        I = np.empty(nnz, np.int32)
+        J = np.empty(nnz, np.int32)
+        V = np.empty((nnz, b, b), np.float64)
+        lib.qo_result_copy(out, _ptr(I, ctypes.c_int32), _ptr(J, ctypes.c_int32), _ptr(V, ctypes.c_double))
+        mul = np.zeros(nl, np.int64)
+        add = np.zeros(nl, np.int64)
+        nodes = np.zeros(nl, np.int64)
+        st = np.zeros(2, np.int64)
+        lib.qo_result_stats(out, *[_ptr(x, ctypes.c_int64) for x in (mul, add, nodes, st)])
+    finally:
+        lib.qo_result_free(out)
+    return BlockMatrix(rows, cols, b, I, J, V, meta), OracleStats(mul, add, nodes, int(st[0]), int(st[1]))
+
+
+def add(A: BlockMatrix, B: BlockMatrix, leaf: int, lib=None):
+    """C = A + B by Algorithm 2 (structural union; both-present blocks summed)."""
+    lib = _lib() if lib is None else lib
+    if A.b != B.b or A.n_rows != B.n_rows or A.n_cols != B.n_cols:
+        raise OracleError(2)
+    b = A.b
+    arrs = [np.ascontiguousarray(x, t) for x, t in ((A.I, np.int32), (A.J, np.int32), (A.V, np.float64),
+                                                     (B.I, np.int32), (B.J, np.int32), (B.V, np.float64))]
+    out = ctypes.c_void_p()
+    rc = lib.qo_add(A.n_rows, A.n_cols, A.nnz, _ptr(arrs[0], ctypes.c_int32), _ptr(arrs[1], ctypes.c_int32),
+                    _ptr(arrs[2], ctypes.c_double), B.nnz, _ptr(arrs[3], ctypes.c_int32),
+                    _ptr(arrs[4], ctypes.c_int32), _ptr(arrs[5], ctypes.c_double), b, leaf, ctypes.byref(out))
+    if rc != 0:
+        raise OracleError(rc)
+    return _take(lib, out, A.n_rows, A.n_cols, b, {"from": "oracle add", "leaf": leaf})
 
 
 def threads() -> int:

@@ -18,7 +18,8 @@
  *     C_mn = add(mul(A_m1, B_1n), mul(A_m2, B_2n)) for m, n in {1, 2} and the
  *     four results are assembled into one node (createFromIds, Sec. 3.2).
  *   - Add (Sec. 3, Algorithm 2): both present -> recurse (or leaf add);
- *     otherwise the one that is present, or NIL.
+ *     otherwise the one that is present, or NIL. Also exported on its own
+ *     (qo_add) for the standalone C = A + B.
  *   - Leaf multiply (Sec. 4.1, Fig. 2): every product A(i,k) B(k,j) of two
  *     present blocks is added into block (i,j) of the result; here as plain
  *     triple loops, k ascending, each block product summed over t ascending
@@ -428,6 +429,91 @@ int qo_multiply(int64_t a_rows, int64_t a_cols, int64_t a_nnz,
     memcpy(res->mul_tasks, ctx.mul_tasks, sizeof(ctx.mul_tasks));
     memcpy(res->add_tasks, ctx.add_tasks, sizeof(ctx.add_tasks));
     res->block_products = ctx.block_products;
+    res->leaf_block_adds = ctx.leaf_block_adds;
+    *out = res;
+    return QO_OK;
+}
+
+/* Deep copy of an input tree into owned blocks (Algorithm 2 consumes its
+ * operands, which are temporaries of Algorithm 1 in the multiply). */
+static qo_node *tree_clone(const qo_node *n, int lb, int b, int *err) {
+    if (!n) return NULL;
+    qo_node *c = node_new(n->is_leaf, lb);
+    if (!c) { *err = QO_ERR_OOM; return NULL; }
+    if (n->is_leaf) {
+        for (int q = 0; q < lb * lb; ++q) {
+            if (!n->blk[q]) continue;
+            c->blk[q] = (double *)malloc((size_t)b * b * sizeof(double));
+            if (!c->blk[q]) { *err = QO_ERR_OOM; tree_free(c, lb, 1); return NULL; }
+            memcpy(c->blk[q], n->blk[q], (size_t)b * b * sizeof(double));
+        }
+    } else {
+        for (int q = 0; q < 4; ++q) {
+            c->child[q] = tree_clone(n->child[q], lb, b, err);
+            if (*err) { tree_free(c, lb, 1); return NULL; }
+        }
+    }
+    return c;
+}
+
+/* C = A + B by Algorithm 2 (both operands rows x cols, same b and leaf). */
+int qo_add(int64_t rows, int64_t cols, int64_t a_nnz, const int32_t *Ia, const int32_t *Ja, const double *Va,
+           int64_t b_nnz, const int32_t *Ib, const int32_t *Jb, const double *Vb, int b, int leaf,
+           qo_result **out) {
+    *out = NULL;
+    if (b <= 0 || leaf <= 0 || rows < 0 || cols < 0) return QO_ERR_ARG;
+    if (rows % b || cols % b || leaf % b || !is_pow2(leaf / b)) return QO_ERR_SHAPE;
+    int lb = leaf / b;
+    int64_t nbr = rows / b, nbc = cols / b;
+    int rc = validate(nbr, nbc, a_nnz, Ia, Ja);
+    if (rc) return rc;
+    rc = validate(nbr, nbc, b_nnz, Ib, Jb);
+    if (rc) return rc;
+    int64_t need = nbr > nbc ? nbr : nbc, side = lb;
+    int L = 0;
+    while (side < need) { side *= 2; ++L; }
+    if (L + 1 >= QO_MAX_LEVELS) return QO_ERR_SHAPE;
+    qo_result *res = (qo_result *)calloc(1, sizeof(qo_result));
+    if (!res) return QO_ERR_OOM;
+    res->b = b; res->lb = lb; res->L = L;
+    int err = QO_OK;
+    int64_t *ia = (int64_t *)malloc((size_t)(a_nnz + 1) * sizeof(int64_t));
+    int64_t *ib = (int64_t *)malloc((size_t)(b_nnz + 1) * sizeof(int64_t));
+    if (!ia || !ib) { free(ia); free(ib); free(res); return QO_ERR_OOM; }
+    for (int64_t t = 0; t < a_nnz; ++t) ia[t] = t;
+    for (int64_t t = 0; t < b_nnz; ++t) ib[t] = t;
+    qo_node *A = tree_build(Ia, Ja, Va, b, lb, ia, a_nnz, 0, 0, side, &err);
+    qo_node *B = err ? NULL : tree_build(Ib, Jb, Vb, b, lb, ib, b_nnz, 0, 0, side, &err);
+    free(ia); free(ib);
+    qo_node *X = err ? NULL : tree_clone(A, lb, b, &err);
+    qo_node *Y = err ? NULL : tree_clone(B, lb, b, &err);
+    tree_free(A, lb, 0);
+    tree_free(B, lb, 0);
+    if (err) { tree_free(X, lb, 1); tree_free(Y, lb, 1); free(res); return err; }
+    qo_ctx ctx;
+    memset(&ctx, 0, sizeof(ctx));
+    ctx.b = b; ctx.lb = lb; ctx.L = L;
+    qo_node *C = qt_add(&ctx, 0, X, Y);
+    qo_list lst = {0};
+    collect(C, 0, L, lb, 0, 0, side, &lst, res->nodes_per_level);
+    if (lst.err) { free(lst.e); tree_free(C, lb, 1); free(res); return lst.err; }
+    qsort(lst.e, (size_t)lst.n, sizeof(qo_entry), cmp_entry);
+    res->nnz = lst.n;
+    res->I = (int32_t *)malloc((size_t)(lst.n + 1) * sizeof(int32_t));
+    res->J = (int32_t *)malloc((size_t)(lst.n + 1) * sizeof(int32_t));
+    res->V = (double *)malloc((size_t)(lst.n + 1) * b * b * sizeof(double));
+    if (!res->I || !res->J || !res->V) {
+        free(res->I); free(res->J); free(res->V); free(lst.e); tree_free(C, lb, 1); free(res);
+        return QO_ERR_OOM;
+    }
+    for (int64_t t = 0; t < lst.n; ++t) {
+        res->I[t] = lst.e[t].I;
+        res->J[t] = lst.e[t].J;
+        memcpy(res->V + (size_t)t * b * b, lst.e[t].p, (size_t)b * b * sizeof(double));
+    }
+    free(lst.e);
+    tree_free(C, lb, 1);
+    memcpy(res->add_tasks, ctx.add_tasks, sizeof(ctx.add_tasks));
     res->leaf_block_adds = ctx.leaf_block_adds;
     *out = res;
     return QO_OK;

@@ -48,10 +48,18 @@ def _load():
     lib.qt_build.argtypes = [i64, i64, i32, i32, i64, vp, vp, vp, ctypes.c_int, vp, ctypes.POINTER(vp)]
     lib.qt_multiply.restype = ctypes.c_int
     lib.qt_multiply.argtypes = [vp, vp, ctypes.c_int, vp, ctypes.POINTER(vp)]
+    lib.qt_multiply_ex.restype = ctypes.c_int
+    lib.qt_multiply_ex.argtypes = [vp, vp, i32, ctypes.c_int, vp, ctypes.POINTER(vp)]
+    lib.qt_add.restype = ctypes.c_int
+    lib.qt_add.argtypes = [vp, vp, vp, ctypes.POINTER(vp)]
+    lib.qt_sysq.restype = ctypes.c_int
+    lib.qt_sysq.argtypes = [vp, ctypes.c_int, vp, ctypes.POINTER(vp)]
     lib.qt_info.restype = ctypes.c_int
     lib.qt_info.argtypes = [vp, i64p, i64p, i32p, i32p, i64p, ctypes.POINTER(ctypes.c_int)]
     lib.qt_to_blocks.restype = ctypes.c_int
     lib.qt_to_blocks.argtypes = [vp, vp, vp, vp, ctypes.c_int, ctypes.c_int, vp]
+    lib.qt_get_blocks.restype = ctypes.c_int
+    lib.qt_get_blocks.argtypes = [vp, i64, vp, vp, vp, vp, ctypes.c_int, ctypes.c_int, vp]
     lib.qt_stats.restype = ctypes.c_int
     lib.qt_stats.argtypes = [vp, i64p, i32, i32p, i64p]
     lib.qt_prepare.restype = ctypes.c_int
@@ -89,7 +97,7 @@ def _load():
 
 lib = _load()
 
-EXPORTS = ("qt_build", "qt_multiply", "qt_info", "qt_to_blocks", "qt_stats", "qt_prepare", "qt_free",
+EXPORTS = ("qt_build", "qt_multiply", "qt_multiply_ex", "qt_add", "qt_sysq", "qt_info", "qt_to_blocks", "qt_get_blocks", "qt_stats", "qt_prepare", "qt_free",
            "qt_plan_create", "qt_plan_execute", "qt_plan_tune", "qt_plan_set_schedule", "qt_plan_result", "qt_plan_info",
            "qt_plan_destroy", "qt_tune_leaf", "qt_profile", "qt_profile_read", "qt_last_error", "qt_version")
 PLAN_SCHEDULES = ("flat", "persistent-1", "persistent-4", "persistent-16")
@@ -164,6 +172,26 @@ class Matrix:
         _check(lib.qt_to_blocks(self._h, I.ctypes.data, J.ctypes.data, V.ctypes.data, PREC[dtype], MEM_HOST,
                                 _stream_ptr(stream)))
         return I, J, V
+
+    def pattern(self, stream=None):
+        """Block positions (I, J) sorted row-major, without the values."""
+        n = self.info()["nblocks"]
+        I = np.empty(n, np.int32)
+        J = np.empty(n, np.int32)
+        _check(lib.qt_to_blocks(self._h, I.ctypes.data, J.ctypes.data, None, PREC["f64"], MEM_HOST,
+                                _stream_ptr(stream)))
+        return I, J
+
+    def get_blocks(self, I, J, dtype: str = "f64", stream=None):
+        """Chosen blocks (I[t], J[t]) as (values, found) numpy arrays (qt_get_blocks)."""
+        I = np.ascontiguousarray(I, np.int32)
+        J = np.ascontiguousarray(J, np.int32)
+        b = self.info()["b"]
+        V = np.empty((len(I), b, b), np.float64 if dtype == "f64" else np.float32)
+        F = np.empty(len(I), np.int32)
+        _check(lib.qt_get_blocks(self._h, len(I), I.ctypes.data, J.ctypes.data, V.ctypes.data, F.ctypes.data,
+                                 PREC[dtype], MEM_HOST, _stream_ptr(stream)))
+        return V, F.astype(bool)
 
     def to_blocks_device(self, I, J, V, dtype: str = "f64", stream=None):
         """Copy out into caller-provided torch device tensors (no host sync)."""
@@ -273,6 +301,32 @@ def tune_leaf(A: Matrix, B: Matrix, prec: str = "f64", reps: int = 3, stream=Non
     _check(lib.qt_tune_leaf(A.handle, B.handle, PREC[prec], _stream_ptr(stream), reps, ctypes.byref(best), leaves,
                             ms, 8, ctypes.byref(n)))
     return best.value, {leaves[i]: ms[i] for i in range(n.value)}
+
+
+OP_TRANS_A, OP_TRANS_B, OP_UPPER = 1, 2, 4
+
+
+def multiply_ex(A: Matrix, B: Matrix, trans_a: bool = False, trans_b: bool = False, upper: bool = False,
+                prec: str = "f64", stream=None) -> Matrix:
+    """qt_multiply_ex: C = op(A) op(B), optionally only the upper block triangle."""
+    flags = (OP_TRANS_A if trans_a else 0) | (OP_TRANS_B if trans_b else 0) | (OP_UPPER if upper else 0)
+    out = ctypes.c_void_p()
+    _check(lib.qt_multiply_ex(A.handle, B.handle, flags, PREC[prec], _stream_ptr(stream), ctypes.byref(out)))
+    return Matrix(out.value)
+
+
+def add(A: Matrix, B: Matrix, stream=None) -> Matrix:
+    """qt_add: C = A + B (union of the block patterns)."""
+    out = ctypes.c_void_p()
+    _check(lib.qt_add(A.handle, B.handle, _stream_ptr(stream), ctypes.byref(out)))
+    return Matrix(out.value)
+
+
+def sysq(A: Matrix, prec: str = "f64", stream=None) -> Matrix:
+    """qt_sysq: upper block triangle of S*S, S symmetric given by its upper block triangle A."""
+    out = ctypes.c_void_p()
+    _check(lib.qt_sysq(A.handle, PREC[prec], _stream_ptr(stream), ctypes.byref(out)))
+    return Matrix(out.value)
 
 
 def prepare(M: Matrix, prec: str, stream=None):

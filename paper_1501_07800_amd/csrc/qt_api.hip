@@ -10,10 +10,9 @@ static thread_local std::string t_last_error;
 
 void set_last_error(const std::string& m) { t_last_error = m; }
 
-qt_matrix* build(int64_t, int64_t, int32_t, int32_t, int64_t, const int32_t*, const int32_t*, const double*,
-                 qt_mem, hipStream_t);
-qt_matrix* multiply(qt_matrix*, qt_matrix*, qt_prec, hipStream_t);
 void to_blocks(const qt_matrix*, int32_t*, int32_t*, void*, qt_prec, qt_mem, hipStream_t);
+void get_blocks(const qt_matrix*, int64_t, const int32_t*, const int32_t*, void*, int32_t*, qt_prec, qt_mem,
+                hipStream_t);
 qt_plan* plan_create(int32_t, const qt_matrix* const*, const qt_matrix* const*, qt_prec, hipStream_t);
 void plan_execute(qt_plan*, hipStream_t, int);
 int plan_tune(qt_plan*, hipStream_t, int, float*);
@@ -119,6 +118,62 @@ qt_status qt_multiply(const qt_matrix* A, const qt_matrix* B, qt_prec prec, void
     QT_GUARD_END
 }
 
+qt_status qt_multiply_ex(const qt_matrix* A, const qt_matrix* B, int32_t op_flags, qt_prec prec, void* stream,
+                         qt_matrix** C) {
+    if (!C) {
+        set_last_error("NULL output handle");
+        return QT_ERR_ARG;
+    }
+    *C = nullptr;
+    if (!A || !B || (op_flags & ~(QT_OP_TRANS_A | QT_OP_TRANS_B | QT_OP_UPPER))) {
+        set_last_error("NULL operand or unknown flag");
+        return QT_ERR_ARG;
+    }
+    QT_GUARD_BEGIN
+    MulOp op;
+    op.ta = (op_flags & QT_OP_TRANS_A) ? 1 : 0;
+    op.tb = (op_flags & QT_OP_TRANS_B) ? 1 : 0;
+    op.upper = (op_flags & QT_OP_UPPER) ? 1 : 0;
+    *C = multiply(const_cast<qt_matrix*>(A), const_cast<qt_matrix*>(B), prec, (hipStream_t)stream, op);
+    return QT_OK;
+    QT_GUARD_END
+}
+
+qt_status qt_add(const qt_matrix* A, const qt_matrix* B, void* stream, qt_matrix** C) {
+    if (!C) {
+        set_last_error("NULL output handle");
+        return QT_ERR_ARG;
+    }
+    *C = nullptr;
+    if (!A || !B) {
+        set_last_error("NULL operand");
+        return QT_ERR_ARG;
+    }
+    QT_GUARD_BEGIN
+    *C = add(const_cast<qt_matrix*>(A), const_cast<qt_matrix*>(B), (hipStream_t)stream);
+    return QT_OK;
+    QT_GUARD_END
+}
+
+qt_status qt_sysq(const qt_matrix* A, qt_prec prec, void* stream, qt_matrix** C) {
+    if (!C) {
+        set_last_error("NULL output handle");
+        return QT_ERR_ARG;
+    }
+    *C = nullptr;
+    if (!A) {
+        set_last_error("NULL operand");
+        return QT_ERR_ARG;
+    }
+    QT_GUARD_BEGIN
+    qt_matrix* S = symmetric_full(const_cast<qt_matrix*>(A), (hipStream_t)stream);
+    MulOp op;
+    op.upper = 1;
+    *C = multiply(S, S, prec, (hipStream_t)stream, op);
+    return QT_OK;
+    QT_GUARD_END
+}
+
 qt_status qt_info(const qt_matrix* M, int64_t* n_rows, int64_t* n_cols, int32_t* block_size, int32_t* leaf_size,
                   int64_t* nblocks, qt_prec* value_type) {
     if (!M) {
@@ -142,6 +197,18 @@ qt_status qt_to_blocks(const qt_matrix* M, int32_t* I, int32_t* J, void* values,
     }
     QT_GUARD_BEGIN
     to_blocks(M, I, J, values, out_type, where, (hipStream_t)stream);
+    return QT_OK;
+    QT_GUARD_END
+}
+
+qt_status qt_get_blocks(const qt_matrix* M, int64_t count, const int32_t* I, const int32_t* J, void* values,
+                        int32_t* found, qt_prec out_type, qt_mem where, void* stream) {
+    if (!M) {
+        set_last_error("NULL matrix");
+        return QT_ERR_ARG;
+    }
+    QT_GUARD_BEGIN
+    get_blocks(M, count, I, J, values, found, out_type, where, (hipStream_t)stream);
     return QT_OK;
     QT_GUARD_END
 }

@@ -212,6 +212,79 @@ __global__ void k_gather_convert<double, float>(const double* __restrict__ src, 
     }
 }
 
+// One workgroup per requested block: binary search of its Morton key, then
+// a copy (or zeros when the block is not stored).
+template <class S, class D>
+__global__ void k_get_blocks(const uint64_t* __restrict__ bkey, int64_t nblocks, int64_t nbr, int64_t nbc,
+                             const S* __restrict__ vals, const int32_t* __restrict__ I,
+                             const int32_t* __restrict__ J, int64_t count, int bb, D* __restrict__ out,
+                             int32_t* __restrict__ found) {
+    __shared__ int64_t pos;
+    for (int64_t t = blockIdx.x; t < count; t += gridDim.x) {
+        if (threadIdx.x == 0) {
+            int64_t at = -1;
+            const int32_t i = I[t], j = J[t];
+            if (i >= 0 && j >= 0 && i < nbr && j < nbc) {
+                const uint64_t k = morton_key((uint32_t)i, (uint32_t)j);
+                int64_t lo = 0, hi = nblocks;           // first index with bkey >= k
+                while (lo < hi) {
+                    const int64_t mid = (lo + hi) >> 1;
+                    if (bkey[mid] < k) lo = mid + 1; else hi = mid;
+                }
+                if (lo < nblocks && bkey[lo] == k) at = lo;
+            }
+            pos = at;
+            found[t] = at >= 0 ? 1 : 0;
+        }
+        __syncthreads();
+        const int64_t at = pos;
+        D* d = out + (size_t)t * bb;
+        if (at >= 0) {
+            const S* src = vals + (size_t)at * bb;
+            for (int e = threadIdx.x; e < bb; e += blockDim.x) d[e] = (D)src[e];
+        } else {
+            for (int e = threadIdx.x; e < bb; e += blockDim.x) d[e] = (D)0;
+        }
+        __syncthreads();
+    }
+}
+
+template <>
+__global__ void k_get_blocks<double, float>(const uint64_t* __restrict__ bkey, int64_t nblocks, int64_t nbr,
+                                            int64_t nbc, const double* __restrict__ vals,
+                                            const int32_t* __restrict__ I, const int32_t* __restrict__ J,
+                                            int64_t count, int bb, float* __restrict__ out,
+                                            int32_t* __restrict__ found) {
+    __shared__ int64_t pos;
+    for (int64_t t = blockIdx.x; t < count; t += gridDim.x) {
+        if (threadIdx.x == 0) {
+            int64_t at = -1;
+            const int32_t i = I[t], j = J[t];
+            if (i >= 0 && j >= 0 && i < nbr && j < nbc) {
+                const uint64_t k = morton_key((uint32_t)i, (uint32_t)j);
+                int64_t lo = 0, hi = nblocks;
+                while (lo < hi) {
+                    const int64_t mid = (lo + hi) >> 1;
+                    if (bkey[mid] < k) lo = mid + 1; else hi = mid;
+                }
+                if (lo < nblocks && bkey[lo] == k) at = lo;
+            }
+            pos = at;
+            found[t] = at >= 0 ? 1 : 0;
+        }
+        __syncthreads();
+        const int64_t at = pos;
+        float* d = out + (size_t)t * bb;
+        if (at >= 0) {
+            const double* src = vals + (size_t)at * bb;
+            for (int e = threadIdx.x; e < bb; e += blockDim.x) d[e] = __double2float_rn(src[e]);
+        } else {
+            for (int e = threadIdx.x; e < bb; e += blockDim.x) d[e] = 0.f;
+        }
+        __syncthreads();
+    }
+}
+
 // ------------------------------------------------------------- helpers
 
 static inline unsigned grid_for(int64_t n, int T = 256) {
@@ -305,6 +378,42 @@ const float* operand_f32(qt_matrix* M, hipStream_t s) {
         QT_LAUNCH("k_f64_to_f32");
     }
     return M->v32.p;
+}
+
+// dst block t = src block t transposed
+template <class T>
+__global__ void k_transpose_blocks(const T* __restrict__ src, int64_t nblk, int b, T* __restrict__ dst) {
+    const int64_t bb = (int64_t)b * b;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nblk * bb) return;
+    const int64_t t = i / bb;
+    const int e = (int)(i - t * bb);
+    const int r = e / b, c = e - r * b;
+    dst[t * bb + (int64_t)c * b + r] = src[i];
+}
+
+const double* operand_f64_t(qt_matrix* M, hipStream_t s) {
+    const double* v = operand_f64(M, s);
+    std::lock_guard<std::mutex> lk(M->mu);
+    if (!M->v64_t.p && M->nblocks > 0) {
+        const int64_t n = M->nblocks * (int64_t)M->b * M->b;
+        M->v64_t.alloc(n, s);
+        k_transpose_blocks<double><<<grid_for(n), 256, 0, s>>>(v, M->nblocks, M->b, M->v64_t.p);
+        QT_LAUNCH("k_transpose_blocks");
+    }
+    return M->v64_t.p;
+}
+
+const float* operand_f32_t(qt_matrix* M, hipStream_t s) {
+    const float* v = operand_f32(M, s);
+    std::lock_guard<std::mutex> lk(M->mu);
+    if (!M->v32_t.p && M->nblocks > 0) {
+        const int64_t n = M->nblocks * (int64_t)M->b * M->b;
+        M->v32_t.alloc(n, s);
+        k_transpose_blocks<float><<<grid_for(n), 256, 0, s>>>(v, M->nblocks, M->b, M->v32_t.p);
+        QT_LAUNCH("k_transpose_blocks");
+    }
+    return M->v32_t.p;
 }
 
 void operand_bf16(qt_matrix* M, hipStream_t s) {
@@ -461,7 +570,7 @@ void to_blocks(const qt_matrix* M, int32_t* I, int32_t* J, void* values, qt_prec
     if (where != QT_MEM_HOST && where != QT_MEM_DEVICE) fail(QT_ERR_ARG, "bad memory kind");
     const int64_t n = M->nblocks;
     if (n == 0) return;
-    if (!I || !J || !values) fail(QT_ERR_ARG, "NULL output array");
+    if (!I || !J) fail(QT_ERR_ARG, "NULL output array");
     const int bb = M->b * M->b;
     const int64_t nbc = M->n_cols / M->b;
     int64_t npow2 = 1;
@@ -471,7 +580,7 @@ void to_blocks(const qt_matrix* M, int32_t* I, int32_t* J, void* values, qt_prec
     k_rowmajor_keys<<<grid_for(n), 256, 0, s>>>(M->bkey.p, n, nbc, rk.p, perm.p);
     QT_LAUNCH("k_rowmajor_keys");
     bitonic_sort(rk.p, perm.p, n, s);
-    const size_t vbytes = (size_t)n * bb * (out_type == QT_F64 ? sizeof(double) : sizeof(float));
+    const size_t vbytes = values ? (size_t)n * bb * (out_type == QT_F64 ? sizeof(double) : sizeof(float)) : 0;
     DBuf<int32_t> tI, tJ;
     DBuf<char> tV;
     int32_t* oI = I;
@@ -480,15 +589,17 @@ void to_blocks(const qt_matrix* M, int32_t* I, int32_t* J, void* values, qt_prec
     if (where == QT_MEM_HOST) {
         tI.alloc(n, s);
         tJ.alloc(n, s);
-        tV.alloc(vbytes, s);
+        if (values) tV.alloc(vbytes, s);
         oI = tI.p;
         oJ = tJ.p;
-        oV = tV.p;
+        oV = values ? (void*)tV.p : nullptr;
     }
     k_coords<<<grid_for(n), 256, 0, s>>>(M->bkey.p, perm.p, n, oI, oJ);
     QT_LAUNCH("k_coords");
     const unsigned g = block_grid(n);
-    if (M->vtype == QT_F64 && out_type == QT_F64)
+    if (!values) {
+        // pattern only
+    } else if (M->vtype == QT_F64 && out_type == QT_F64)
         k_gather_convert<double, double><<<g, 256, 0, s>>>(M->v64.p, perm.p, n, bb, (double*)oV);
     else if (M->vtype == QT_F64)
         k_gather_convert<double, float><<<g, 256, 0, s>>>(M->v64.p, perm.p, n, bb, (float*)oV);
@@ -496,11 +607,211 @@ void to_blocks(const qt_matrix* M, int32_t* I, int32_t* J, void* values, qt_prec
         k_gather_convert<float, double><<<g, 256, 0, s>>>(M->v32.p, perm.p, n, bb, (double*)oV);
     else
         k_gather_convert<float, float><<<g, 256, 0, s>>>(M->v32.p, perm.p, n, bb, (float*)oV);
-    QT_LAUNCH("k_gather_convert");
+    if (values) QT_LAUNCH("k_gather_convert");
     if (where == QT_MEM_HOST) {
         QT_HIP(hipMemcpyAsync(I, oI, n * sizeof(int32_t), hipMemcpyDeviceToHost, s));
         QT_HIP(hipMemcpyAsync(J, oJ, n * sizeof(int32_t), hipMemcpyDeviceToHost, s));
-        QT_HIP(hipMemcpyAsync(values, oV, vbytes, hipMemcpyDeviceToHost, s));
+        if (values) QT_HIP(hipMemcpyAsync(values, oV, vbytes, hipMemcpyDeviceToHost, s));
+        QT_HIP(hipStreamSynchronize(s));
+    }
+}
+
+// Blocks of the full symmetric matrix from an upper block triangle: block t
+// (I <= J) goes to slot t, and its mirror (J, I) = block^T to slot
+// nblocks + rank among the strictly upper blocks.
+__global__ void k_mirror_flags(const uint64_t* __restrict__ bkey, int64_t n, int32_t* __restrict__ upper,
+                               int32_t* __restrict__ err) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n) return;
+    const uint32_t i = morton_row(bkey[t]), j = morton_col(bkey[t]);
+    upper[t] = i < j ? 1 : 0;
+    if (i > j) atomicOr(err, 1);
+}
+
+__global__ void k_mirror_fill(const uint64_t* __restrict__ bkey, const double* __restrict__ v, int64_t n, int b,
+                              const int32_t* __restrict__ upper, const int32_t* __restrict__ rank,
+                              int32_t* __restrict__ I, int32_t* __restrict__ J, double* __restrict__ V) {
+    const int64_t bb = (int64_t)b * b;
+    for (int64_t t = blockIdx.x; t < n; t += gridDim.x) {
+        const int32_t i = (int32_t)morton_row(bkey[t]), j = (int32_t)morton_col(bkey[t]);
+        const double* src = v + t * bb;
+        if (threadIdx.x == 0) {
+            I[t] = i;
+            J[t] = j;
+        }
+        for (int e = threadIdx.x; e < bb; e += blockDim.x) V[t * bb + e] = src[e];
+        if (upper[t]) {
+            const int64_t m = n + rank[t];
+            if (threadIdx.x == 0) {
+                I[m] = j;
+                J[m] = i;
+            }
+            for (int e = threadIdx.x; e < bb; e += blockDim.x) {
+                const int r = e / b, c = e - r * b;
+                V[m * bb + (int64_t)c * b + r] = src[e];
+            }
+        }
+    }
+}
+
+qt_matrix* symmetric_full(qt_matrix* A, hipStream_t s) {
+    std::lock_guard<std::mutex> lk(A->mu);
+    if (A->sym_full) return A->sym_full.get();
+    if (A->n_rows != A->n_cols) fail(QT_ERR_SHAPE, "a symmetric matrix must be square");
+    const int64_t n = A->nblocks;
+    const int bb = A->b * A->b;
+    if (n == 0) {
+        A->sym_full.reset(build(A->n_rows, A->n_cols, A->b, A->leaf, 0, nullptr, nullptr, nullptr, QT_MEM_DEVICE, s));
+        return A->sym_full.get();
+    }
+    if (A->vtype != QT_F64) fail(QT_ERR_UNSUPPORTED, "symmetric square of an fp32 matrix");
+    DBuf<int32_t> up(n, s), rank(n + 1, s), tmp(scan_tmp_elems(n) + 1, s), err(1, s);
+    QT_HIP(hipMemsetAsync(err.p, 0, sizeof(int32_t), s));
+    k_mirror_flags<<<grid_for(n), 256, 0, s>>>(A->bkey.p, n, up.p, err.p);
+    QT_LAUNCH("k_mirror_flags");
+    exclusive_scan(up.p, rank.p, n, tmp.p, s);
+    int32_t h[2] = {0, 0};
+    QT_HIP(hipMemcpyAsync(&h[0], rank.p + n, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    QT_HIP(hipMemcpyAsync(&h[1], err.p, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    QT_HIP(hipStreamSynchronize(s));
+    if (h[1]) fail(QT_ERR_ARG, "upper-triangular storage holds a block below the diagonal");
+    const int64_t total = n + h[0];
+    DBuf<int32_t> I(total, s), J(total, s);
+    DBuf<double> V((size_t)total * bb, s);
+    k_mirror_fill<<<block_grid(n), 256, 0, s>>>(A->bkey.p, A->v64.p, n, A->b, up.p, rank.p, I.p, J.p, V.p);
+    QT_LAUNCH("k_mirror_fill");
+    A->sym_full.reset(build(A->n_rows, A->n_cols, A->b, A->leaf, total, I.p, J.p, V.p, QT_MEM_DEVICE, s));
+    return A->sym_full.get();
+}
+
+// ------------------------------------------------------------- C = A + B
+
+__global__ void k_iota(int32_t* p, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = (int32_t)i;
+}
+
+__global__ void k_key_flags(const uint64_t* __restrict__ keys, int64_t n, int32_t* __restrict__ flags) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n) flags[t] = (t == 0 || keys[t] != keys[t - 1]) ? 1 : 0;
+}
+
+// Sorted keys of A's and B's blocks (source s < na: A block s, else B block
+// s - na): the first entry of every key writes the output block, adding the
+// second entry when both matrices hold the block.
+__global__ void k_add_blocks(const uint64_t* __restrict__ keys, const int32_t* __restrict__ src, int64_t n,
+                             const int32_t* __restrict__ flags, const int32_t* __restrict__ ex, int64_t na,
+                             const double* __restrict__ va, const double* __restrict__ vb, int bb,
+                             uint64_t* __restrict__ ckey, double* __restrict__ vc) {
+    for (int64_t t = blockIdx.x; t < n; t += gridDim.x) {
+        if (!flags[t]) continue;
+        const int64_t o = ex[t];
+        const int32_t s0 = src[t];
+        const double* x = (s0 < na) ? va + (size_t)s0 * bb : vb + (size_t)(s0 - na) * bb;
+        const bool two = (t + 1 < n) && keys[t + 1] == keys[t];
+        const double* y = nullptr;
+        if (two) {
+            const int32_t s1 = src[t + 1];
+            y = (s1 < na) ? va + (size_t)s1 * bb : vb + (size_t)(s1 - na) * bb;
+        }
+        if (threadIdx.x == 0) ckey[o] = keys[t];
+        for (int e = threadIdx.x; e < bb; e += blockDim.x) vc[(size_t)o * bb + e] = two ? x[e] + y[e] : x[e];
+    }
+}
+
+qt_matrix* add(qt_matrix* A, qt_matrix* B, hipStream_t s) {
+    if (A->b != B->b || A->leaf != B->leaf) fail(QT_ERR_SHAPE, "operands differ in block or leaf size");
+    if (A->n_rows != B->n_rows || A->n_cols != B->n_cols) fail(QT_ERR_SHAPE, "operands differ in dimensions");
+    const double* va = operand_f64(A, s);
+    const double* vb = operand_f64(B, s);
+    const int64_t na = A->nblocks, nb = B->nblocks, n = na + nb;
+    if (n > (int64_t(1) << 31) - 2) fail(QT_ERR_UNSUPPORTED, "too many blocks");
+    if (n == 0) return build(A->n_rows, A->n_cols, A->b, A->leaf, 0, nullptr, nullptr, nullptr, QT_MEM_DEVICE, s);
+    const int bb = A->b * A->b;
+    int64_t npow2 = 1;
+    while (npow2 < n) npow2 <<= 1;
+    DBuf<uint64_t> keys(npow2, s);
+    DBuf<int32_t> src(npow2, s);
+    if (na) QT_HIP(hipMemcpyAsync(keys.p, A->bkey.p, na * sizeof(uint64_t), hipMemcpyDeviceToDevice, s));
+    if (nb) QT_HIP(hipMemcpyAsync(keys.p + na, B->bkey.p, nb * sizeof(uint64_t), hipMemcpyDeviceToDevice, s));
+    k_iota<<<grid_for(n), 256, 0, s>>>(src.p, n);
+    QT_LAUNCH("k_iota");
+    bitonic_sort(keys.p, src.p, n, s);
+    DBuf<int32_t> flags(n, s), ex(n + 1, s), tmp(scan_tmp_elems(n) + 1, s);
+    k_key_flags<<<grid_for(n), 256, 0, s>>>(keys.p, n, flags.p);
+    QT_LAUNCH("k_key_flags");
+    exclusive_scan(flags.p, ex.p, n, tmp.p, s);
+    const int32_t nc = read_scalar(ex.p + n, s);
+
+    std::unique_ptr<qt_matrix> C(new qt_matrix);
+    C->n_rows = A->n_rows;
+    C->n_cols = A->n_cols;
+    C->b = A->b;
+    C->leaf = A->leaf;
+    C->lb = A->lb;
+    C->lb_log = A->lb_log;
+    C->L = std::max(A->L, B->L);
+    C->vtype = QT_F64;
+    C->nblocks = nc;
+    C->stream = s;
+    QT_HIP(hipGetDevice(&C->device));
+    C->levels.resize(C->L);
+    C->bkey.alloc(nc, s);
+    C->v64.alloc((size_t)nc * bb, s);
+    k_add_blocks<<<block_grid(n), 256, 0, s>>>(keys.p, src.p, n, flags.p, ex.p, na, va, vb, bb, C->bkey.p, C->v64.p);
+    QT_LAUNCH("k_add_blocks");
+    build_tree_levels(C.get(), s);
+    build_histograms(C.get(), s);
+    QT_HIP(hipStreamSynchronize(s));
+    return C.release();
+}
+
+void get_blocks(const qt_matrix* M, int64_t count, const int32_t* I, const int32_t* J, void* values,
+                int32_t* found, qt_prec out_type, qt_mem where, hipStream_t s) {
+    if (out_type != QT_F64 && out_type != QT_F32) fail(QT_ERR_UNSUPPORTED, "output type must be F64 or F32");
+    if (where != QT_MEM_HOST && where != QT_MEM_DEVICE) fail(QT_ERR_ARG, "bad memory kind");
+    if (count < 0) fail(QT_ERR_ARG, "negative count");
+    if (count == 0) return;
+    if (!I || !J || !values || !found) fail(QT_ERR_ARG, "NULL array");
+    const int bb = M->b * M->b;
+    const size_t esz = out_type == QT_F64 ? sizeof(double) : sizeof(float);
+    DBuf<int32_t> dI, dJ, dF;
+    DBuf<char> dV;
+    const int32_t* pI = I;
+    const int32_t* pJ = J;
+    int32_t* pF = found;
+    void* pV = values;
+    if (where == QT_MEM_HOST) {
+        dI.alloc(count, s);
+        dJ.alloc(count, s);
+        dF.alloc(count, s);
+        dV.alloc((size_t)count * bb * esz, s);
+        QT_HIP(hipMemcpyAsync(dI.p, I, count * sizeof(int32_t), hipMemcpyHostToDevice, s));
+        QT_HIP(hipMemcpyAsync(dJ.p, J, count * sizeof(int32_t), hipMemcpyHostToDevice, s));
+        pI = dI.p;
+        pJ = dJ.p;
+        pF = dF.p;
+        pV = dV.p;
+    }
+    const int64_t nbr = M->n_rows / M->b, nbc = M->n_cols / M->b;
+    const unsigned g = block_grid(count);
+    const bool src64 = M->vtype == QT_F64;
+    if (src64 && out_type == QT_F64)
+        k_get_blocks<double, double><<<g, 256, 0, s>>>(M->bkey.p, M->nblocks, nbr, nbc, M->v64.p, pI, pJ, count, bb,
+                                                      (double*)pV, pF);
+    else if (src64)
+        k_get_blocks<double, float><<<g, 256, 0, s>>>(M->bkey.p, M->nblocks, nbr, nbc, M->v64.p, pI, pJ, count, bb,
+                                                     (float*)pV, pF);
+    else if (out_type == QT_F64)
+        k_get_blocks<float, double><<<g, 256, 0, s>>>(M->bkey.p, M->nblocks, nbr, nbc, M->v32.p, pI, pJ, count, bb,
+                                                     (double*)pV, pF);
+    else
+        k_get_blocks<float, float><<<g, 256, 0, s>>>(M->bkey.p, M->nblocks, nbr, nbc, M->v32.p, pI, pJ, count, bb,
+                                                    (float*)pV, pF);
+    QT_LAUNCH("k_get_blocks");
+    if (where == QT_MEM_HOST) {
+        QT_HIP(hipMemcpyAsync(found, pF, count * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        QT_HIP(hipMemcpyAsync(values, pV, (size_t)count * bb * esz, hipMemcpyDeviceToHost, s));
         QT_HIP(hipStreamSynchronize(s));
     }
 }

@@ -144,6 +144,9 @@ struct qt_matrix {
     qt::DBuf<uint16_t> bf_hi, bf_lo;     // bf16 split, row-major per block
     qt::DBuf<uint16_t> bf_hi_t, bf_lo_t; // same, each block transposed
     qt::DBuf<double> v64_cache;          // fp64 copy when vtype == QT_F32
+    std::unique_ptr<qt_matrix> sym_full; // full symmetric matrix from this upper triangle
+    qt::DBuf<double> v64_t;              // fp64 values, every block transposed
+    qt::DBuf<float> v32_t;               // fp32 values, every block transposed
     qt::Histograms hist;
 
     // counters of the multiply that produced this matrix
@@ -181,6 +184,8 @@ void bitonic_sort(uint64_t* keys, int32_t* vals, int64_t n, hipStream_t s);
 void build_histograms(qt_matrix* M, hipStream_t s);   // fills M->hist (synchronizes)
 const double* operand_f64(qt_matrix* M, hipStream_t s);
 const float* operand_f32(qt_matrix* M, hipStream_t s);
+const double* operand_f64_t(qt_matrix* M, hipStream_t s);   // every block transposed
+const float* operand_f32_t(qt_matrix* M, hipStream_t s);
 void operand_bf16(qt_matrix* M, hipStream_t s);
 uint64_t morton2(uint32_t r, uint32_t c);
 
@@ -239,7 +244,18 @@ struct SymbolicOut {
     PhaseEvents ev{};
     bool prof = false;
 };
+// Which product: op(A) op(B), op(X) = X or X^T, optionally only the blocks
+// of C on or above the block diagonal.
+struct MulOp {
+    int ta = 0, tb = 0, upper = 0;
+};
 void symbolic(qt_matrix* A, qt_matrix* B, qt_prec prec, hipStream_t s, SymbolicOut& out,
-              bool allow_profile = true);
+              bool allow_profile = true, const MulOp& op = MulOp{});
+qt_matrix* multiply(qt_matrix* A, qt_matrix* B, qt_prec prec, hipStream_t s, const MulOp& op = MulOp{});
+qt_matrix* build(int64_t n_rows, int64_t n_cols, int32_t b, int32_t leaf, int64_t nblocks, const int32_t* I,
+                 const int32_t* J, const double* values, qt_mem where, hipStream_t s);
+qt_matrix* add(qt_matrix* A, qt_matrix* B, hipStream_t s);
+// The full symmetric matrix whose upper block triangle is A (cached in A).
+qt_matrix* symmetric_full(qt_matrix* A, hipStream_t s);
 
 }  // namespace qt

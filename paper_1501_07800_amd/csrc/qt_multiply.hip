@@ -105,9 +105,30 @@ struct TreeStep {
     uint64_t* nckey;
     int32_t* cchild;          // C's child table at this level (4 per node)
     int32_t* ncount_next;
-    int32_t np_next;          // pairs at the next level (known exactly)
+    int32_t np_next;          // bound on pairs at the next level (exact unless `upper`)
     int32_t* check;           // device total of child pairs, for the host check
+    int ta, tb;               // operand used transposed: child (m, k) of op(A) is child (k, m) of A
+    int upper;                // keep only C nodes on or above the block diagonal
 };
+
+// Children of an operand node in the orientation of op(X): for a transposed
+// operand the off-diagonal children swap (quadrant (m, k) of X^T is (k, m) of X).
+__device__ __forceinline__ int4 op_children(const int32_t* tab, int32_t node, int transposed) {
+    int4 c = *reinterpret_cast<const int4*>(tab + 4 * (int64_t)node);
+    if (transposed) {
+        const int t = c.y;
+        c.y = c.z;
+        c.z = t;
+    }
+    return c;
+}
+
+// Quadrant mn of C node `key` is dropped when only the upper triangle is
+// wanted and the node lies on the diagonal (its lower-left child is strictly
+// below it); nodes off the diagonal are entirely above it.
+__device__ __forceinline__ bool quadrant_dropped(int upper, uint64_t key, int mn) {
+    return upper && mn == 2 && morton_row(key) == morton_col(key);
+}
 
 __device__ void tree_count_node(const TreeStep& st, int32_t c, int lane) {
     if (c >= *st.ncount) {
@@ -119,14 +140,15 @@ __device__ void tree_count_node(const TreeStep& st, int32_t c, int lane) {
     for (int32_t base = 0; base < len; base += 64) {
         if (base + lane < len) {
             const int32_t p = s0 + base + lane;
-            const int4 a = load_children(st.Ach, st.fa[p]);   // A child (m, k) at 2m + k
-            const int4 b = load_children(st.Bch, st.fb[p]);   // B child (k, n) at 2k + n
+            const int4 a = op_children(st.Ach, st.fa[p], st.ta);   // A child (m, k) at 2m + k
+            const int4 b = op_children(st.Bch, st.fb[p], st.tb);   // B child (k, n) at 2k + n
             t0 += (a.x >= 0 && b.x >= 0) + (a.y >= 0 && b.z >= 0);
             t1 += (a.x >= 0 && b.y >= 0) + (a.y >= 0 && b.w >= 0);
             t2 += (a.z >= 0 && b.x >= 0) + (a.w >= 0 && b.z >= 0);
             t3 += (a.z >= 0 && b.y >= 0) + (a.w >= 0 && b.w >= 0);
         }
     }
+    if (quadrant_dropped(st.upper, st.ckey[c], 2)) t2 = 0;
     t0 = wave_sum(t0);
     t1 = wave_sum(t1);
     t2 = wave_sum(t2);
@@ -142,7 +164,7 @@ __device__ void tree_fill_node(const TreeStep& st, int32_t c, int lane) {
         const int64_t T = st.off[st.ncap];
         const int32_t nc_next = hi32(T);
         *st.ncount_next = nc_next;
-        if (nc_next <= st.np_next) st.ncseg[nc_next] = st.np_next;
+        if (nc_next <= st.np_next) st.ncseg[nc_next] = lo32(T);
         *st.check = lo32(T);
     }
     if (c >= *st.ncount) return;
@@ -173,21 +195,23 @@ __device__ void tree_fill_node(const TreeStep& st, int32_t c, int lane) {
     }
     const int32_t s0 = st.cseg[c], len = st.cseg[c + 1] - s0;
     const uint64_t below = lanes_below(lane);
+    const bool drop_lower = quadrant_dropped(st.upper, st.ckey[c], 2);
     for (int32_t base = 0; base < len; base += 64) {
         const bool act = base + lane < len;
         int4 a = make_int4(-1, -1, -1, -1), b = make_int4(-1, -1, -1, -1);
         if (act) {
             const int32_t p = s0 + base + lane;
-            a = load_children(st.Ach, st.fa[p]);
-            b = load_children(st.Bch, st.fb[p]);
+            a = op_children(st.Ach, st.fa[p], st.ta);
+            b = op_children(st.Bch, st.fb[p], st.tb);
         }
         const int av[4] = {a.x, a.y, a.z, a.w};
         const int bv[4] = {b.x, b.y, b.z, b.w};
 #pragma unroll
         for (int mn = 0; mn < 4; ++mn) {
             const int m = mn >> 1, n = mn & 1;
-            const bool e0 = av[2 * m] >= 0 && bv[n] >= 0;           // k' = 0
-            const bool e1 = av[2 * m + 1] >= 0 && bv[2 + n] >= 0;   // k' = 1
+            const bool keep = !(mn == 2 && drop_lower);
+            const bool e0 = keep && av[2 * m] >= 0 && bv[n] >= 0;           // k' = 0
+            const bool e1 = keep && av[2 * m + 1] >= 0 && bv[2 + n] >= 0;   // k' = 1
             const uint64_t m0 = __ballot(e0), m1 = __ballot(e1);
             int out = run[mn] + __popcll(m0 & below) + __popcll(m1 & below);
             if (e0) {
@@ -325,7 +349,15 @@ struct LeafStep {
     uint64_t* lcm;
     int32_t* nblocks_out;
     int32_t* check;
+    int ta, tb;               // op(A) = A^T / op(B) = B^T (masks already swapped by the host)
+    int upper;                // keep only blocks on or above the diagonal
 };
+
+// Block q of a C leaf is kept unless only the upper triangle is wanted and
+// it lies below the diagonal of a diagonal leaf.
+__device__ __forceinline__ bool leaf_block_kept(const LeafStep& st, uint64_t leafkey, int i, int j) {
+    return !(st.upper && i > j && morton_row(leafkey) == morton_col(leafkey));
+}
 
 // Lane q (a block of the C leaf, local Morton index) counts its products.
 __device__ int leaf_lane_count(const LeafStep& st, int32_t s0, int32_t len, int lane, int i, int j, int lb,
@@ -353,8 +385,8 @@ __device__ void leaf_count_node(const LeafStep& st, int32_t c, int lane) {
         return;
     }
     const int lb = 1 << st.lb_log;
-    const bool on = lane < lb * lb;
     const int i = (int)morton_row((uint64_t)lane), j = (int)morton_col((uint64_t)lane);
+    const bool on = lane < lb * lb && leaf_block_kept(st, st.ckey[c], i, j);
     const int32_t s0 = st.cseg[c], len = st.cseg[c + 1] - s0;
     const int cnt = leaf_lane_count(st, s0, len, lane, i, j, lb, on);
     const uint64_t em = __ballot(cnt > 0);
@@ -372,8 +404,8 @@ __device__ void leaf_fill_node(const LeafStep& st, int32_t c, int lane) {
     }
     if (c >= *st.ncount) return;
     const int lb = 1 << st.lb_log;
-    const bool on = lane < lb * lb;
     const int i = (int)morton_row((uint64_t)lane), j = (int)morton_col((uint64_t)lane);
+    const bool on = lane < lb * lb && leaf_block_kept(st, st.ckey[c], i, j);
     const int32_t s0 = st.cseg[c], len = st.cseg[c + 1] - s0;
     const int cnt = leaf_lane_count(st, s0, len, lane, i, j, lb, on);
     const int64_t o = st.off[c];
@@ -409,8 +441,11 @@ __device__ void leaf_fill_node(const LeafStep& st, int32_t c, int lane) {
             while (m) {
                 const int k = __ffs(m) - 1;
                 m &= m - 1;
-                const uint32_t qa = (uint32_t)morton_key((uint32_t)i, (uint32_t)k);
-                const uint32_t qb = (uint32_t)morton_key((uint32_t)k, (uint32_t)j);
+                // local Morton position of A(i,k) / B(k,j) in the stored (untransposed) leaf
+                const uint32_t qa = st.ta ? (uint32_t)morton_key((uint32_t)k, (uint32_t)i)
+                                          : (uint32_t)morton_key((uint32_t)i, (uint32_t)k);
+                const uint32_t qb = st.tb ? (uint32_t)morton_key((uint32_t)j, (uint32_t)k)
+                                          : (uint32_t)morton_key((uint32_t)k, (uint32_t)j);
                 if (out < st.P) {
                     st.prodA[out] = abt + __popcll(amot & ((1ull << qa) - 1));
                     st.prodB[out] = bbt + __popcll(bmot & ((1ull << qb) - 1));
@@ -479,10 +514,11 @@ static int64_t dot_counts(const std::vector<int32_t>& a, const std::vector<int32
 
 static const int64_t kMaxI32 = (int64_t(1) << 31) - 2;
 
-static qt_matrix* new_result(const qt_matrix* A, const qt_matrix* B, int L, qt_prec prec, hipStream_t s) {
+static qt_matrix* new_result(const qt_matrix* A, const qt_matrix* B, int L, qt_prec prec, hipStream_t s,
+                             const MulOp& op) {
     std::unique_ptr<qt_matrix> C(new qt_matrix);
-    C->n_rows = A->n_rows;
-    C->n_cols = B->n_cols;
+    C->n_rows = op.ta ? A->n_cols : A->n_rows;
+    C->n_cols = op.tb ? B->n_rows : B->n_cols;
     C->b = A->b;
     C->leaf = A->leaf;
     C->lb = A->lb;
@@ -496,8 +532,9 @@ static qt_matrix* new_result(const qt_matrix* A, const qt_matrix* B, int L, qt_p
     return C.release();
 }
 
-static qt_matrix* empty_result(const qt_matrix* A, const qt_matrix* B, int L, qt_prec prec, hipStream_t s) {
-    qt_matrix* C = new_result(A, B, L, prec, s);
+static qt_matrix* empty_result(const qt_matrix* A, const qt_matrix* B, int L, qt_prec prec, hipStream_t s,
+                               const MulOp& op) {
+    qt_matrix* C = new_result(A, B, L, prec, s, op);
     C->pairs.assign(L + 1, 0);
     C->hist.ready = true;
     C->hist.rowcnt.resize(L + 1);
@@ -514,59 +551,70 @@ static qt_matrix* empty_result(const qt_matrix* A, const qt_matrix* B, int L, qt
 // Symbolic phase of C = A*B: C's tree, block keys and (uninitialised) value
 // array, plus the product lists the numeric phase reads (kept in
 // out.scratch). Synchronizes once. out.na.nseg == 0 means C has no blocks.
-void symbolic(qt_matrix* A, qt_matrix* B, qt_prec prec, hipStream_t s, SymbolicOut& out, bool allow_profile) {
+void symbolic(qt_matrix* A, qt_matrix* B, qt_prec prec, hipStream_t s, SymbolicOut& out, bool allow_profile,
+              const MulOp& op) {
     if (prec != QT_F64 && prec != QT_F32 && prec != QT_BF16X3) fail(QT_ERR_ARG, "unknown precision");
     if (A->b != B->b || A->leaf != B->leaf) fail(QT_ERR_SHAPE, "operands differ in block or leaf size");
-    if (A->n_cols != B->n_rows) fail(QT_ERR_SHAPE, "inner dimensions differ");
+    const int64_t a_cols = op.ta ? A->n_rows : A->n_cols;   // op(A) = A or A^T
+    const int64_t b_rows = op.tb ? B->n_cols : B->n_rows;
+    if (a_cols != b_rows) fail(QT_ERR_SHAPE, "inner dimensions differ");
+    if (op.upper && (op.ta ? A->n_cols : A->n_rows) != (op.tb ? B->n_rows : B->n_cols))
+        fail(QT_ERR_SHAPE, "an upper-triangular product must be square");
     if (prec == QT_BF16X3 && A->b == 16) fail(QT_ERR_UNSUPPORTED, "split-bf16 path needs b = 32 or 64");
     const int L = std::max(A->L, B->L);
     const int liftA = L - A->L, liftB = L - B->L;
     out.na = NumericArgs{};
     out.prof = false;
     if (A->nblocks == 0 || B->nblocks == 0) {
-        out.C.reset(empty_result(A, B, L, prec, s));
+        out.C.reset(empty_result(A, B, L, prec, s, op));
         return;
     }
 
     build_histograms(A, s);
     build_histograms(B, s);
 
-    // exact pair counts per level and block products
+    // pair counts per level and block products: exact, or upper bounds when
+    // only the upper triangle of C is formed. Columns of op(A) are rows of A
+    // when A is used transposed, and likewise for B.
+    const auto& a_col = op.ta ? A->hist.rowcnt : A->hist.colcnt;
+    const auto& b_row = op.tb ? B->hist.colcnt : B->hist.rowcnt;
     std::vector<int64_t> pairs(L + 1);
     for (int l = 0; l <= L; ++l) {
-        const auto& ca = (l < liftA) ? unit_hist() : A->hist.colcnt[l - liftA];
-        const auto& rb = (l < liftB) ? unit_hist() : B->hist.rowcnt[l - liftB];
+        const auto& ca = (l < liftA) ? unit_hist() : a_col[l - liftA];
+        const auto& rb = (l < liftB) ? unit_hist() : b_row[l - liftB];
         pairs[l] = dot_counts(ca, rb);
     }
-    const int64_t P = dot_counts(A->hist.blk_col, B->hist.blk_row);
+    const int64_t P = dot_counts(op.ta ? A->hist.blk_row : A->hist.blk_col,
+                                 op.tb ? B->hist.blk_col : B->hist.blk_row);
     const int lb_log = A->lb_log;
     const int64_t lb2 = int64_t(1) << (2 * lb_log);
     for (int l = 0; l <= L; ++l)
         if (4 * pairs[l] > kMaxI32) fail(QT_ERR_UNSUPPORTED, "too many node pairs at one level");
     if (P > kMaxI32) fail(QT_ERR_UNSUPPORTED, "too many block products");
     if (P == 0) {
-        out.C.reset(empty_result(A, B, L, prec, s));
+        out.C.reset(empty_result(A, B, L, prec, s, op));
         out.C->pairs = pairs;
         return;
     }
 
-    // operand forms for this precision
+    // operand forms for this precision; a transposed operand reads a copy of
+    // its values with every block transposed (same block order)
     NumericArgs na{};
     na.b = A->b;
     na.prec = prec;
     if (prec == QT_F64) {
-        na.A = operand_f64(A, s);
-        na.B = operand_f64(B, s);
+        na.A = op.ta ? operand_f64_t(A, s) : operand_f64(A, s);
+        na.B = op.tb ? operand_f64_t(B, s) : operand_f64(B, s);
     } else if (prec == QT_F32) {
-        na.A = operand_f32(A, s);
-        na.B = operand_f32(B, s);
+        na.A = op.ta ? operand_f32_t(A, s) : operand_f32(A, s);
+        na.B = op.tb ? operand_f32_t(B, s) : operand_f32(B, s);
     } else {
         operand_bf16(A, s);
         operand_bf16(B, s);
-        na.Ahi = A->bf_hi.p;
-        na.Alo = A->bf_lo.p;
-        na.Bhi_t = B->bf_hi_t.p;
-        na.Blo_t = B->bf_lo_t.p;
+        na.Ahi = op.ta ? A->bf_hi_t.p : A->bf_hi.p;
+        na.Alo = op.ta ? A->bf_lo_t.p : A->bf_lo.p;
+        na.Bhi_t = op.tb ? B->bf_hi.p : B->bf_hi_t.p;
+        na.Blo_t = op.tb ? B->bf_lo.p : B->bf_lo_t.p;
     }
 
     // ---- plan the two allocations
@@ -597,7 +645,7 @@ void symbolic(qt_matrix* A, qt_matrix* B, qt_prec prec, hipStream_t s, SymbolicO
     const size_t o_cbseg = tmp.take((cap + 1) * sizeof(int32_t));
     const size_t o_count = tmp.take((2 * L + 4) * sizeof(int32_t));
 
-    out.C.reset(new_result(A, B, L, prec, s));
+    out.C.reset(new_result(A, B, L, prec, s, op));
     qt_matrix* C = out.C.get();
     C->pairs = pairs;
     C->products = P;
@@ -639,6 +687,9 @@ void symbolic(qt_matrix* A, qt_matrix* B, qt_prec prec, hipStream_t s, SymbolicO
         st.ncount_next = dcount + l + 1;
         st.np_next = (int32_t)pairs[l + 1];
         st.check = dcount + L + 2 + l;
+        st.ta = op.ta;
+        st.tb = op.tb;
+        st.upper = op.upper;
         return st;
     };
     RootInit root{(int32_t*)at(W, o_fa[0]), (int32_t*)at(W, o_fb[0]), (int32_t*)at(W, o_cseg[0]),
@@ -678,8 +729,12 @@ void symbolic(qt_matrix* A, qt_matrix* B, qt_prec prec, hipStream_t s, SymbolicO
     ls.ncount = dcount + L;
     ls.ncap = (int32_t)pairs[L];
     ls.lb_log = lb_log;
-    ls.Arm = A->leaves.mask_rm.p;
-    ls.Bcm = B->leaves.mask_cm.p;
+    // rows of op(A) are columns of A when transposed; columns of op(B) rows of B
+    ls.Arm = op.ta ? A->leaves.mask_cm.p : A->leaves.mask_rm.p;
+    ls.Bcm = op.tb ? B->leaves.mask_rm.p : B->leaves.mask_cm.p;
+    ls.ta = op.ta;
+    ls.tb = op.tb;
+    ls.upper = op.upper;
     ls.Amo = A->leaves.mask_mo.p;
     ls.Bmo = B->leaves.mask_mo.p;
     ls.Abase = A->leaves.base.p;
@@ -711,10 +766,13 @@ void symbolic(qt_matrix* A, qt_matrix* B, qt_prec prec, hipStream_t s, SymbolicO
     QT_HIP(hipStreamSynchronize(s));
     for (int l = 0; l <= L; ++l) {
         const int64_t expect = (l < L) ? pairs[l + 1] : P;
-        if (hc[L + 2 + l] != expect) fail(QT_ERR_DEVICE, "symbolic phase: pair count mismatch");
+        const bool bad = op.upper ? (hc[L + 2 + l] < 0 || hc[L + 2 + l] > expect) : (hc[L + 2 + l] != expect);
+        if (bad) fail(QT_ERR_DEVICE, "symbolic phase: pair count mismatch");
+        if (l < L) C->pairs[l + 1] = hc[L + 2 + l];   // pairs actually formed
     }
+    C->products = hc[2 * L + 2];
     const int32_t nnzC = hc[L + 1];
-    if (nnzC <= 0 || nnzC > cap) fail(QT_ERR_DEVICE, "symbolic phase: C block count out of range");
+    if (nnzC < 0 || nnzC > cap || (nnzC == 0 && !op.upper)) fail(QT_ERR_DEVICE, "symbolic phase: C block count out of range");
 
     // C's tree: views into its arena
     for (int l = 0; l < L; ++l) {
@@ -743,13 +801,13 @@ void symbolic(qt_matrix* A, qt_matrix* B, qt_prec prec, hipStream_t s, SymbolicO
     na.nseg = nnzC;
     na.C = (prec == QT_F32) ? (void*)C->v32.p : (void*)C->v64.p;
     out.na = na;
-    ev.products = P;
+    ev.products = C->products;
     ev.cblocks = nnzC;
 }
 
-qt_matrix* multiply(qt_matrix* A, qt_matrix* B, qt_prec prec, hipStream_t s) {
+qt_matrix* multiply(qt_matrix* A, qt_matrix* B, qt_prec prec, hipStream_t s, const MulOp& op) {
     SymbolicOut sym;
-    symbolic(A, B, prec, s, sym);
+    symbolic(A, B, prec, s, sym, true, op);
     if (sym.na.nseg > 0) launch_numeric(sym.na, s);
     if (sym.prof) {
         QT_HIP(hipEventRecord(sym.ev.e2, s));

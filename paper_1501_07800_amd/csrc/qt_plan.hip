@@ -190,9 +190,6 @@ int plan_tune(qt_plan* plan, hipStream_t s, int reps, float* ms_out) {
 
 // ------------------------------------------------------------ leaf tuner
 
-qt_matrix* build(int64_t, int64_t, int32_t, int32_t, int64_t, const int32_t*, const int32_t*, const double*,
-                 qt_mem, hipStream_t);
-qt_matrix* multiply(qt_matrix*, qt_matrix*, qt_prec, hipStream_t);
 void to_blocks(const qt_matrix*, int32_t*, int32_t*, void*, qt_prec, qt_mem, hipStream_t);
 
 static qt_matrix* rebuild(const qt_matrix* M, int32_t leaf, hipStream_t s) {

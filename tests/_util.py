@@ -74,3 +74,23 @@ def compare(C_ref: BlockMatrix, C: BlockMatrix, absAB: BlockMatrix | None = None
             r = np.where(den > 0, num / np.where(den > 0, den, 1.0), np.where(num > 0, np.inf, 0.0))
         e_cw = float(r.max())
     return True, e_max, e_f, e_cw
+
+
+def transpose(M: BlockMatrix) -> BlockMatrix:
+    """M^T by definition: block (I, J) -> (J, I), each block transposed."""
+    return make(M.n_cols, M.n_rows, M.b, M.J, M.I, np.ascontiguousarray(M.V.transpose(0, 2, 1)))
+
+
+def upper_blocks(M: BlockMatrix) -> BlockMatrix:
+    """The blocks of M with I <= J."""
+    k = M.I <= M.J
+    return BlockMatrix(M.n_rows, M.n_cols, M.b, M.I[k], M.J[k], np.ascontiguousarray(M.V[k]))
+
+
+def symmetric_from_upper(U: BlockMatrix) -> BlockMatrix:
+    """S with S(I,J) = U(I,J) for I <= J and S(J,I) = U(I,J)^T for I < J."""
+    k = U.I < U.J
+    I = np.concatenate([U.I, U.J[k]])
+    J = np.concatenate([U.J, U.I[k]])
+    V = np.concatenate([U.V, U.V[k].transpose(0, 2, 1)])
+    return make(U.n_rows, U.n_cols, U.b, I, J, V)

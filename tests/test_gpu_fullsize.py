@@ -1,0 +1,141 @@
+"""GPU parity at the benchmark workloads' full sizes, in the benchmark's launch
+configuration (same leaf sizes, same entry points).
+
+The CPU oracle cannot run the full quadtree multiply here in seconds, so:
+  * the C block pattern is compared exactly with the boolean product of the
+    block patterns (computed by sparse 0/1 products);
+  * sampled C blocks are compared with C(I,J) = sum_K A(I,K) B(K,J) computed
+    straight from the definition, relative to (|A||B|)(I,J) from the same
+    definition on absolute values;
+  * sampled absent positions must come back as absent.
+For the 131072-dimension decay workload (C is 24 GB) the pattern is checked
+through its exact block count and sampled present/absent positions.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def qt():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1501_07800_amd as q
+    return q
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+def _ref_blocks(A, I, J):
+    idx = oracle.make_index(A, A)
+    absA = wl.BlockMatrix(A.n_rows, A.n_cols, A.b, A.I, A.J, np.abs(A.V))
+    refs, absrefs, ks = [], [], []
+    for i, j in zip(I, J):
+        refs.append(oracle.block_by_definition(A, A, i, j, idx))
+        absrefs.append(oracle.block_by_definition(absA, absA, i, j, idx))
+        ks.append(len(set(idx[0].get(int(i), {})) & set(idx[1].get(int(j), {}))))
+    return refs, absrefs, ks
+
+
+def _sample_present_absent(pos_ref, nbc, nb_total, rng, n):
+    pres = pos_ref[rng.choice(pos_ref.size, size=min(n, pos_ref.size), replace=False)]
+    cand = rng.choice(nb_total, size=4 * n, replace=False)
+    absent = np.setdiff1d(cand, pos_ref)[:n]
+    return pres // nbc, pres % nbc, absent // nbc, absent % nbc
+
+
+def _check_samples(C, dtype, I, J, refs, absrefs, ks, rel, abs_slack_per_term=0.0, b=32):
+    V, F = C.get_blocks(I, J, dtype)
+    assert F.all()
+    worst = 0.0
+    for t in range(len(I)):
+        err = np.abs(V[t].astype(np.float64) - refs[t])
+        bound = rel(ks[t]) * absrefs[t] + abs_slack_per_term * ks[t] * b
+        assert np.all(err <= bound), (t, float((err - bound).max()))
+        with np.errstate(divide="ignore", invalid="ignore"):
+            r = np.where(absrefs[t] > 0, err / absrefs[t], 0.0)
+        worst = max(worst, float(r.max()))
+    return worst
+
+
+def _full_case(qt, name, precs, n_samples=120):
+    A = wl.config(name)
+    leaf = wl.CONFIGS[name]["leaf"]
+    _say(name, "nnz", A.nnz, "leaf", leaf)
+    h = qt.from_blockmatrix(A, leaf)
+    pos_ref = oracle.pattern_by_definition(A, A)
+    rng = np.random.default_rng(123)
+    Ip, Jp, Ia, Ja = _sample_present_absent(pos_ref, A.nb_cols, A.nb_rows * A.nb_cols, rng, n_samples)
+    refs, absrefs, ks = _ref_blocks(A, Ip, Jp)
+    out = {}
+    for prec in precs:
+        _say(name, prec)
+        C = qt.multiply(h, h, prec)
+        I, J = C.pattern()
+        pos = I.astype(np.int64) * A.nb_cols + J
+        assert np.array_equal(pos, pos_ref), "C block pattern differs from the boolean product"
+        _, F = C.get_blocks(Ia, Ja)
+        assert not F.any()
+        b = A.b
+        if prec == "f64":
+            out[prec] = _check_samples(C, "f64", Ip, Jp, refs, absrefs, ks, lambda k: 1e-12, b=b)
+        elif prec == "f32":
+            out[prec] = _check_samples(C, "f32", Ip, Jp, refs, absrefs, ks,
+                                       lambda k: (k * b + 2) * 2.0 ** -24, 4 * 2.0 ** -126, b)
+        else:
+            out[prec] = _check_samples(C, "f64", Ip, Jp, refs, absrefs, ks,
+                                       lambda k: 3 * 2.0 ** -16 + (3 * b + 4) * 2.0 ** -24, 4 * 2.0 ** -126, b)
+        C.free()
+    _say(name, "worst componentwise errors", out)
+    return out
+
+
+def test_decay32768_full(qt):
+    e = _full_case(qt, "decay32768", ["f64", "f32", "bf16x3"])
+    assert e["f64"] <= 1e-12
+
+
+def test_random65536_full(qt):
+    e = _full_case(qt, "random65536", ["f64", "f32"])
+    assert e["f64"] <= 1e-12
+
+
+def test_banded1024_bench_config(qt):
+    e = _full_case(qt, "banded1024", ["f64", "f32", "bf16x3"], n_samples=60)
+    assert e["f64"] <= 1e-12
+
+
+@pytest.mark.slow
+def test_decay131072_sampled(qt):
+    """b = 64, leaf 512: fp64 and split-bf16 paths; exact C block count."""
+    name = "decay131072"
+    A = wl.config(name)
+    leaf = wl.CONFIGS[name]["leaf"]
+    _say(name, "nnz", A.nnz)
+    h = qt.from_blockmatrix(A, leaf)
+    pos_ref = oracle.pattern_by_definition(A, A)
+    rng = np.random.default_rng(321)
+    Ip, Jp, Ia, Ja = _sample_present_absent(pos_ref, A.nb_cols, A.nb_rows * A.nb_cols, rng, 40)
+    refs, absrefs, ks = _ref_blocks(A, Ip, Jp)
+    b = A.b
+    for prec in ("f64", "bf16x3"):
+        _say(name, prec)
+        C = qt.multiply(h, h, prec)
+        assert C.nblocks == pos_ref.size
+        _, F = C.get_blocks(Ia, Ja)
+        assert not F.any()
+        if prec == "f64":
+            w = _check_samples(C, "f64", Ip, Jp, refs, absrefs, ks, lambda k: 1e-12, b=b)
+            assert w <= 1e-12
+        else:
+            _check_samples(C, "f64", Ip, Jp, refs, absrefs, ks,
+                           lambda k: 3 * 2.0 ** -16 + (3 * b + 4) * 2.0 ** -24, 4 * 2.0 ** -126, b)
+        assert C.stats()["products"] == oracle.product_count(A, A)
+        C.free()

@@ -1,0 +1,172 @@
+"""GPU: transposed products, upper-triangle products and the symmetric
+square (the task types of Sec. 3.2 and 3.3), through the C ABI, against the
+CPU oracle run on the transposed / mirrored inputs built by definition."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as wl
+from tests._util import (compare, positions, random_pattern, symmetric_from_upper, transpose,
+                         upper_blocks)
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def qt():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1501_07800_amd as q
+    return q
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+def _blocks(h, n_rows, n_cols, b):
+    I, J, V = h.to_blocks("f64")
+    return wl.BlockMatrix(n_rows, n_cols, b, I, J, V)
+
+
+def _check(C, ref, absref, tol):
+    same, _, e_f, e_cw = compare(ref, C, absref)
+    assert same, (ref.nnz, C.nnz)
+    assert e_cw <= tol, e_cw
+    return e_cw
+
+
+@pytest.mark.parametrize("ta,tb", [(False, False), (True, False), (False, True), (True, True)])
+@pytest.mark.parametrize("b,lb", [(32, 4), (64, 2), (16, 8)])
+def test_transposed_products_f64(qt, ta, tb, b, lb):
+    rng = np.random.default_rng(100 + 2 * ta + tb + b)
+    m, k, n = 19, 27, 13
+    A = random_pattern(rng, k if ta else m, m if ta else k, 0.15, b)   # op(A) is m x k blocks
+    B = random_pattern(rng, n if tb else k, k if tb else n, 0.15, b)   # op(B) is k x n blocks
+    opA = transpose(A) if ta else A
+    opB = transpose(B) if tb else B
+    _say("transposes", ta, tb, "b", b)
+    ref, st = oracle.multiply(opA, opB, lb * b)
+    absref, _ = oracle.multiply(opA, opB, lb * b, use_abs=True)
+    hA, hB = qt.from_blockmatrix(A, lb * b), qt.from_blockmatrix(B, lb * b)
+    hC = qt.multiply_ex(hA, hB, trans_a=ta, trans_b=tb)
+    inf = hC.info()
+    assert (inf["n_rows"], inf["n_cols"]) == (m * b, n * b)
+    _check(_blocks(hC, m * b, n * b, b), ref, absref, 1e-12)
+    assert hC.stats()["products"] == st.block_products
+    assert hC.stats()["pairs"].tolist() == st.mul_tasks.tolist()
+
+
+@pytest.mark.parametrize("prec", ["f32", "bf16x3"])
+def test_transposed_products_reduced(qt, prec):
+    rng = np.random.default_rng(7)
+    b = 32
+    A = random_pattern(rng, 30, 20, 0.2, b)
+    B = random_pattern(rng, 30, 25, 0.2, b)
+    ref, _ = oracle.multiply(transpose(A), B, 4 * b)
+    absref, _ = oracle.multiply(transpose(A), B, 4 * b, use_abs=True)
+    hC = qt.multiply_ex(qt.from_blockmatrix(A, 4 * b), qt.from_blockmatrix(B, 4 * b), trans_a=True, prec=prec)
+    kmax = int(np.bincount(A.J, minlength=20).max())
+    tol = (kmax * b + 2) * 2.0 ** -24 if prec == "f32" else 3 * 2.0 ** -16 + (3 * b + 4) * 2.0 ** -24
+    _check(_blocks(hC, 20 * b, 25 * b, b), ref, absref, tol)
+
+
+def test_upper_only_product(qt):
+    rng = np.random.default_rng(8)
+    b = 32
+    A = random_pattern(rng, 45, 45, 0.08, b)
+    B = random_pattern(rng, 45, 45, 0.08, b)
+    full, _ = oracle.multiply(A, B, 8 * b)
+    absfull, _ = oracle.multiply(A, B, 8 * b, use_abs=True)
+    for leaf in (b, 4 * b, 8 * b):
+        hC = qt.multiply_ex(qt.from_blockmatrix(A, leaf), qt.from_blockmatrix(B, leaf), upper=True)
+        _check(_blocks(hC, A.n_rows, B.n_cols, b), upper_blocks(full), upper_blocks(absfull), 1e-12)
+    with pytest.raises(qt.QtError) as e:
+        R = random_pattern(rng, 5, 7, 0.5, b)
+        qt.multiply_ex(qt.from_blockmatrix(R, b), qt.from_blockmatrix(random_pattern(rng, 7, 4, 0.5, b), b),
+                       upper=True)
+    assert e.value.status == qt.QT_ERR_SHAPE
+
+
+def _sym_upper(rng, nb, fill, b):
+    X = random_pattern(rng, nb, nb, fill, b)
+    U = upper_blocks(X)
+    V = U.V.copy()
+    d = U.I == U.J
+    V[d] = 0.5 * (V[d] + V[d].transpose(0, 2, 1))          # symmetric diagonal blocks
+    return wl.BlockMatrix(U.n_rows, U.n_cols, b, U.I, U.J, V)
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32", "bf16x3"])
+def test_sysq(qt, prec):
+    rng = np.random.default_rng(9)
+    b = 32
+    U = _sym_upper(rng, 50, 0.06, b)
+    S = symmetric_from_upper(U)
+    full, st = oracle.multiply(S, S, 4 * b)
+    absfull, _ = oracle.multiply(S, S, 4 * b, use_abs=True)
+    h = qt.from_blockmatrix(U, 4 * b)
+    _say("sysq", prec)
+    C = qt.sysq(h, prec)
+    kmax = int(np.bincount(S.I, minlength=50).max())
+    tol = {"f64": 1e-12, "f32": (kmax * b + 2) * 2.0 ** -24,
+           "bf16x3": 3 * 2.0 ** -16 + (3 * b + 4) * 2.0 ** -24}[prec]
+    _check(_blocks(C, U.n_rows, U.n_cols, b), upper_blocks(full), upper_blocks(absfull), tol)
+    # about half the block products of the full square (Sec. 6.1: the expected speedup of 2)
+    ratio = C.stats()["products"] / st.block_products
+    assert 0.45 < ratio < 0.65, ratio
+
+
+def test_sysq_decay_and_errors(qt):
+    A = wl.decay3d(512, 16.0, 16, 32, seed=11)
+    S = wl.BlockMatrix(A.n_rows, A.n_cols, 32, A.I, A.J, A.V)
+    U = upper_blocks(S)
+    Sm = symmetric_from_upper(U)
+    full, _ = oracle.multiply(Sm, Sm, 256)
+    absfull, _ = oracle.multiply(Sm, Sm, 256, use_abs=True)
+    C = qt.sysq(qt.from_blockmatrix(U, 256))
+    _check(_blocks(C, U.n_rows, U.n_cols, 32), upper_blocks(full), upper_blocks(absfull), 1e-12)
+    with pytest.raises(qt.QtError) as e:
+        qt.sysq(qt.from_blockmatrix(S, 256))               # holds blocks below the diagonal
+    assert e.value.status == qt.QT_ERR_ARG
+    rng = np.random.default_rng(0)
+    with pytest.raises(qt.QtError) as e:
+        qt.sysq(qt.from_blockmatrix(random_pattern(rng, 4, 6, 0.5, 32), 32))
+    assert e.value.status == qt.QT_ERR_SHAPE
+
+
+def test_add_matches_algorithm2_bitwise(qt):
+    rng = np.random.default_rng(12)
+    for b, leaf in ((32, 128), (16, 16), (64, 512)):
+        A = random_pattern(rng, 30, 22, 0.2, b)
+        B = random_pattern(rng, 30, 22, 0.2, b)
+        ref, _ = oracle.add(A, B, leaf)
+        hC = qt.add(qt.from_blockmatrix(A, leaf), qt.from_blockmatrix(B, leaf))
+        C = _blocks(hC, A.n_rows, A.n_cols, b)
+        assert np.array_equal(positions(C), positions(ref))
+        assert np.array_equal(C.V, ref.V)                 # one fp64 addition per shared entry: exact
+        # the sum is a full matrix handle: it multiplies like any other
+        D = qt.multiply(hC, qt.from_blockmatrix(transpose(A), leaf))
+        refD, _ = oracle.multiply(ref, transpose(A), leaf)
+        absD, _ = oracle.multiply(wl.BlockMatrix(ref.n_rows, ref.n_cols, b, ref.I, ref.J, np.abs(ref.V)),
+                                  wl.BlockMatrix(A.n_cols, A.n_rows, b, transpose(A).I, transpose(A).J,
+                                                 np.abs(transpose(A).V)), leaf)
+        _check(_blocks(D, A.n_rows, A.n_rows, b), refD, absD, 1e-12)
+    empty = random_pattern(rng, 4, 4, 0.0, 32)
+    X = random_pattern(rng, 4, 4, 0.5, 32)
+    C = qt.add(qt.from_blockmatrix(empty, 64), qt.from_blockmatrix(X, 64))
+    assert np.array_equal(_blocks(C, X.n_rows, X.n_cols, 32).V, X.V)
+
+
+@pytest.mark.parametrize("a", [0.25, 0.6, 0.9])
+def test_rmat_pair_counts_match_oracle(qt, a):
+    """Per-level multiply pairs (the task counts of Sec. 5) on R-MAT patterns."""
+    A = wl.rmat(9, 5, a, 16, seed=61)
+    for leaf in (16, 64, 128):
+        ref, st = oracle.multiply(A, A, leaf)
+        h = qt.from_blockmatrix(A, leaf)
+        C = qt.multiply(h, h)
+        assert C.stats()["pairs"].tolist() == st.mul_tasks.tolist()
+        assert C.stats()["products"] == st.block_products
+        assert np.array_equal(positions(_blocks(C, A.n_rows, A.n_cols, 16)), positions(ref))

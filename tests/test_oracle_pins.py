@@ -268,3 +268,42 @@ def test_bf16_rounding_definition():
     hi, lo = split_bf16(v)
     a32 = v.astype(np.float32)
     assert np.all(np.abs((hi.astype(np.float64) + lo) - a32) <= np.abs(a32) * 2.0 ** -16)
+
+
+def test_add_algorithm2_dense_and_union():
+    """Sec. 3, Algorithm 2: the sum's pattern is the union of the patterns and
+    its values the dense sum (exact: one addition per entry at most)."""
+    rng = np.random.default_rng(51)
+    for b, lb in ((1, 1), (2, 4), (8, 2), (4, 8)):
+        A = random_pattern(rng, 21, 17, 0.3, b)
+        B = random_pattern(rng, 21, 17, 0.3, b)
+        C, st = oracle.add(A, B, lb * b)
+        assert np.array_equal(to_dense(C), to_dense(A) + to_dense(B))
+        assert np.array_equal(positions(C), np.union1d(positions(A), positions(B)))
+        # one leaf block addition per position present in both
+        assert st.leaf_block_adds == np.intersect1d(positions(A), positions(B)).size
+    Z = random_pattern(rng, 21, 17, 0.0, 2)
+    A = random_pattern(rng, 21, 17, 0.3, 2)
+    C, _ = oracle.add(A, Z, 8)
+    assert np.array_equal(C.V, A.V) and np.array_equal(positions(C), positions(A))
+
+
+def test_rmat_locality_moves_tasks_down():
+    """Sec. 5.1, R-MAT matrices: a = 0.25 is the random case (Eq. 1 within a
+    few percent at the populated levels), and raising a pushes the multiply
+    tasks towards the lowest levels (the share of leaf-level tasks grows)."""
+    scale = 10
+    shares = []
+    for a in (0.25, 0.5, 0.75, 0.9):
+        A = wl.rmat(scale, 5, a, 1, seed=60)
+        _, st = oracle.multiply(A, A, 1)
+        m = st.mul_tasks.astype(float)
+        shares.append(m[-1] / m.sum())
+        if a == 0.25:
+            N = 1 << scale
+            delta = A.nnz / float(N * N)
+            for l in range(scale + 1):
+                e = _eq1(N, delta, l)
+                if e >= 2e4:
+                    assert abs(m[l] - e) <= 0.05 * e, (l, m[l], e)
+    assert all(shares[i] < shares[i + 1] for i in range(len(shares) - 1)), shares

@@ -19,8 +19,9 @@ Patterns (Rubensson & Rudberg, Sec. 5.1 and Sec. 6):
   The paper builds its overlap matrices with an electronic structure code
   from water clusters, which are not available here; this generator stands
   in for them with the same kind of distance-decay sparsity.
+* ``rmat``: R-MAT graph patterns with a tunable degree of locality (Sec. 5.1).
 * ``batch_mix``: many independent problems of uneven size and fill, mixing
-  the three patterns above.
+  the banded, random and decay patterns.
 
 Random streams are numpy's PCG64 ``default_rng(seed)``; block values are
 drawn in row-major block order.
@@ -38,6 +39,7 @@ __all__ = [
     "random_blocks",
     "decay3d",
     "divide_space_order",
+    "rmat",
     "batch_mix",
     "config",
     "CONFIGS",
@@ -201,6 +203,29 @@ def decay3d(natoms: int, side: float, bf_per_atom: int, b: int, seed: int,
     return _finish(n, n, b, cI[keep], cJ[keep], V, {
         "pattern": "decay3d", "natoms": natoms, "side": side,
         "bf_per_atom": bf_per_atom, "threshold": threshold, "seed": seed})
+
+
+def rmat(scale: int, edges_per_row: float, a: float, b: int, seed: int, rng=None) -> BlockMatrix:
+    """R-MAT graph pattern on a 2^scale x 2^scale block grid (Sec. 5.1, Fig. 4).
+
+    Each edge picks, level by level from the top, one quadrant with
+    probabilities (a, q, q, q), q = (1 - a) / 3; repeated edges coincide, so
+    the matrix holds at most round(edges_per_row * 2^scale) blocks. a = 0.25
+    is the uniformly random case; larger a concentrates the pattern (more
+    locality). Block values N(0,1), drawn in row-major block order.
+    """
+    rng = np.random.default_rng(seed) if rng is None else rng
+    n = 1 << scale
+    m = int(round(edges_per_row * n))
+    q = (1.0 - a) / 3.0
+    quad = rng.choice(4, size=(m, scale), p=[a, q, q, q])   # 0: (0,0) 1: (0,1) 2: (1,0) 3: (1,1)
+    w = (1 << np.arange(scale - 1, -1, -1)).astype(np.int64)
+    I = ((quad >> 1) * w).sum(axis=1)
+    J = ((quad & 1) * w).sum(axis=1)
+    pos = np.unique(I * n + J)
+    I, J = pos // n, pos % n
+    V = rng.standard_normal((pos.size, b, b))
+    return _finish(n * b, n * b, b, I, J, V, {"pattern": "rmat", "a": a, "seed": seed})
 
 
 def _decay_with_fill(n: int, b: int, fill: float, rng) -> BlockMatrix:
