@@ -29,6 +29,23 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def measured_traffic(kernel_source: str, workload: str, prec: str):
+    """HBM bytes per launch of the numeric kernel from the committed rocprofv3
+    counter summary (FETCH_SIZE and WRITE_SIZE, scaled by a plain copy's
+    reading), or None when there is none for this workload or the kernel's
+    source has changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"traffic_{prec}_{workload}.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    src = os.path.join(ROOT, "paper_1501_07800_amd", "csrc", kernel_source)
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    if rec.get("source_sha256") != sha:
+        return None
+    return rec.get("traffic_bytes")
+
+
 def timed_steps(qt, torch, hA, prec, steps, warmup):
     for _ in range(warmup):
         qt.multiply(hA, hA, prec).free()
@@ -197,6 +214,10 @@ def main():
     main_r = results[args.prec]
     P = main_r["P"]
     flops = 2.0 * b ** 3 * P
+    esz = 4 if args.prec == "f32" else 8
+    # algorithmic HBM bytes of one numeric launch: A's values read once (C = A*A)
+    # and C written once
+    alg_bytes = A.nnz * b * b * esz + main_r["nnz_C"] * b * b * (4 if args.prec == "f32" else 8)
 
     cpu = None
     ref = None
@@ -250,7 +271,9 @@ def main():
                    "block_products": P, "nnz_C": main_r["nnz_C"], "prec": args.prec, "op": "C = A*A"},
         "mfma_peak_frac": main_r["tflops"] / peak,
         "roofline": {"bound": "mfma", "achieved": main_r["numeric_tflops"], "peak": peak, "unit": "TFLOP/s",
-                     "frac": main_r["numeric_tflops"] / peak, "traffic": None,
+                     "frac": main_r["numeric_tflops"] / peak,
+                     "traffic": measured_traffic("qt_numeric.hip", args.workload, args.prec),
+                     "algorithmic_bytes": alg_bytes,
                      "kernel": "k_numeric (block GEMM per C block)"},
         "cpu_baseline": cpu,
         "paths": paths,

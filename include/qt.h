@@ -123,6 +123,18 @@ qt_status qt_multiply_ex(const qt_matrix* A, const qt_matrix* B, int32_t op_flag
 qt_status qt_add(const qt_matrix* A, const qt_matrix* B, void* stream, qt_matrix** C);
 
 /*
+ * Value truncation: T holds M without its smallest blocks, removed in order
+ * of increasing Frobenius norm for as long as the Frobenius norm of all
+ * removed blocks together stays below eps (the error matrix E = M - T has
+ * ||E||_F < eps; Sec. 6.2 truncates its overlap matrix this way). Kept blocks
+ * are copied unchanged. *removed / *removed_norm2 (may be NULL) receive the
+ * number of removed blocks and ||E||_F^2. Synchronizes `stream`.
+ * Errors: ARG (eps negative or NaN), OOM, DEVICE.
+ */
+qt_status qt_truncate(const qt_matrix* M, double eps, void* stream, qt_matrix** T, int64_t* removed,
+                      double* removed_norm2);
+
+/*
  * Symmetric matrix square (Sec. 3.3): A holds the upper block triangle
  * (blocks with I <= J; diagonal blocks stored whole) of a symmetric S; C
  * holds the upper block triangle of S*S. S is formed once from A (the strictly

@@ -179,6 +179,18 @@ def add(A: BlockMatrix, B: BlockMatrix, leaf: int, lib=None):
     return _take(lib, out, A.n_rows, A.n_cols, b, {"from": "oracle add", "leaf": leaf})
 
 
+def truncate(M: BlockMatrix, eps: float):
+    """Drop blocks in order of increasing Frobenius norm while the norm of all
+    removed blocks stays below eps (||M - T||_F < eps). Returns (T, removed)."""
+    n2 = (M.V.reshape(M.nnz, -1) ** 2).sum(axis=1)
+    order = np.argsort(n2, kind="stable")
+    run = np.cumsum(n2[order])
+    k = int(np.count_nonzero(run < eps * eps))
+    keep = np.ones(M.nnz, bool)
+    keep[order[:k]] = False
+    return BlockMatrix(M.n_rows, M.n_cols, M.b, M.I[keep], M.J[keep], M.V[keep], dict(M.meta)), k
+
+
 def threads() -> int:
     """OpenMP threads the oracle's multiply uses."""
     return int(_lib().qo_threads(0))

@@ -52,6 +52,8 @@ def _load():
     lib.qt_multiply_ex.argtypes = [vp, vp, i32, ctypes.c_int, vp, ctypes.POINTER(vp)]
     lib.qt_add.restype = ctypes.c_int
     lib.qt_add.argtypes = [vp, vp, vp, ctypes.POINTER(vp)]
+    lib.qt_truncate.restype = ctypes.c_int
+    lib.qt_truncate.argtypes = [vp, ctypes.c_double, vp, ctypes.POINTER(vp), i64p, ctypes.POINTER(ctypes.c_double)]
     lib.qt_sysq.restype = ctypes.c_int
     lib.qt_sysq.argtypes = [vp, ctypes.c_int, vp, ctypes.POINTER(vp)]
     lib.qt_info.restype = ctypes.c_int
@@ -97,7 +99,7 @@ def _load():
 
 lib = _load()
 
-EXPORTS = ("qt_build", "qt_multiply", "qt_multiply_ex", "qt_add", "qt_sysq", "qt_info", "qt_to_blocks", "qt_get_blocks", "qt_stats", "qt_prepare", "qt_free",
+EXPORTS = ("qt_build", "qt_multiply", "qt_multiply_ex", "qt_add", "qt_truncate", "qt_sysq", "qt_info", "qt_to_blocks", "qt_get_blocks", "qt_stats", "qt_prepare", "qt_free",
            "qt_plan_create", "qt_plan_execute", "qt_plan_tune", "qt_plan_set_schedule", "qt_plan_result", "qt_plan_info",
            "qt_plan_destroy", "qt_tune_leaf", "qt_profile", "qt_profile_read", "qt_last_error", "qt_version")
 PLAN_SCHEDULES = ("flat", "persistent-1", "persistent-4", "persistent-16")
@@ -320,6 +322,15 @@ def add(A: Matrix, B: Matrix, stream=None) -> Matrix:
     out = ctypes.c_void_p()
     _check(lib.qt_add(A.handle, B.handle, _stream_ptr(stream), ctypes.byref(out)))
     return Matrix(out.value)
+
+
+def truncate(M: Matrix, eps: float, stream=None):
+    """qt_truncate: drop the smallest blocks while ||removed||_F < eps; returns (T, removed, ||E||_F^2)."""
+    out = ctypes.c_void_p()
+    k = ctypes.c_int64()
+    e2 = ctypes.c_double()
+    _check(lib.qt_truncate(M.handle, eps, _stream_ptr(stream), ctypes.byref(out), ctypes.byref(k), ctypes.byref(e2)))
+    return Matrix(out.value), k.value, e2.value
 
 
 def sysq(A: Matrix, prec: str = "f64", stream=None) -> Matrix:

@@ -155,6 +155,23 @@ qt_status qt_add(const qt_matrix* A, const qt_matrix* B, void* stream, qt_matrix
     QT_GUARD_END
 }
 
+qt_status qt_truncate(const qt_matrix* M, double eps, void* stream, qt_matrix** T, int64_t* removed,
+                      double* removed_norm2) {
+    if (!T) {
+        set_last_error("NULL output handle");
+        return QT_ERR_ARG;
+    }
+    *T = nullptr;
+    if (!M) {
+        set_last_error("NULL matrix");
+        return QT_ERR_ARG;
+    }
+    QT_GUARD_BEGIN
+    *T = truncate(const_cast<qt_matrix*>(M), eps, (hipStream_t)stream, removed, removed_norm2);
+    return QT_OK;
+    QT_GUARD_END
+}
+
 qt_status qt_sysq(const qt_matrix* A, qt_prec prec, void* stream, qt_matrix** C) {
     if (!C) {
         set_last_error("NULL output handle");

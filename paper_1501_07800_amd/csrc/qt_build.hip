@@ -766,6 +766,103 @@ qt_matrix* add(qt_matrix* A, qt_matrix* B, hipStream_t s) {
     return C.release();
 }
 
+// --------------------------------------------------- value truncation
+
+// Squared Frobenius norm of every block, and its bit pattern as a sort key
+// (non-negative doubles order like their bit patterns).
+__global__ void k_block_norm2(const double* __restrict__ v, int64_t n, int bb, double* __restrict__ norm2,
+                              uint64_t* __restrict__ key, int32_t* __restrict__ idx) {
+    __shared__ double part[256];
+    for (int64_t t = blockIdx.x; t < n; t += gridDim.x) {
+        double s = 0.0;
+        for (int e = threadIdx.x; e < bb; e += blockDim.x) {
+            const double x = v[(size_t)t * bb + e];
+            s += x * x;
+        }
+        part[threadIdx.x] = s;
+        __syncthreads();
+        for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+            if ((int)threadIdx.x < w) part[threadIdx.x] += part[threadIdx.x + w];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) {
+            norm2[t] = part[0];
+            key[t] = (uint64_t)__double_as_longlong(part[0]);
+            idx[t] = (int32_t)t;
+        }
+        __syncthreads();
+    }
+}
+
+__global__ void k_gather_f64(const double* __restrict__ src, const int32_t* __restrict__ idx, int64_t n,
+                             double* __restrict__ dst) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) dst[i] = src[idx[i]];
+}
+
+// Sorted position p is removed while the running sum of squared norms up to
+// and including p stays below eps^2; the survivors are flagged by block.
+__global__ void k_trunc_flags(const double* __restrict__ excl, const double* __restrict__ sorted, int64_t n,
+                              double eps2, const int32_t* __restrict__ idx, int32_t* __restrict__ keep) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p < n) keep[idx[p]] = (excl[p] + sorted[p] < eps2) ? 0 : 1;
+}
+
+__global__ void k_compact_blocks(const uint64_t* __restrict__ bkey, const double* __restrict__ v, int64_t n, int bb,
+                                 const int32_t* __restrict__ keep, const int32_t* __restrict__ pos,
+                                 int32_t* __restrict__ I, int32_t* __restrict__ J, double* __restrict__ out) {
+    for (int64_t t = blockIdx.x; t < n; t += gridDim.x) {
+        if (!keep[t]) continue;
+        const int64_t o = pos[t];
+        if (threadIdx.x == 0) {
+            I[o] = (int32_t)morton_row(bkey[t]);
+            J[o] = (int32_t)morton_col(bkey[t]);
+        }
+        for (int e = threadIdx.x; e < bb; e += blockDim.x) out[(size_t)o * bb + e] = v[(size_t)t * bb + e];
+    }
+}
+
+qt_matrix* truncate(qt_matrix* M, double eps, hipStream_t s, int64_t* removed, double* removed_norm2) {
+    if (!(eps >= 0.0)) fail(QT_ERR_ARG, "eps must be a non-negative number");
+    const double* v = operand_f64(M, s);
+    const int64_t n = M->nblocks;
+    const int bb = M->b * M->b;
+    if (removed) *removed = 0;
+    if (removed_norm2) *removed_norm2 = 0.0;
+    if (n == 0) return build(M->n_rows, M->n_cols, M->b, M->leaf, 0, nullptr, nullptr, nullptr, QT_MEM_DEVICE, s);
+    int64_t npow2 = 1;
+    while (npow2 < n) npow2 <<= 1;
+    DBuf<double> norm2(n, s), sorted(n, s), excl(n + 1, s), dtmp(scan_tmp_elems(n) + 1, s);
+    DBuf<uint64_t> key(npow2, s);
+    DBuf<int32_t> idx(npow2, s), keep(n, s), pos(n + 1, s), itmp(scan_tmp_elems(n) + 1, s);
+    k_block_norm2<<<block_grid(n), 256, 0, s>>>(v, n, bb, norm2.p, key.p, idx.p);
+    QT_LAUNCH("k_block_norm2");
+    bitonic_sort(key.p, idx.p, n, s);
+    k_gather_f64<<<grid_for(n), 256, 0, s>>>(norm2.p, idx.p, n, sorted.p);
+    QT_LAUNCH("k_gather_f64");
+    exclusive_scan(sorted.p, excl.p, n, dtmp.p, s);
+    k_trunc_flags<<<grid_for(n), 256, 0, s>>>(excl.p, sorted.p, n, eps * eps, idx.p, keep.p);
+    QT_LAUNCH("k_trunc_flags");
+    exclusive_scan(keep.p, pos.p, n, itmp.p, s);
+    const int32_t nk = read_scalar(pos.p + n, s);
+    DBuf<int32_t> I(std::max<int64_t>(nk, 1), s), J(std::max<int64_t>(nk, 1), s);
+    DBuf<double> V(std::max<size_t>((size_t)nk * bb, 1), s);
+    k_compact_blocks<<<block_grid(n), 256, 0, s>>>(M->bkey.p, v, n, bb, keep.p, pos.p, I.p, J.p, V.p);
+    QT_LAUNCH("k_compact_blocks");
+    if (removed || removed_norm2) {
+        const int64_t k = n - nk;   // the k smallest blocks were removed
+        if (removed) *removed = k;
+        if (removed_norm2 && k > 0) {
+            double e = 0.0, last = 0.0;
+            QT_HIP(hipMemcpyAsync(&e, excl.p + (k - 1), sizeof(double), hipMemcpyDeviceToHost, s));
+            QT_HIP(hipMemcpyAsync(&last, sorted.p + (k - 1), sizeof(double), hipMemcpyDeviceToHost, s));
+            QT_HIP(hipStreamSynchronize(s));
+            *removed_norm2 = e + last;
+        }
+    }
+    return build(M->n_rows, M->n_cols, M->b, M->leaf, nk, I.p, J.p, V.p, QT_MEM_DEVICE, s);
+}
+
 void get_blocks(const qt_matrix* M, int64_t count, const int32_t* I, const int32_t* J, void* values,
                 int32_t* found, qt_prec out_type, qt_mem where, hipStream_t s) {
     if (out_type != QT_F64 && out_type != QT_F32) fail(QT_ERR_UNSUPPORTED, "output type must be F64 or F32");

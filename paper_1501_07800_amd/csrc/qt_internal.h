@@ -163,6 +163,7 @@ namespace qt {
 size_t scan_tmp_elems(int64_t n);
 void exclusive_scan(const int32_t* in, int32_t* out, int64_t n, int32_t* tmp, hipStream_t s);
 void exclusive_scan(const int64_t* in, int64_t* out, int64_t n, int64_t* tmp, hipStream_t s);
+void exclusive_scan(const double* in, double* out, int64_t n, double* tmp, hipStream_t s);
 
 // Sub-allocation of one device allocation: offsets are planned on the host
 // (256-byte aligned) before the single allocation is made.
@@ -255,6 +256,7 @@ qt_matrix* multiply(qt_matrix* A, qt_matrix* B, qt_prec prec, hipStream_t s, con
 qt_matrix* build(int64_t n_rows, int64_t n_cols, int32_t b, int32_t leaf, int64_t nblocks, const int32_t* I,
                  const int32_t* J, const double* values, qt_mem where, hipStream_t s);
 qt_matrix* add(qt_matrix* A, qt_matrix* B, hipStream_t s);
+qt_matrix* truncate(qt_matrix* M, double eps, hipStream_t s, int64_t* removed, double* removed_norm2);
 // The full symmetric matrix whose upper block triangle is A (cached in A).
 qt_matrix* symmetric_full(qt_matrix* A, hipStream_t s);
 

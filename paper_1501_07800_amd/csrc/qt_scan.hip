@@ -127,4 +127,8 @@ void exclusive_scan(const int64_t* in, int64_t* out, int64_t n, int64_t* tmp, hi
     scan_impl<int64_t>(in, out, n, tmp, s);
 }
 
+void exclusive_scan(const double* in, double* out, int64_t n, double* tmp, hipStream_t s) {
+    scan_impl<double>(in, out, n, tmp, s);
+}
+
 }  // namespace qt

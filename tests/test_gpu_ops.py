@@ -170,3 +170,30 @@ def test_rmat_pair_counts_match_oracle(qt, a):
         assert C.stats()["pairs"].tolist() == st.mul_tasks.tolist()
         assert C.stats()["products"] == st.block_products
         assert np.array_equal(positions(_blocks(C, A.n_rows, A.n_cols, 16)), positions(ref))
+
+
+def test_truncate_matches_definition(qt):
+    rng = np.random.default_rng(13)
+    b = 32
+    M = random_pattern(rng, 40, 40, 0.1, b)
+    M.V *= np.exp(rng.uniform(-12, 0, size=(M.nnz, 1, 1)))      # well separated block norms
+    n2 = np.sort((M.V.reshape(M.nnz, -1) ** 2).sum(1))
+    cums = np.cumsum(n2)
+    h = qt.from_blockmatrix(M, 4 * b)
+    for k_target in (0, 1, 7, M.nnz // 2, M.nnz - 1, M.nnz):
+        # eps between the cumulative sums, far from either
+        lo = cums[k_target - 1] if k_target > 0 else 0.0
+        hi = cums[k_target] if k_target < M.nnz else 2 * cums[-1] + 1.0
+        eps = float(np.sqrt(0.5 * (lo + hi))) if k_target > 0 else float(np.sqrt(0.5 * cums[0]))
+        ref, k = oracle.truncate(M, eps)
+        T, removed, e2 = qt.truncate(h, eps)
+        assert removed == k == k_target
+        got = _blocks(T, M.n_rows, M.n_cols, b)
+        assert np.array_equal(positions(got), positions(wl.BlockMatrix(M.n_rows, M.n_cols, b, *_sorted(ref))))
+        assert np.array_equal(got.V, _sorted(ref)[2])
+        assert e2 < eps * eps and abs(e2 - lo) <= 1e-12 * max(lo, 1e-300)
+
+
+def _sorted(M):
+    o = np.lexsort((M.J, M.I))
+    return M.I[o], M.J[o], M.V[o]

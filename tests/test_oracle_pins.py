@@ -307,3 +307,25 @@ def test_rmat_locality_moves_tasks_down():
                 if e >= 2e4:
                     assert abs(m[l] - e) <= 0.05 * e, (l, m[l], e)
     assert all(shares[i] < shares[i + 1] for i in range(len(shares) - 1)), shares
+
+
+def test_truncation_definition():
+    """Truncation of Sec. 6.2: ||M - T||_F < eps, the removed blocks are the
+    smallest ones, and removing the next block would reach eps."""
+    rng = np.random.default_rng(70)
+    M = random_pattern(rng, 30, 30, 0.3, 4)
+    M.V *= rng.uniform(1e-6, 1.0, size=(M.nnz, 1, 1))
+    norms = np.sqrt((M.V.reshape(M.nnz, -1) ** 2).sum(1))
+    for eps in (0.0, 1e-5, 1e-3, 0.5, 3.0, 1e9):
+        T, k = oracle.truncate(M, eps)
+        E = to_dense(M) - to_dense(T)
+        assert np.linalg.norm(E) < eps or (k == 0 and eps == 0.0)
+        kept = set(zip(T.I.tolist(), T.J.tolist()))
+        removed = [t for t in range(M.nnz) if (int(M.I[t]), int(M.J[t])) not in kept]
+        assert len(removed) == k
+        if k and T.nnz:
+            assert norms[removed].max() <= np.sort(norms[[t for t in range(M.nnz) if t not in removed]])[0]
+        if T.nnz:
+            nxt = np.sort(norms[[t for t in range(M.nnz) if t not in removed]])[0]
+            assert np.sqrt(np.sum(norms[removed] ** 2) + nxt ** 2) >= eps
+        assert np.array_equal(to_dense(T)[to_dense(T) != 0], to_dense(M)[to_dense(T) != 0])
