@@ -16,6 +16,17 @@
 // lets each lane read its A entries with 16-byte loads (see wave_block),
 // while the 16 lanes of a group read 16 consecutive entries of one B row.
 //
+// Launch shape. Each workgroup is a single wave that owns one 32 x 32 (or
+// 16 x 16) tile of a C block: a finished wave frees its slot at once, so a
+// short segment never holds a SIMD while a long neighbour runs. The
+// dispatcher hands workgroup w to XCD w % 8, and each XCD has its own L2.
+// Consecutive C blocks in Morton order share most of their A and B blocks,
+// so the launch gives each XCD runs of 2^XCD_CHUNK_LOG consecutive tiles
+// (XCD x takes runs x, x+8, x+16, ...) instead of every eighth tile:
+// neighbours then meet in the same L2, while the interleaved runs keep the
+// eight XCDs equally loaded. C is written with non-temporal stores, since no
+// later step of the multiply reads it.
+//
 // The same per-wave routines serve one multiply (k_numeric: one launch over
 // the C blocks of C) and a batch of independent multiplies (k_batch_*: one
 // launch over the C blocks of all of them).
@@ -47,18 +58,32 @@ template <> struct Mfma<float> {
 };
 
 // Tile geometry for block size BS: each wave computes a WT x WT tile made of
-// MT x MT 16x16 MFMA tiles; WPB waves cover one C block; a 256-thread
-// workgroup covers SPW C blocks; the inner dimension is walked in chunks of
-// KC with KS 4-deep MFMA steps each.
+// MT x MT 16x16 MFMA tiles; WPB waves cover one C block; the inner dimension
+// is walked in chunks of KC with KS 4-deep MFMA steps each.
 template <int BS> struct Geo {
     static constexpr int WT = BS < 32 ? BS : 32;
     static constexpr int MT = WT / 16;
     static constexpr int WPB = (BS / WT) * (BS / WT);
-    static constexpr int SPW = 4 / WPB;
     static constexpr int KC = BS < 32 ? BS : 32;
     static constexpr int KS = KC / 4;
     static constexpr int NCH = BS / KC;
 };
+
+constexpr int XCD_CHUNK_LOG = 8;
+
+// Logical tile of physical workgroup w; a bijection on [0, grid) when the
+// grid is a multiple of 8 << XCD_CHUNK_LOG (xcd_grid pads it so).
+__device__ __forceinline__ int64_t xcd_logical(int64_t w) {
+    const int64_t x = w & 7, i = w >> 3;
+    return ((((i >> XCD_CHUNK_LOG) << 3) + x) << XCD_CHUNK_LOG) | (i & ((1 << XCD_CHUNK_LOG) - 1));
+}
+
+static unsigned xcd_grid(int64_t tiles) {
+    const int64_t q = int64_t(8) << XCD_CHUNK_LOG;
+    const int64_t g = (tiles + q - 1) / q * q;
+    if (g > 0x7fffffffLL) fail(QT_ERR_UNSUPPORTED, "numeric launch too large");
+    return (unsigned)g;
+}
 
 // One wave: tile `sub` of a C block, over the products t0 .. t1-1.
 template <class T, int BS>
@@ -130,7 +155,8 @@ __device__ __forceinline__ void wave_block(const T* __restrict__ A, const T* __r
         for (int nt = 0; nt < G::MT; ++nt)
 #pragma unroll
             for (int i = 0; i < 4; ++i)
-                c[(wm + mt * 16 + Mfma<T>::row(g, i)) * BS + wn + nt * 16 + r16] = acc[mt][nt][i];
+                __builtin_nontemporal_store(acc[mt][nt][i],
+                                            c + (wm + mt * 16 + Mfma<T>::row(g, i)) * BS + wn + nt * 16 + r16);
 }
 
 // Split-bf16 path: per block product, F = lo_a*hi_b + hi_a*lo_b + hi_a*hi_b
@@ -211,57 +237,56 @@ __device__ __forceinline__ void wave_block_bf16x3(const uint16_t* __restrict__ A
         for (int nt = 0; nt < MT; ++nt)
 #pragma unroll
             for (int i = 0; i < 4; ++i)
-                c[(wm + mt * 16 + 4 * g + i) * BS + wn + nt * 16 + r16] = acc[mt][nt][i];
+                __builtin_nontemporal_store(acc[mt][nt][i], c + (wm + mt * 16 + 4 * g + i) * BS + wn + nt * 16 + r16);
 }
 
 // ------------------------------------------------------ one multiply
 
 template <class T, int BS>
-__global__ __launch_bounds__(256) void k_numeric(const T* __restrict__ A, const T* __restrict__ B,
-                                                 const int32_t* __restrict__ prodA,
-                                                 const int32_t* __restrict__ prodB,
-                                                 const int32_t* __restrict__ seg, int32_t nseg,
-                                                 T* __restrict__ C) {
+__global__ __launch_bounds__(64) void k_numeric(const T* __restrict__ A, const T* __restrict__ B,
+                                                const int32_t* __restrict__ prodA,
+                                                const int32_t* __restrict__ prodB,
+                                                const int32_t* __restrict__ seg, int32_t nseg,
+                                                T* __restrict__ C) {
     typedef Geo<BS> G;
-    const int wave = threadIdx.x >> 6;
-    const int64_t s = (int64_t)blockIdx.x * G::SPW + wave / G::WPB;
+    const int64_t tile = xcd_logical(blockIdx.x);
+    const int64_t s = tile / G::WPB;
     if (s >= nseg) return;
-    wave_block<T, BS>(A, B, prodA, prodB, seg[s], seg[s + 1], C + (size_t)s * (BS * BS), wave % G::WPB);
+    wave_block<T, BS>(A, B, prodA, prodB, seg[s], seg[s + 1], C + (size_t)s * (BS * BS), (int)(tile % G::WPB));
 }
 
 template <int BS>
-__global__ __launch_bounds__(256) void k_numeric_bf16x3(const uint16_t* __restrict__ Ahi,
-                                                        const uint16_t* __restrict__ Alo,
-                                                        const uint16_t* __restrict__ Bhi_t,
-                                                        const uint16_t* __restrict__ Blo_t,
-                                                        const int32_t* __restrict__ prodA,
-                                                        const int32_t* __restrict__ prodB,
-                                                        const int32_t* __restrict__ seg, int32_t nseg,
-                                                        double* __restrict__ C) {
+__global__ __launch_bounds__(64) void k_numeric_bf16x3(const uint16_t* __restrict__ Ahi,
+                                                       const uint16_t* __restrict__ Alo,
+                                                       const uint16_t* __restrict__ Bhi_t,
+                                                       const uint16_t* __restrict__ Blo_t,
+                                                       const int32_t* __restrict__ prodA,
+                                                       const int32_t* __restrict__ prodB,
+                                                       const int32_t* __restrict__ seg, int32_t nseg,
+                                                       double* __restrict__ C) {
     constexpr int WPB = (BS / 32) * (BS / 32);
-    constexpr int SPW = 4 / WPB;
-    const int wave = threadIdx.x >> 6;
-    const int64_t s = (int64_t)blockIdx.x * SPW + wave / WPB;
+    const int64_t tile = xcd_logical(blockIdx.x);
+    const int64_t s = tile / WPB;
     if (s >= nseg) return;
     wave_block_bf16x3<BS>(Ahi, Alo, Bhi_t, Blo_t, prodA, prodB, seg[s], seg[s + 1], C + (size_t)s * (BS * BS),
-                          wave % WPB);
+                          (int)(tile % WPB));
 }
 
 template <class T, int BS>
 static void launch_t(const NumericArgs& a, hipStream_t s) {
     typedef Geo<BS> G;
-    const unsigned grid = (unsigned)((a.nseg + G::SPW - 1) / G::SPW);
-    k_numeric<T, BS><<<grid, 256, 0, s>>>((const T*)a.A, (const T*)a.B, a.prodA, a.prodB, a.seg, a.nseg,
-                                          (T*)a.C);
+    const unsigned grid = xcd_grid((int64_t)a.nseg * G::WPB);
+    k_numeric<T, BS><<<grid, 64, 0, s>>>((const T*)a.A, (const T*)a.B, a.prodA, a.prodB, a.seg, a.nseg,
+                                         (T*)a.C);
     QT_LAUNCH("k_numeric");
 }
 
 template <int BS>
 static void launch_bf(const NumericArgs& a, hipStream_t s) {
-    constexpr int SPW = 4 / ((BS / 32) * (BS / 32));
-    const unsigned grid = (unsigned)((a.nseg + SPW - 1) / SPW);
-    k_numeric_bf16x3<BS><<<grid, 256, 0, s>>>(a.Ahi, a.Alo, a.Bhi_t, a.Blo_t, a.prodA, a.prodB, a.seg, a.nseg,
-                                              (double*)a.C);
+    constexpr int WPB = (BS / 32) * (BS / 32);
+    const unsigned grid = xcd_grid((int64_t)a.nseg * WPB);
+    k_numeric_bf16x3<BS><<<grid, 64, 0, s>>>(a.Ahi, a.Alo, a.Bhi_t, a.Blo_t, a.prodA, a.prodB, a.seg, a.nseg,
+                                             (double*)a.C);
     QT_LAUNCH("k_numeric_bf16x3");
 }
 
@@ -293,7 +318,8 @@ void launch_numeric(const NumericArgs& a, hipStream_t s) {
 // Work item i of the batch is one wave's tile of one C block. Problem p owns
 // items item_base[p] .. item_base[p+1]-1 (C blocks in Morton order, WPB tiles
 // each). Two schedules:
-//   flat:       one launch whose grid covers every item (the hardware
+//   flat:       one launch whose grid covers every item, one wave per
+//               workgroup in the XCD-run order above (the hardware
 //               dispatcher balances the uneven problems);
 //   persistent: a grid sized to fill the GPU once; each wave takes the next
 //               CHUNK items from a counter until none are left, so every
@@ -359,15 +385,15 @@ template <int BS> struct Item<2, BS> {   // split bf16
 };
 
 template <int KIND, int BS>
-__global__ __launch_bounds__(256) void k_batch_flat(const BatchProblem* __restrict__ probs,
-                                                    const int64_t* __restrict__ item_base, int32_t nprob) {
-    const int64_t it = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+__global__ __launch_bounds__(64) void k_batch_flat(const BatchProblem* __restrict__ probs,
+                                                   const int64_t* __restrict__ item_base, int32_t nprob) {
+    const int64_t it = xcd_logical(blockIdx.x);
     if (it >= item_base[nprob]) return;
     Item<KIND, BS>::run(probs, item_base, nprob, it);
 }
 
 template <int KIND, int BS, int CHUNK>
-__global__ __launch_bounds__(256) void k_batch_persistent(const BatchProblem* __restrict__ probs,
+__global__ __launch_bounds__(64) void k_batch_persistent(const BatchProblem* __restrict__ probs,
                                                           const int64_t* __restrict__ item_base, int32_t nprob,
                                                           unsigned long long* __restrict__ counter) {
     const int lane = threadIdx.x & 63;
@@ -389,8 +415,8 @@ __global__ void k_batch_reset(unsigned long long* counter) { *counter = 0ull; }
 template <int KIND, int BS>
 static void launch_batch_kb(const BatchLaunch& L, hipStream_t s) {
     if (L.variant == 0) {
-        const unsigned grid = (unsigned)((L.total_items + 3) / 4);
-        k_batch_flat<KIND, BS><<<grid, 256, 0, s>>>(L.probs, L.item_base, L.nprob);
+        const unsigned grid = xcd_grid(L.total_items);
+        k_batch_flat<KIND, BS><<<grid, 64, 0, s>>>(L.probs, L.item_base, L.nprob);
         QT_LAUNCH("k_batch_flat");
         return;
     }
@@ -398,11 +424,11 @@ static void launch_batch_kb(const BatchLaunch& L, hipStream_t s) {
     QT_LAUNCH("k_batch_reset");
     const unsigned g = (unsigned)L.persistent_grid;
     if (L.variant == 1)
-        k_batch_persistent<KIND, BS, 1><<<g, 256, 0, s>>>(L.probs, L.item_base, L.nprob, L.counter);
+        k_batch_persistent<KIND, BS, 1><<<g, 64, 0, s>>>(L.probs, L.item_base, L.nprob, L.counter);
     else if (L.variant == 2)
-        k_batch_persistent<KIND, BS, 4><<<g, 256, 0, s>>>(L.probs, L.item_base, L.nprob, L.counter);
+        k_batch_persistent<KIND, BS, 4><<<g, 64, 0, s>>>(L.probs, L.item_base, L.nprob, L.counter);
     else
-        k_batch_persistent<KIND, BS, 16><<<g, 256, 0, s>>>(L.probs, L.item_base, L.nprob, L.counter);
+        k_batch_persistent<KIND, BS, 16><<<g, 64, 0, s>>>(L.probs, L.item_base, L.nprob, L.counter);
     QT_LAUNCH("k_batch_persistent");
 }
 
@@ -411,7 +437,7 @@ static int persistent_grid_kb() {
     int dev = 0, cus = 0, per_cu = 0;
     QT_HIP(hipGetDevice(&dev));
     QT_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-    QT_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch_persistent<KIND, BS, 4>, 256, 0));
+    QT_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch_persistent<KIND, BS, 4>, 64, 0));
     return std::max(1, cus * std::max(1, per_cu));
 }
 
