@@ -46,6 +46,57 @@ def measured_traffic(kernel_source: str, workload: str, prec: str):
     return rec.get("traffic_bytes")
 
 
+COPY_BYTES = 1 << 31   # plain device copy used to calibrate the traffic counters
+
+
+def calibrate_copy():
+    """A plain device-to-device copy of COPY_BYTES, three times: the reading
+    of FETCH_SIZE / WRITE_SIZE for it gives the counters' scale."""
+    import torch
+    x = torch.ones(COPY_BYTES // 8, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(3):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes": COPY_BYTES, "copies": 3}), flush=True)
+
+
+def _pmc_mean_kib(csv_path, counter, name_part):
+    import csv
+    vals = [float(r["Counter_Value"]) for r in csv.DictReader(open(csv_path))
+            if r["Counter_Name"] == counter and name_part in r["Kernel_Name"]]
+    if not vals:
+        raise SystemExit(f"no {counter} rows for kernels matching {name_part!r} in {csv_path}")
+    return sum(vals) / len(vals), len(vals)
+
+
+def traffic_from_counters(fetch_csv, write_csv, copy_fetch_csv, copy_write_csv, workload, prec, b):
+    """Writes profiles/traffic_<prec>_<workload>.json: HBM-side bytes per
+    launch of the numeric kernel from rocprofv3 --pmc FETCH_SIZE and
+    WRITE_SIZE (KiB per dispatch), each scaled so that the plain copy of
+    COPY_BYTES reads as COPY_BYTES."""
+    import hashlib
+    kname = {"f64": f"k_numeric<double, {b}>", "f32": f"k_numeric<float, {b}>",
+             "bf16x3": f"k_numeric_bf16x3<{b}>"}[prec]
+    cf, _ = _pmc_mean_kib(copy_fetch_csv, "FETCH_SIZE", "copyBuffer")
+    cw, _ = _pmc_mean_kib(copy_write_csv, "WRITE_SIZE", "copyBuffer")
+    f_scale = COPY_BYTES / (cf * 1024.0)
+    w_scale = COPY_BYTES / (cw * 1024.0)
+    kf, nf = _pmc_mean_kib(fetch_csv, "FETCH_SIZE", kname)
+    kw, nw = _pmc_mean_kib(write_csv, "WRITE_SIZE", kname)
+    fetch = kf * 1024.0 * f_scale
+    write = kw * 1024.0 * w_scale
+    src = os.path.join(ROOT, "paper_1501_07800_amd", "csrc", "qt_numeric.hip")
+    rec = {"kernel": kname, "workload": workload, "prec": prec,
+           "fetch_kib_per_dispatch": kf, "write_kib_per_dispatch": kw, "dispatches": [nf, nw],
+           "copy_fetch_kib": cf, "copy_write_kib": cw, "fetch_scale": f_scale, "write_scale": w_scale,
+           "fetch_bytes": fetch, "write_bytes": write, "traffic_bytes": fetch + write,
+           "source_sha256": hashlib.sha256(open(src, "rb").read()).hexdigest()}
+    out = os.path.join(ROOT, "profiles", f"traffic_{prec}_{workload}.json")
+    json.dump(rec, open(out, "w"), indent=1)
+    print(json.dumps(rec), flush=True)
+
+
 def timed_steps(qt, torch, hA, prec, steps, warmup):
     for _ in range(warmup):
         qt.multiply(hA, hA, prec).free()
@@ -163,7 +214,15 @@ def main():
     ap.add_argument("--prec", default="f64", choices=["f64", "f32", "bf16x3"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-paths", action="store_true", help="time only --prec")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run the plain copy that calibrates the traffic counters")
+    ap.add_argument("--traffic-from", nargs=4, metavar=("FETCH_CSV", "WRITE_CSV", "COPY_FETCH_CSV", "COPY_WRITE_CSV"),
+                    help="write the numeric kernel's measured traffic for --workload/--prec from rocprofv3 "
+                         "counter_collection.csv files (no GPU needed)")
     args = ap.parse_args()
+    if args.traffic_from:
+        import workloads as wl
+        return traffic_from_counters(*args.traffic_from, args.workload, args.prec, wl.CONFIGS[args.workload]["b"])
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the multiply has no multi-GPU path in this build "
               "(see the sharding paragraph of the design notes).", file=sys.stderr)
@@ -176,6 +235,8 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(2)
+    if args.calibrate_copy:
+        return calibrate_copy()
     import paper_1501_07800_amd as qt
 
     if args.workload == "batch64":

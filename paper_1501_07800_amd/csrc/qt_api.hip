@@ -47,7 +47,7 @@ static void profile_drain() {
         QT_HIP(hipEventSynchronize(ev.e2));
         float a = 0, b = 0;
         QT_HIP(hipEventElapsedTime(&a, ev.e0, ev.e1));
-        QT_HIP(hipEventElapsedTime(&b, ev.e1, ev.e2));
+        QT_HIP(hipEventElapsedTime(&b, ev.e3, ev.e2));
         g_prof_sym += a;
         g_prof_num += b;
         g_prof_calls += 1;
@@ -56,6 +56,7 @@ static void profile_drain() {
         (void)hipEventDestroy(ev.e0);
         (void)hipEventDestroy(ev.e1);
         (void)hipEventDestroy(ev.e2);
+        (void)hipEventDestroy(ev.e3);
     }
     g_prof_events.clear();
 }

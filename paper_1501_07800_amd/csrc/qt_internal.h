@@ -234,7 +234,9 @@ constexpr int kBatchVariants = 4;
 
 // profiling ----------------------------------------------------------------
 bool profiling_on();
-struct PhaseEvents { hipEvent_t e0, e1, e2; int64_t products, cblocks; };
+// e0 .. e1: symbolic kernels; e3 .. e2: the numeric launch (recorded after
+// the host has read C's size, so host latency falls in neither interval).
+struct PhaseEvents { hipEvent_t e0, e1, e2, e3; int64_t products, cblocks; };
 void profile_push(const PhaseEvents& ev);
 
 // multiply.hip -------------------------------------------------------------

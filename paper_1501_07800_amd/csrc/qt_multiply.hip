@@ -271,11 +271,12 @@ struct TopArgs {
     TreeStep step[TOP_MAX_LEVELS];
 };
 
-__device__ __forceinline__ void wg_sync() {
-    __threadfence();
-    __syncthreads();
-    __threadfence();
-}
+// Every step of the top levels is done by this one workgroup, and all its
+// waves share one CU and its L1, so a workgroup barrier (which orders global
+// as well as LDS accesses at workgroup scope) makes one step's global writes
+// visible to the next; no device-scope fence (an L2 write-back and
+// invalidate on this GPU) is needed.
+__device__ __forceinline__ void wg_sync() { __syncthreads(); }
 
 __device__ void wg_scan_i64(const int64_t* in, int64_t* out, int32_t n, int64_t* lds_waves) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -662,6 +663,7 @@ void symbolic(qt_matrix* A, qt_matrix* B, qt_prec prec, hipStream_t s, SymbolicO
         QT_HIP(hipEventCreate(&ev.e0));
         QT_HIP(hipEventCreate(&ev.e1));
         QT_HIP(hipEventCreate(&ev.e2));
+        QT_HIP(hipEventCreate(&ev.e3));
         QT_HIP(hipEventRecord(ev.e0, s));
     }
 
@@ -808,6 +810,7 @@ void symbolic(qt_matrix* A, qt_matrix* B, qt_prec prec, hipStream_t s, SymbolicO
 qt_matrix* multiply(qt_matrix* A, qt_matrix* B, qt_prec prec, hipStream_t s, const MulOp& op) {
     SymbolicOut sym;
     symbolic(A, B, prec, s, sym, true, op);
+    if (sym.prof) QT_HIP(hipEventRecord(sym.ev.e3, s));
     if (sym.na.nseg > 0) launch_numeric(sym.na, s);
     if (sym.prof) {
         QT_HIP(hipEventRecord(sym.ev.e2, s));
