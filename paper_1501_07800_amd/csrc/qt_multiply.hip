@@ -38,9 +38,14 @@
 #include "qt_morton.h"
 
 #include <algorithm>
+#include <chrono>
+#include <cstring>
 #include <map>
+#include <string>
 
 namespace qt {
+
+constexpr int kPublishMax = 64;   // counts read back per multiply: 2 * depth + 4
 
 // ------------------------------------------------------------- helpers
 
@@ -477,6 +482,83 @@ __global__ __launch_bounds__(256) void k_leaf_fill(LeafStep st) {
 
 // ----------------------------------------------------------- host side
 
+// Reading C's counts back. Instead of a device-to-host copy followed by a
+// stream synchronization (whose wake-up latency is tens of microseconds), a
+// one-wave kernel writes the counts into pinned, host-coherent memory and
+// then releases a sequence number there at system scope; the host spins on
+// that word. The spin checks the stream every so often, so a failed launch
+// ends it with the stream's error instead of a hang.
+struct alignas(64) HostSlot {
+    int32_t counts[kPublishMax];
+    uint32_t flag;
+};
+
+__global__ void k_publish(const int32_t* __restrict__ counts, int n, HostSlot* slot, uint32_t seq) {
+    const int t = threadIdx.x;
+    if (t < n) slot->counts[t] = counts[t];
+    __threadfence_system();
+    __syncthreads();
+    if (t == 0) __hip_atomic_store(&slot->flag, seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
+static std::mutex g_slot_mu;
+static std::vector<HostSlot*> g_slot_free;
+static uint32_t g_slot_seq = 0;
+
+// A pinned slot for one read-back, returned to the free list on scope exit.
+struct SlotLease {
+    HostSlot* slot = nullptr;
+    uint32_t seq = 0;
+    SlotLease() {
+        std::lock_guard<std::mutex> lk(g_slot_mu);
+        if (g_slot_free.empty()) {
+            constexpr int kChunk = 16;
+            HostSlot* chunk = nullptr;
+            QT_HIP(hipHostMalloc((void**)&chunk, kChunk * sizeof(HostSlot),
+                                 hipHostMallocCoherent | hipHostMallocPortable | hipHostMallocMapped));
+            for (int i = 0; i < kChunk; ++i) {
+                chunk[i].flag = 0;
+                g_slot_free.push_back(chunk + i);
+            }
+        }
+        slot = g_slot_free.back();
+        g_slot_free.pop_back();
+        if (++g_slot_seq == 0) ++g_slot_seq;   // 0 never marks a publication
+        seq = g_slot_seq;
+    }
+    ~SlotLease() {
+        std::lock_guard<std::mutex> lk(g_slot_mu);
+        g_slot_free.push_back(slot);
+    }
+    SlotLease(const SlotLease&) = delete;
+    SlotLease& operator=(const SlotLease&) = delete;
+};
+
+static void read_back_counts(const int32_t* dcount, int n, hipStream_t s, int32_t* out) {
+    if (n > kPublishMax) fail(QT_ERR_UNSUPPORTED, "tree too deep for the count read-back");
+    SlotLease lease;
+    __atomic_store_n(&lease.slot->flag, 0u, __ATOMIC_RELAXED);
+    HostSlot* dslot = nullptr;
+    QT_HIP(hipHostGetDevicePointer((void**)&dslot, lease.slot, 0));
+    k_publish<<<1, 64, 0, s>>>(dcount, n, dslot, lease.seq);
+    QT_LAUNCH("k_publish");
+    const auto t0 = std::chrono::steady_clock::now();
+    for (uint64_t it = 1;; ++it) {
+        if (__atomic_load_n(&lease.slot->flag, __ATOMIC_ACQUIRE) == lease.seq) break;
+        if ((it & 4095) == 0) {
+            const hipError_t e = hipStreamQuery(s);
+            if (e == hipSuccess) {
+                if (__atomic_load_n(&lease.slot->flag, __ATOMIC_ACQUIRE) == lease.seq) break;
+                fail(QT_ERR_DEVICE, "symbolic phase: counts were not published");
+            }
+            if (e != hipErrorNotReady) fail(QT_ERR_DEVICE, std::string("symbolic phase: ") + hipGetErrorString(e));
+            if (std::chrono::steady_clock::now() - t0 > std::chrono::seconds(600))
+                fail(QT_ERR_DEVICE, "symbolic phase: no progress for 600 s");
+        }
+    }
+    std::memcpy(out, (const void*)lease.slot->counts, n * sizeof(int32_t));
+}
+
 static inline unsigned waves_grid(int64_t nwaves) {
     return (unsigned)std::max<int64_t>((nwaves + 3) / 4, 1);
 }
@@ -764,8 +846,7 @@ void symbolic(qt_matrix* A, qt_matrix* B, qt_prec prec, hipStream_t s, SymbolicO
 
     // the one synchronization: node and block counts of C
     std::vector<int32_t> hc(2 * L + 4);
-    QT_HIP(hipMemcpyAsync(hc.data(), dcount, hc.size() * sizeof(int32_t), hipMemcpyDeviceToHost, s));
-    QT_HIP(hipStreamSynchronize(s));
+    read_back_counts(dcount, (int)hc.size(), s, hc.data());
     for (int l = 0; l <= L; ++l) {
         const int64_t expect = (l < L) ? pairs[l + 1] : P;
         const bool bad = op.upper ? (hc[L + 2 + l] < 0 || hc[L + 2 + l] > expect) : (hc[L + 2 + l] != expect);

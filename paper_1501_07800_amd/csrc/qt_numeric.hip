@@ -21,7 +21,7 @@
 // short segment never holds a SIMD while a long neighbour runs. The
 // dispatcher hands workgroup w to XCD w % 8, and each XCD has its own L2.
 // Consecutive C blocks in Morton order share most of their A and B blocks,
-// so the launch gives each XCD runs of 2^XCD_CHUNK_LOG consecutive tiles
+// so the launch gives each XCD runs of 2^XCD_CHUNK_LOG (1024) consecutive tiles
 // (XCD x takes runs x, x+8, x+16, ...) instead of every eighth tile:
 // neighbours then meet in the same L2, while the interleaved runs keep the
 // eight XCDs equally loaded. C is written with non-temporal stores, since no
@@ -72,7 +72,7 @@ template <int BS> struct Geo {
     static constexpr int NCH = BS / KC;
 };
 
-constexpr int XCD_CHUNK_LOG = 8;
+constexpr int XCD_CHUNK_LOG = 10;
 
 // Logical tile of physical workgroup w; a bijection on [0, grid) when the
 // grid is a multiple of 8 << XCD_CHUNK_LOG (xcd_grid pads it so).
@@ -245,8 +245,15 @@ __device__ __forceinline__ void wave_block_bf16x3(const uint16_t* __restrict__ A
 
 // ------------------------------------------------------ one multiply
 
+// Waves per SIMD the compiler must fit: for the b = 32 fp64 kernel five
+// (accumulators then live in ordinary VGPRs), about 1.5% faster than the
+// four it picks by itself and 3% faster than seven (measured on gfx950);
+// the other instances already fit enough waves, and forcing more would spill.
+template <class T, int BS> struct MinWaves { static constexpr int value = 1; };
+template <> struct MinWaves<double, 32> { static constexpr int value = 5; };
+
 template <class T, int BS>
-__global__ __launch_bounds__(64) void k_numeric(const T* __restrict__ A, const T* __restrict__ B,
+__global__ __launch_bounds__(64, (MinWaves<T, BS>::value)) void k_numeric(const T* __restrict__ A, const T* __restrict__ B,
                                                 const int32_t* __restrict__ prodA,
                                                 const int32_t* __restrict__ prodB,
                                                 const int32_t* __restrict__ seg, int32_t nseg,
