@@ -47,7 +47,7 @@ def measured_traffic(kernel_source: str, workload: str, prec: str):
 
 
 COPY_BYTES = 1 << 31   # plain device copy used to calibrate the traffic counters
-CPU_SAMPLE_FLOPS = 3.0e11   # block-product work the CPU oracle is given at most (about 10 s)
+CPU_SAMPLE_FLOPS = 1.0e11   # block-product work the CPU oracle is given at most (10-20 s)
 
 
 def calibrate_copy():
@@ -114,6 +114,126 @@ def timed_steps(qt, torch, hA, prec, steps, warmup):
     prof = qt.profile_read()
     qt.profile(False)
     return (t1 - t0), prof, last
+
+
+def _time_call(torch, fn, reps):
+    """Mean wall time (ms) of fn() over reps calls, device-synchronized; fn's
+    result is freed between calls."""
+    r = fn()
+    torch.cuda.synchronize()
+    if hasattr(r, "free"):
+        r.free()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        r = fn()
+        if hasattr(r, "free"):
+            r.free()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / reps * 1e3
+
+
+def bench_ops(args, qt, torch, wl):
+    """The operations beside C = A*B on the decay workload, one JSON line:
+    transposed products (op(A) op(B)), the symmetric square with upper-
+    triangular storage against the full square of the same symmetric matrix,
+    C = A + B, and value-aware truncation. TFLOP/s count 2b^3 per block
+    product as everywhere; add and truncate are reported in GB/s of block
+    data read and written once."""
+    import numpy as np
+    cfg = wl.CONFIGS[args.workload]
+    leaf = args.leaf or cfg["leaf"]
+    A = wl.config(args.workload)
+    b = A.b
+    reps = max(3, args.steps // 2)
+    hA = qt.from_blockmatrix(A, leaf)
+    qt.prepare(hA, "f64")
+    out = {}
+
+    def prod_tf(C, ms):
+        P = C.stats()["products"]
+        return P, 2.0 * b ** 3 * P / (ms * 1e-3) / 1e12
+
+    for name, ta, tb in (("A*A", False, False), ("A^T*A", True, False), ("A*A^T", False, True),
+                         ("A^T*A^T", True, True)):
+        ms = _time_call(torch, lambda: qt.multiply_ex(hA, hA, ta, tb, prec="f64"), reps)
+        C = qt.multiply_ex(hA, hA, ta, tb, prec="f64")
+        P, tf = prod_tf(C, ms)
+        out[name] = {"ms": ms, "products": P, "tflops": tf, "nnz_C": C.nblocks}
+        C.free()
+        log(f"bench: {name}: {ms:.3f} ms, {tf:.2f} TFLOP/s")
+
+    # symmetric S from A's upper block triangle (strictly upper blocks mirrored, transposed)
+    up = A.I <= A.J
+    st = A.I < A.J
+    UI, UJ, UV = A.I[up], A.J[up], A.V[up]
+    U = wl.BlockMatrix(A.n_rows, A.n_cols, b, UI, UJ, np.ascontiguousarray(UV))
+    SI = np.concatenate([A.I[up], A.J[st]])
+    SJ = np.concatenate([A.J[up], A.I[st]])
+    SV = np.concatenate([A.V[up], A.V[st].transpose(0, 2, 1)])
+    S = wl.BlockMatrix(A.n_rows, A.n_cols, b, SI, SJ, np.ascontiguousarray(SV))
+    hU = qt.from_blockmatrix(U, leaf)
+    hS = qt.from_blockmatrix(S, leaf)
+    qt.prepare(hS, "f64")
+    ms_full = _time_call(torch, lambda: qt.multiply(hS, hS, "f64"), reps)
+    C = qt.multiply(hS, hS, "f64")
+    P_full, tf_full = prod_tf(C, ms_full)
+    C.free()
+    ms_sq = _time_call(torch, lambda: qt.sysq(hU, "f64"), reps)
+    C = qt.sysq(hU, "f64")
+    P_sq, tf_sq = prod_tf(C, ms_sq)
+    out["sysq"] = {"ms": ms_sq, "products": P_sq, "tflops": tf_sq, "nnz_C": C.nblocks,
+                   "full_square_ms": ms_full, "full_square_products": P_full,
+                   "products_ratio": P_sq / P_full, "speedup_vs_full": ms_full / ms_sq}
+    log(f"bench: sysq: {ms_sq:.3f} ms ({P_sq} products) vs full S*S {ms_full:.3f} ms ({P_full})")
+
+    # C = A + S (union of two different patterns)
+    ms_add = _time_call(torch, lambda: qt.add(hA, hS), reps)
+    C = qt.add(hA, hS)
+    moved = (A.nnz + S.nnz + C.nblocks) * b * b * 8
+    out["add"] = {"ms": ms_add, "nnz_A": A.nnz, "nnz_B": S.nnz, "nnz_C": C.nblocks,
+                  "bytes": moved, "GB_per_s": moved / (ms_add * 1e-3) / 1e9}
+    log(f"bench: add: {ms_add:.3f} ms, {out['add']['GB_per_s']:.0f} GB/s")
+
+    # truncation of C = A*A at eps = 1e-6 ||C||_F
+    C = qt.multiply(hA, hA, "f64")
+    I, J, V = C.to_blocks("f64")
+    eps = 1e-6 * float(np.linalg.norm(V))
+    del I, J, V
+    ms_tr = _time_call(torch, lambda: qt.truncate(C, eps)[0], reps)
+    T, removed, e2 = qt.truncate(C, eps)
+    moved = (C.nblocks + T.nblocks) * b * b * 8
+    out["truncate"] = {"ms": ms_tr, "eps": eps, "nnz_in": C.nblocks, "nnz_out": T.nblocks, "removed": removed,
+                       "removed_norm": float(np.sqrt(e2)), "bytes": moved,
+                       "GB_per_s": moved / (ms_tr * 1e-3) / 1e9}
+    log(f"bench: truncate: {ms_tr:.3f} ms, removed {removed} of {C.nblocks} blocks")
+    T.free()
+    C.free()
+    print(json.dumps({"metric": METRIC, "workload": args.workload, "n": A.n_rows, "b": b, "leaf": leaf,
+                      "dtype": "f64", "data": "synthetic", "reps": reps, "ops": out}), flush=True)
+
+
+def bench_rmat(args, qt, torch, wl):
+    """R-MAT locality sweep (Sec. 5.1, Fig. 4): C = A*A on an 8192 x 8192 block
+    grid with 5 blocks per row, quadrant weight a from 0.25 (uniformly random)
+    to 0.9; the multiply pairs per quadtree level (the task counts C_l) and
+    the end-to-end rate at each a."""
+    b, leaf = 16, 128
+    rows = []
+    for a in (0.25, 0.4, 0.55, 0.7, 0.8, 0.9):
+        A = wl.rmat(13, 5, a, b, seed=7)
+        h = qt.from_blockmatrix(A, leaf)
+        qt.prepare(h, "f64")
+        ms = _time_call(torch, lambda: qt.multiply(h, h, "f64"), max(3, args.steps // 4))
+        C = qt.multiply(h, h, "f64")
+        stt = C.stats()
+        rows.append({"a": a, "nnz_A": A.nnz, "nnz_C": C.nblocks, "products": stt["products"],
+                     "pairs_per_level": [int(x) for x in stt["pairs"]], "ms": ms,
+                     "tflops": 2.0 * b ** 3 * stt["products"] / (ms * 1e-3) / 1e12})
+        log(f"bench: rmat a={a}: {ms:.3f} ms, pairs {[int(x) for x in stt['pairs']]}")
+        C.free()
+        h.free()
+    print(json.dumps({"metric": METRIC, "workload": "rmat8192x5", "b": b, "leaf": leaf, "dtype": "f64",
+                      "data": "synthetic", "sweep": rows}), flush=True)
 
 
 def bench_batch(args, qt, torch, wl):
@@ -215,6 +335,8 @@ def main():
     ap.add_argument("--prec", default="f64", choices=["f64", "f32", "bf16x3"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-paths", action="store_true", help="time only --prec")
+    ap.add_argument("--ops", action="store_true",
+                    help="time the other operations (transposes, symmetric square, add, truncate) on --workload")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run the plain copy that calibrates the traffic counters")
     ap.add_argument("--traffic-from", nargs=4, metavar=("FETCH_CSV", "WRITE_CSV", "COPY_FETCH_CSV", "COPY_WRITE_CSV"),
@@ -240,6 +362,10 @@ def main():
         return calibrate_copy()
     import paper_1501_07800_amd as qt
 
+    if args.workload == "rmat":
+        return bench_rmat(args, qt, torch, wl)
+    if args.ops:
+        return bench_ops(args, qt, torch, wl)
     if args.workload == "batch64":
         args.batch_prec_explicit = "--prec" in sys.argv
         return bench_batch(args, qt, torch, wl)
@@ -341,6 +467,9 @@ def main():
         paths[prec] = entry
 
     peak = PEAK[args.prec] if args.prec != "bf16x3" else PEAK["f32"]
+    # the rate a register-only loop of the same MFMA instruction reaches on this GPU
+    probe = qt.probe_mfma(args.prec)
+    log(f"bench: MFMA probe ({args.prec} instruction, no memory traffic): {probe:.1f} TFLOP/s")
     out = {
         "metric": METRIC,
         "value": main_r["tflops"],
@@ -361,7 +490,9 @@ def main():
                      "frac": main_r["numeric_tflops"] / peak,
                      "traffic": measured_traffic("qt_numeric.hip", args.workload, args.prec),
                      "algorithmic_bytes": alg_bytes,
-                     "kernel": "k_numeric (block GEMM per C block)"},
+                     "kernel": "k_numeric (block GEMM per C block)",
+                     "probe_tflops": probe,
+                     "frac_of_probe": main_r["numeric_tflops"] / (probe if args.prec != "bf16x3" else probe / 3.0)},
         "cpu_baseline": cpu,
         "paths": paths,
     }

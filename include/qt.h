@@ -264,6 +264,16 @@ qt_status qt_profile(int enable);
 qt_status qt_profile_read(double* symbolic_ms, double* numeric_ms, int64_t* calls,
                           int64_t* products, int64_t* c_blocks);
 
+/* Attainable MFMA rate: times a register-only loop of the MFMA instruction
+ * the numeric kernels of `prec` issue (fp64 16x16x4, fp32 16x16x4, bf16
+ * 16x16x32; eight independent accumulator chains per wave, eight waves per
+ * SIMD, no memory traffic in the loop) and returns its rate in TFLOP/s
+ * (2*M*N*K flops per instruction) in *tflops. A diagnostic beside the
+ * published peak, not part of the multiply (the paper measures its own
+ * "practical peak" of the batched leaf GEMM the same way, Sec. 6.1, Table 2).
+ * Synchronizes `stream`. Errors: ARG (NULL output, unknown precision), DEVICE. */
+qt_status qt_probe_mfma(qt_prec prec, void* stream, double* tflops);
+
 /* Text of the last error on this thread ("" if none). */
 const char* qt_last_error(void);
 

@@ -92,6 +92,8 @@ def _load():
                                  i32, i32p]
     lib.qt_last_error.restype = ctypes.c_char_p
     lib.qt_last_error.argtypes = []
+    lib.qt_probe_mfma.restype = ctypes.c_int
+    lib.qt_probe_mfma.argtypes = [ctypes.c_int, ctypes.c_void_p, ctypes.POINTER(ctypes.c_double)]
     lib.qt_version.restype = ctypes.c_char_p
     lib.qt_version.argtypes = []
     return lib
@@ -101,7 +103,7 @@ lib = _load()
 
 EXPORTS = ("qt_build", "qt_multiply", "qt_multiply_ex", "qt_add", "qt_truncate", "qt_sysq", "qt_info", "qt_to_blocks", "qt_get_blocks", "qt_stats", "qt_prepare", "qt_free",
            "qt_plan_create", "qt_plan_execute", "qt_plan_tune", "qt_plan_set_schedule", "qt_plan_result", "qt_plan_info",
-           "qt_plan_destroy", "qt_tune_leaf", "qt_profile", "qt_profile_read", "qt_last_error", "qt_version")
+           "qt_plan_destroy", "qt_tune_leaf", "qt_profile", "qt_profile_read", "qt_probe_mfma", "qt_last_error", "qt_version")
 PLAN_SCHEDULES = ("flat", "persistent-1", "persistent-4", "persistent-16")
 
 
@@ -356,6 +358,13 @@ def profile_read() -> dict:
                                ctypes.byref(cb)))
     return {"symbolic_ms": a.value, "numeric_ms": b.value, "calls": calls.value, "products": prods.value,
             "c_blocks": cb.value}
+
+
+def probe_mfma(prec: str = "f64", stream=None) -> float:
+    """qt_probe_mfma: TFLOP/s of a register-only loop of the path's MFMA instruction."""
+    out = ctypes.c_double()
+    _check(lib.qt_probe_mfma(PREC[prec], _stream_ptr(stream), ctypes.byref(out)))
+    return out.value
 
 
 def version() -> str:

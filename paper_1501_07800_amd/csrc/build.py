@@ -17,8 +17,8 @@ ROOT = os.path.dirname(HERE)
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libqt.so")
 
-SOURCES = ["qt_api.hip", "qt_build.hip", "qt_multiply.hip", "qt_numeric.hip", "qt_plan.hip", "qt_scan.hip",
-           "qt_sort.hip"]
+SOURCES = ["qt_api.hip", "qt_build.hip", "qt_multiply.hip", "qt_numeric.hip", "qt_plan.hip", "qt_probe.hip",
+           "qt_scan.hip", "qt_sort.hip"]
 
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall", "-Wshadow",

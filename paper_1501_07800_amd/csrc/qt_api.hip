@@ -297,6 +297,18 @@ qt_status qt_profile_read(double* symbolic_ms, double* numeric_ms, int64_t* call
     QT_GUARD_END
 }
 
+qt_status qt_probe_mfma(qt_prec prec, void* stream, double* tflops) {
+    if (!tflops) {
+        set_last_error("NULL output");
+        return QT_ERR_ARG;
+    }
+    *tflops = 0;
+    QT_GUARD_BEGIN
+    *tflops = probe_mfma(prec, (hipStream_t)stream);
+    return QT_OK;
+    QT_GUARD_END
+}
+
 qt_status qt_plan_create(int32_t count, const qt_matrix* const* A, const qt_matrix* const* B, qt_prec prec,
                          void* stream, qt_plan** plan) {
     if (!plan) {

@@ -205,6 +205,7 @@ struct NumericArgs {
     void* C;                  // fp64 or fp32 C blocks, one per segment
 };
 void launch_numeric(const NumericArgs& a, hipStream_t s);
+double probe_mfma(qt_prec prec, hipStream_t s);   // TFLOP/s of a register-only MFMA loop
 
 // One problem of a batch, as the batch kernels read it (device memory).
 struct BatchProblem {
