@@ -399,6 +399,22 @@ def main():
                          "numeric_tflops": flops / (num_ms * 1e-3) / 1e12, "nnz_C": C.nblocks}
         log(f"bench: {prec}: {tflops:.2f} TFLOP/s end to end, numeric {num_ms:.3f} ms, symbolic {sym_ms:.3f} ms")
 
+    # the same multiply with the boundary's host buffers included: build from
+    # host block lists (PCIe in), multiply, copy C back to host (PCIe out)
+    pcie_ms = None
+    if not args.no_paths:
+        reps_h = 3
+        t0 = time.perf_counter()
+        for _ in range(reps_h):
+            h = qt.from_blockmatrix(A, leaf)
+            Ch = qt.multiply(h, h, args.prec)
+            Ch.to_blocks("f32" if args.prec == "f32" else "f64")
+            Ch.free()
+            h.free()
+        torch.cuda.synchronize()
+        pcie_ms = (time.perf_counter() - t0) / reps_h * 1e3
+        log(f"bench: {args.prec} host to host (build from host arrays + multiply + C to host): {pcie_ms:.1f} ms")
+
     main_r = results[args.prec]
     P = main_r["P"]
     flops = 2.0 * b ** 3 * P
@@ -494,6 +510,9 @@ def main():
                      "probe_tflops": probe,
                      "frac_of_probe": main_r["numeric_tflops"] / (probe if args.prec != "bf16x3" else probe / 3.0)},
         "cpu_baseline": cpu,
+        "host_to_host": None if pcie_ms is None else {
+            "ms": pcie_ms, "tflops": flops / (pcie_ms * 1e-3) / 1e12,
+            "what": "qt_build from host block lists + qt_multiply + qt_to_blocks to host (PCIe both ways)"},
         "paths": paths,
     }
     print(json.dumps(out), flush=True)

@@ -179,11 +179,25 @@ def add(A: BlockMatrix, B: BlockMatrix, leaf: int, lib=None):
     return _take(lib, out, A.n_rows, A.n_cols, b, {"from": "oracle add", "leaf": leaf})
 
 
+def _morton(I, J):
+    """Bit-interleaved position of block (I, J): column bits at even, row bits
+    at odd positions (the Z order of the quadtree's children 2m + n)."""
+    key = np.zeros(len(I), np.uint64)
+    I = np.asarray(I, np.uint64)
+    J = np.asarray(J, np.uint64)
+    for bit in range(32):
+        one = np.uint64(1)
+        key |= ((J >> np.uint64(bit)) & one) << np.uint64(2 * bit)
+        key |= ((I >> np.uint64(bit)) & one) << np.uint64(2 * bit + 1)
+    return key
+
+
 def truncate(M: BlockMatrix, eps: float):
-    """Drop blocks in order of increasing Frobenius norm while the norm of all
-    removed blocks stays below eps (||M - T||_F < eps). Returns (T, removed)."""
+    """Drop blocks in order of increasing Frobenius norm (equal norms: quadtree
+    Z order first) while the norm of all removed blocks stays below eps
+    (||M - T||_F < eps). Returns (T, removed)."""
     n2 = (M.V.reshape(M.nnz, -1) ** 2).sum(axis=1)
-    order = np.argsort(n2, kind="stable")
+    order = np.lexsort((_morton(M.I, M.J), n2))
     run = np.cumsum(n2[order])
     k = int(np.count_nonzero(run < eps * eps))
     keep = np.ones(M.nnz, bool)

@@ -1,5 +1,7 @@
 // Key/value sort used when a matrix is built or copied out (outside the
-// multiply): a bitonic network over a power-of-two padded array.
+// multiply): a bitonic network over a power-of-two padded array. Pairs are
+// ordered by (key, value), so equal keys come out in ascending value order
+// (the callers pass positions as values: a deterministic tie-break).
 #include "qt_internal.h"
 
 namespace qt {
@@ -20,12 +22,13 @@ __global__ void k_bitonic_step(uint64_t* keys, int32_t* vals, int64_t npow2, int
     if (l <= i) return;
     const bool up = (i & k) == 0;
     uint64_t ki = keys[i], kl = keys[l];
-    if ((ki > kl) == up) {
+    const int32_t vi = vals[i], vl = vals[l];
+    const bool greater = (ki > kl) || (ki == kl && vi > vl);
+    if (greater == up) {
         keys[i] = kl;
         keys[l] = ki;
-        int32_t t = vals[i];
-        vals[i] = vals[l];
-        vals[l] = t;
+        vals[i] = vl;
+        vals[l] = vi;
     }
 }
 

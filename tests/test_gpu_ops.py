@@ -194,6 +194,24 @@ def test_truncate_matches_definition(qt):
         assert e2 < eps * eps and abs(e2 - lo) <= 1e-12 * max(lo, 1e-300)
 
 
+def test_truncate_equal_norms_follow_z_order(qt):
+    """All blocks of equal norm: which ones go is decided by the tie rule
+    (quadtree Z order first), the same on the GPU as in the oracle."""
+    rng = np.random.default_rng(14)
+    b = 16
+    M = random_pattern(rng, 64, 64, 0.2, b)
+    M.V[:] = 0.0
+    M.V[:, 0, 0] = 1.0
+    h = qt.from_blockmatrix(M, 4 * b)
+    for k_target in (1, 5, M.nnz // 3, M.nnz - 1):
+        eps = float(np.sqrt(k_target + 0.5))
+        ref, k = oracle.truncate(M, eps)
+        T, removed, _ = qt.truncate(h, eps)
+        assert removed == k == k_target
+        got = _blocks(T, M.n_rows, M.n_cols, b)
+        assert np.array_equal(positions(got), positions(wl.BlockMatrix(M.n_rows, M.n_cols, b, *_sorted(ref))))
+
+
 def _sorted(M):
     o = np.lexsort((M.J, M.I))
     return M.I[o], M.J[o], M.V[o]

@@ -329,3 +329,20 @@ def test_truncation_definition():
             nxt = np.sort(norms[[t for t in range(M.nnz) if t not in removed]])[0]
             assert np.sqrt(np.sum(norms[removed] ** 2) + nxt ** 2) >= eps
         assert np.array_equal(to_dense(T)[to_dense(T) != 0], to_dense(M)[to_dense(T) != 0])
+
+
+def test_truncation_ties_follow_z_order():
+    """Equal block norms are removed in quadtree (Z) order: on a 2 x 2 block
+    grid of unit-norm blocks, eps^2 = 2.5 removes exactly two blocks, the
+    top-left and then the top-right one (children 0 and 1 of the root)."""
+    b = 2
+    I = np.array([1, 1, 0, 0], np.int32)
+    J = np.array([1, 0, 1, 0], np.int32)
+    V = np.zeros((4, b, b))
+    V[:, 0, 0] = 1.0                                   # every block has norm 1
+    M = wl.BlockMatrix(2 * b, 2 * b, b, I, J, V)
+    T, k = oracle.truncate(M, float(np.sqrt(2.5)))
+    assert k == 2
+    assert sorted(zip(T.I.tolist(), T.J.tolist())) == [(1, 0), (1, 1)]
+    T, k = oracle.truncate(M, float(np.sqrt(3.5)))
+    assert k == 3 and list(zip(T.I.tolist(), T.J.tolist())) == [(1, 1)]
