@@ -76,13 +76,15 @@ constexpr int XCD_CHUNK_LOG = 10;
 
 // Logical tile of physical workgroup w; a bijection on [0, grid) when the
 // grid is a multiple of 8 << XCD_CHUNK_LOG (xcd_grid pads it so).
+template <int LOG = XCD_CHUNK_LOG>
 __device__ __forceinline__ int64_t xcd_logical(int64_t w) {
     const int64_t x = w & 7, i = w >> 3;
-    return ((((i >> XCD_CHUNK_LOG) << 3) + x) << XCD_CHUNK_LOG) | (i & ((1 << XCD_CHUNK_LOG) - 1));
+    return ((((i >> LOG) << 3) + x) << LOG) | (i & ((1 << LOG) - 1));
 }
 
+template <int LOG = XCD_CHUNK_LOG>
 static unsigned xcd_grid(int64_t tiles) {
-    const int64_t q = int64_t(8) << XCD_CHUNK_LOG;
+    const int64_t q = int64_t(8) << LOG;
     const int64_t g = (tiles + q - 1) / q * q;
     if (g > 0x7fffffffLL) fail(QT_ERR_UNSUPPORTED, "numeric launch too large");
     return (unsigned)g;
@@ -259,7 +261,7 @@ __global__ __launch_bounds__(64, (MinWaves<T, BS>::value)) void k_numeric(const 
                                                 const int32_t* __restrict__ seg, int32_t nseg,
                                                 T* __restrict__ C) {
     typedef Geo<BS> G;
-    const int64_t tile = xcd_logical(blockIdx.x);
+    const int64_t tile = xcd_logical<>(blockIdx.x);
     const int64_t s = tile / G::WPB;
     if (s >= nseg) return;
     wave_block<T, BS>(A, B, prodA, prodB, seg[s], seg[s + 1], C + (size_t)s * (BS * BS), (int)(tile % G::WPB));
@@ -275,7 +277,7 @@ __global__ __launch_bounds__(64) void k_numeric_bf16x3(const uint16_t* __restric
                                                        const int32_t* __restrict__ seg, int32_t nseg,
                                                        double* __restrict__ C) {
     constexpr int WPB = (BS / 32) * (BS / 32);
-    const int64_t tile = xcd_logical(blockIdx.x);
+    const int64_t tile = xcd_logical<>(blockIdx.x);
     const int64_t s = tile / WPB;
     if (s >= nseg) return;
     wave_block_bf16x3<BS>(Ahi, Alo, Bhi_t, Blo_t, prodA, prodB, seg[s], seg[s + 1], C + (size_t)s * (BS * BS),
@@ -285,16 +287,138 @@ __global__ __launch_bounds__(64) void k_numeric_bf16x3(const uint16_t* __restric
 template <class T, int BS>
 static void launch_t(const NumericArgs& a, hipStream_t s) {
     typedef Geo<BS> G;
-    const unsigned grid = xcd_grid((int64_t)a.nseg * G::WPB);
+    const unsigned grid = xcd_grid<>((int64_t)a.nseg * G::WPB);
     k_numeric<T, BS><<<grid, 64, 0, s>>>((const T*)a.A, (const T*)a.B, a.prodA, a.prodB, a.seg, a.nseg,
                                          (T*)a.C);
     QT_LAUNCH("k_numeric");
 }
 
+// b = 64 split-bf16 with the operands shared through LDS. One workgroup of
+// four waves owns a 64 x 64 C block, wave w the 32 x 32 tile (w / 2, w % 2).
+// Per block product the hi and lo parts of A and of B^T (8 KiB each) are
+// staged in LDS once and each wave reads its 32-row panels from there, so a
+// product moves 32 KiB from L2 instead of 64 KiB (two waves share every A
+// panel and every B panel). Four workgroups share a CU (36 KiB of LDS each),
+// so one workgroup's loads overlap the others' MFMAs. LDS rows are padded to 72
+// elements (144 bytes) so the 16 lanes reading 16 consecutive rows hit
+// distinct banks.
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));   // a 16-byte piece, kept in VGPRs
+constexpr int BFL_ROW = 72;
+constexpr int BFL_ARR = 64 * BFL_ROW;      // elements per staged block
+
+__global__ __launch_bounds__(256, 2) void k_numeric_bf16x3_b64(const uint16_t* __restrict__ Ahi,
+                                                                const uint16_t* __restrict__ Alo,
+                                                                const uint16_t* __restrict__ Bhi_t,
+                                                                const uint16_t* __restrict__ Blo_t,
+                                                                const int32_t* __restrict__ prodA,
+                                                                const int32_t* __restrict__ prodB,
+                                                                const int32_t* __restrict__ seg, int32_t nseg,
+                                                                double* __restrict__ C) {
+    constexpr int BS = 64, MT = 2;
+    __shared__ __attribute__((aligned(16))) uint16_t lds[4 * BFL_ARR];   // Ahi, Alo, Bhi^T, Blo^T
+    const int64_t s = xcd_logical<8>(blockIdx.x);
+    if (s >= nseg) return;   // uniform over the workgroup
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int r16 = lane & 15, g = lane >> 4;
+    const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+    const int32_t t0 = seg[s], t1 = seg[s + 1];
+
+    // thread tid moves 16-byte pieces tid and tid + 256 of each 64 x 64 block:
+    // piece q is row q / 8, elements 8 * (q % 8) .. + 7
+    const uint16_t* const base4[4] = {Ahi, Alo, Bhi_t, Blo_t};
+    u32x4 st0, st1, st2, st3, st4, st5, st6, st7;   // [block m][half h] = st(2m + h)
+#define QT_BFL_FETCH(t)                                                                             \
+    do {                                                                                            \
+        const size_t oa_ = (size_t)prodA[t] * (BS * BS), ob_ = (size_t)prodB[t] * (BS * BS);        \
+        st0 = *reinterpret_cast<const u32x4*>(base4[0] + oa_ + (size_t)tid * 8);                    \
+        st1 = *reinterpret_cast<const u32x4*>(base4[0] + oa_ + (size_t)(tid + 256) * 8);            \
+        st2 = *reinterpret_cast<const u32x4*>(base4[1] + oa_ + (size_t)tid * 8);                    \
+        st3 = *reinterpret_cast<const u32x4*>(base4[1] + oa_ + (size_t)(tid + 256) * 8);            \
+        st4 = *reinterpret_cast<const u32x4*>(base4[2] + ob_ + (size_t)tid * 8);                    \
+        st5 = *reinterpret_cast<const u32x4*>(base4[2] + ob_ + (size_t)(tid + 256) * 8);            \
+        st6 = *reinterpret_cast<const u32x4*>(base4[3] + ob_ + (size_t)tid * 8);                    \
+        st7 = *reinterpret_cast<const u32x4*>(base4[3] + ob_ + (size_t)(tid + 256) * 8);            \
+    } while (0)
+    const int q0 = ((tid >> 3) * BFL_ROW + (tid & 7) * 8);                  // LDS offset of piece tid
+    const int q1 = (((tid + 256) >> 3) * BFL_ROW + (tid & 7) * 8);          // and of piece tid + 256
+
+    v4d acc[MT][MT];
+#pragma unroll
+    for (int i = 0; i < MT; ++i)
+#pragma unroll
+        for (int j = 0; j < MT; ++j) acc[i][j] = v4d{0, 0, 0, 0};
+
+    for (int32_t t = t0; t < t1; ++t) {
+        QT_BFL_FETCH(t);   // issued before the barrier: overlaps the other waves' previous product
+        __syncthreads();   // every wave is done reading the previous product
+        *reinterpret_cast<u32x4*>(lds + 0 * BFL_ARR + q0) = st0;
+        *reinterpret_cast<u32x4*>(lds + 0 * BFL_ARR + q1) = st1;
+        *reinterpret_cast<u32x4*>(lds + 1 * BFL_ARR + q0) = st2;
+        *reinterpret_cast<u32x4*>(lds + 1 * BFL_ARR + q1) = st3;
+        *reinterpret_cast<u32x4*>(lds + 2 * BFL_ARR + q0) = st4;
+        *reinterpret_cast<u32x4*>(lds + 2 * BFL_ARR + q1) = st5;
+        *reinterpret_cast<u32x4*>(lds + 3 * BFL_ARR + q0) = st6;
+        *reinterpret_cast<u32x4*>(lds + 3 * BFL_ARR + q1) = st7;
+        __syncthreads();
+        v4f f[MT][MT];
+#pragma unroll
+        for (int i = 0; i < MT; ++i)
+#pragma unroll
+            for (int j = 0; j < MT; ++j) f[i][j] = v4f{0, 0, 0, 0};
+#pragma unroll
+        for (int kc = 0; kc < BS / 32; ++kc) {
+            v8bf ah[MT], al[MT], bh[MT], bl[MT];
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt) {
+                const int o = (wm + mt * 16 + r16) * BFL_ROW + kc * 32 + g * 8;
+                __builtin_memcpy(&ah[mt], lds + 0 * BFL_ARR + o, 16);
+                __builtin_memcpy(&al[mt], lds + 1 * BFL_ARR + o, 16);
+            }
+#pragma unroll
+            for (int nt = 0; nt < MT; ++nt) {
+                const int o = (wn + nt * 16 + r16) * BFL_ROW + kc * 32 + g * 8;
+                __builtin_memcpy(&bh[nt], lds + 2 * BFL_ARR + o, 16);
+                __builtin_memcpy(&bl[nt], lds + 3 * BFL_ARR + o, 16);
+            }
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+                for (int nt = 0; nt < MT; ++nt) {
+                    f[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[mt], bh[nt], f[mt][nt], 0, 0, 0);
+                    f[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[mt], bl[nt], f[mt][nt], 0, 0, 0);
+                    f[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[mt], bh[nt], f[mt][nt], 0, 0, 0);
+                }
+        }
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+            for (int nt = 0; nt < MT; ++nt)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) acc[mt][nt][i] += (double)f[mt][nt][i];
+    }
+    double* c = C + (size_t)s * (BS * BS);
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+        for (int nt = 0; nt < MT; ++nt)
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+                __builtin_nontemporal_store(acc[mt][nt][i], c + (wm + mt * 16 + 4 * g + i) * BS + wn + nt * 16 + r16);
+#undef QT_BFL_FETCH
+}
+
 template <int BS>
 static void launch_bf(const NumericArgs& a, hipStream_t s) {
+    if (BS == 64) {
+        const unsigned grid = xcd_grid<8>(a.nseg);
+        k_numeric_bf16x3_b64<<<grid, 256, 0, s>>>(a.Ahi, a.Alo, a.Bhi_t, a.Blo_t, a.prodA, a.prodB, a.seg,
+                                                  a.nseg, (double*)a.C);
+        QT_LAUNCH("k_numeric_bf16x3_b64");
+        return;
+    }
     constexpr int WPB = (BS / 32) * (BS / 32);
-    const unsigned grid = xcd_grid((int64_t)a.nseg * WPB);
+    const unsigned grid = xcd_grid<>((int64_t)a.nseg * WPB);
     k_numeric_bf16x3<BS><<<grid, 64, 0, s>>>(a.Ahi, a.Alo, a.Bhi_t, a.Blo_t, a.prodA, a.prodB, a.seg, a.nseg,
                                              (double*)a.C);
     QT_LAUNCH("k_numeric_bf16x3");
@@ -397,7 +521,7 @@ template <int BS> struct Item<2, BS> {   // split bf16
 template <int KIND, int BS>
 __global__ __launch_bounds__(64) void k_batch_flat(const BatchProblem* __restrict__ probs,
                                                    const int64_t* __restrict__ item_base, int32_t nprob) {
-    const int64_t it = xcd_logical(blockIdx.x);
+    const int64_t it = xcd_logical<>(blockIdx.x);
     if (it >= item_base[nprob]) return;
     Item<KIND, BS>::run(probs, item_base, nprob, it);
 }
@@ -425,7 +549,7 @@ __global__ void k_batch_reset(unsigned long long* counter) { *counter = 0ull; }
 template <int KIND, int BS>
 static void launch_batch_kb(const BatchLaunch& L, hipStream_t s) {
     if (L.variant == 0) {
-        const unsigned grid = xcd_grid(L.total_items);
+        const unsigned grid = xcd_grid<>(L.total_items);
         k_batch_flat<KIND, BS><<<grid, 64, 0, s>>>(L.probs, L.item_base, L.nprob);
         QT_LAUNCH("k_batch_flat");
         return;

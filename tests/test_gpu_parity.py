@@ -241,17 +241,17 @@ def test_bf16x3_split_form_is_what_is_computed(qt):
     accumulation inside one block product: dropping a cross term or a wrong
     split would exceed this much tighter bound."""
     from oracle.precision import split_bf16, with_values
-    b = 32
-    rng = np.random.default_rng(41)
-    A = random_pattern(rng, 24, 24, 0.2, b)
-    hi, lo = split_bf16(A.V)
-    Ah, Al = with_values(A, hi), with_values(A, lo)
-    hh, _ = oracle.multiply(Ah, Ah, 4 * b)
-    hl, _ = oracle.multiply(Ah, Al, 4 * b)
-    lh, _ = oracle.multiply(Al, Ah, 4 * b)
-    absAB, _ = oracle.multiply(A, A, 4 * b, use_abs=True)
-    ref = wl.BlockMatrix(A.n_rows, A.n_cols, b, hh.I, hh.J, hh.V + hl.V + lh.V)
-    C, _, _ = gpu_multiply(qt, A, A, 4 * b, "bf16x3", same=True)
-    same, e_max, e_f, e_cw = compare(ref, C, absAB)
-    assert same
-    assert e_cw <= 1.05 * (3 * b + 4) * 2.0 ** -24, e_cw
+    for b in (32, 64):
+        rng = np.random.default_rng(41 + b)
+        A = random_pattern(rng, 24, 24, 0.2, b)
+        hi, lo = split_bf16(A.V)
+        Ah, Al = with_values(A, hi), with_values(A, lo)
+        hh, _ = oracle.multiply(Ah, Ah, 4 * b)
+        hl, _ = oracle.multiply(Ah, Al, 4 * b)
+        lh, _ = oracle.multiply(Al, Ah, 4 * b)
+        absAB, _ = oracle.multiply(A, A, 4 * b, use_abs=True)
+        ref = wl.BlockMatrix(A.n_rows, A.n_cols, b, hh.I, hh.J, hh.V + hl.V + lh.V)
+        C, _, _ = gpu_multiply(qt, A, A, 4 * b, "bf16x3", same=True)
+        same, e_max, e_f, e_cw = compare(ref, C, absAB)
+        assert same
+        assert e_cw <= 1.05 * (3 * b + 4) * 2.0 ** -24, e_cw
