@@ -742,10 +742,10 @@ void symbolic(qt_matrix* A, qt_matrix* B, qt_prec prec, hipStream_t s, SymbolicO
     const bool prof = out.prof = allow_profile && profiling_on();
     PhaseEvents& ev = out.ev;
     if (prof) {
-        QT_HIP(hipEventCreate(&ev.e0));
-        QT_HIP(hipEventCreate(&ev.e1));
-        QT_HIP(hipEventCreate(&ev.e2));
-        QT_HIP(hipEventCreate(&ev.e3));
+        timing_event(&ev.e0);
+        timing_event(&ev.e1);
+        timing_event(&ev.e2);
+        timing_event(&ev.e3);
         QT_HIP(hipEventRecord(ev.e0, s));
     }
 

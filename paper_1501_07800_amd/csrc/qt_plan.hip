@@ -154,8 +154,8 @@ void plan_execute(qt_plan* plan, hipStream_t s, int use_graph) {
 int plan_tune(qt_plan* plan, hipStream_t s, int reps, float* ms_out) {
     if (reps <= 0) reps = 3;
     hipEvent_t e0, e1;
-    QT_HIP(hipEventCreate(&e0));
-    QT_HIP(hipEventCreate(&e1));
+    timing_event(&e0);
+    timing_event(&e1);
     int best = plan->launch.variant;
     float best_ms = -1.f;
     try {
@@ -206,8 +206,8 @@ int32_t tune_leaf(const qt_matrix* A, const qt_matrix* B, qt_prec prec, hipStrea
     if (reps <= 0) reps = 3;
     if (A->b != B->b) fail(QT_ERR_SHAPE, "operands differ in block size");
     hipEvent_t e0, e1;
-    QT_HIP(hipEventCreate(&e0));
-    QT_HIP(hipEventCreate(&e1));
+    timing_event(&e0);
+    timing_event(&e1);
     int32_t best = A->leaf;
     float best_ms = -1.f;
     int32_t k = 0;

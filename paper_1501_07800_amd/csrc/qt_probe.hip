@@ -65,8 +65,8 @@ static double probe_kind(hipStream_t s) {
     const int iters = (KIND == 2) ? 2048 : 4096;
     DBuf<float> out((size_t)wgs * 256, s);
     hipEvent_t e0, e1;
-    QT_HIP(hipEventCreate(&e0));
-    QT_HIP(hipEventCreate(&e1));
+    timing_event(&e0);
+    timing_event(&e1);
     float best = 0;
     for (int rep = 0; rep < 3; ++rep) {   // the first run also warms the clocks
         QT_HIP(hipEventRecord(e0, s));
