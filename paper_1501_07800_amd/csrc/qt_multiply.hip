@@ -101,7 +101,11 @@ struct TreeStep {
     const int32_t* Bch;
     int64_t* cnt;             // per C node: (child pairs, child C nodes)
     int4* tot4;               // per C node: child pairs per quadrant
-    int64_t* off;             // exclusive scan of cnt; off[ncap] = totals
+    int64_t* off;             // exclusive scan of cnt; off[ncap] = totals (scan path)
+                              // or each node's offset inside its workgroup (aggregate path)
+    int64_t* wagg;            // aggregate path: per count workgroup, the sum of its nodes' cnt
+    int64_t* gsum;            // aggregate path: per group of 64 count workgroups, their sum (zeroed first)
+    int use_agg;              // offsets from workgroup aggregates instead of a scan
     int32_t ncap;             // bound on C nodes (= pairs at this level)
     // next level
     int32_t* nfa;
@@ -135,10 +139,10 @@ __device__ __forceinline__ bool quadrant_dropped(int upper, uint64_t key, int mn
     return upper && mn == 2 && morton_row(key) == morton_col(key);
 }
 
-__device__ void tree_count_node(const TreeStep& st, int32_t c, int lane) {
+__device__ int64_t tree_count_node(const TreeStep& st, int32_t c, int lane) {
     if (c >= *st.ncount) {
         if (lane == 0) st.cnt[c] = 0;
-        return;
+        return 0;
     }
     const int32_t s0 = st.cseg[c], len = st.cseg[c + 1] - s0;
     int t0 = 0, t1 = 0, t2 = 0, t3 = 0;
@@ -158,22 +162,25 @@ __device__ void tree_count_node(const TreeStep& st, int32_t c, int lane) {
     t1 = wave_sum(t1);
     t2 = wave_sum(t2);
     t3 = wave_sum(t3);
+    const int64_t v = pack2(t0 + t1 + t2 + t3, (t0 > 0) + (t1 > 0) + (t2 > 0) + (t3 > 0));
     if (lane == 0) {
-        st.cnt[c] = pack2(t0 + t1 + t2 + t3, (t0 > 0) + (t1 > 0) + (t2 > 0) + (t3 > 0));
+        st.cnt[c] = v;
         st.tot4[c] = make_int4(t0, t1, t2, t3);
     }
+    return v;
 }
 
-__device__ void tree_fill_node(const TreeStep& st, int32_t c, int lane) {
-    if (c == 0 && lane == 0) {
-        const int64_t T = st.off[st.ncap];
-        const int32_t nc_next = hi32(T);
-        *st.ncount_next = nc_next;
-        if (nc_next <= st.np_next) st.ncseg[nc_next] = lo32(T);
-        *st.check = lo32(T);
-    }
+// Totals T = (child pairs, child C nodes) of a whole level.
+__device__ void tree_level_totals(const TreeStep& st, int64_t T) {
+    const int32_t nc_next = hi32(T);
+    *st.ncount_next = nc_next;
+    if (nc_next <= st.np_next) st.ncseg[nc_next] = lo32(T);
+    *st.check = lo32(T);
+}
+
+// o: (first child pair, first child C node) of node c in the next level.
+__device__ void tree_fill_node(const TreeStep& st, int32_t c, int lane, int64_t o) {
     if (c >= *st.ncount) return;
-    const int64_t o = st.off[c];
     const int4 t4 = st.tot4[c];
     const int t[4] = {t4.x, t4.y, t4.z, t4.w};
     int run[4], cid[4];
@@ -235,14 +242,93 @@ __device__ void tree_fill_node(const TreeStep& st, int32_t c, int lane) {
     }
 }
 
-__global__ __launch_bounds__(256) void k_tree_count(TreeStep st) {
-    const int32_t c = (int32_t)((blockIdx.x * 256u + threadIdx.x) >> 6);
-    if (c < st.ncap) tree_count_node(st, c, threadIdx.x & 63);
+// The per-level kernels run LEVEL_WAVES waves (one C node each) per
+// workgroup. On the aggregate path the count kernel stores each node's offset
+// inside its workgroup, one aggregate per workgroup, and adds it into the sum
+// of its group of 64 workgroups (an integer atomic add: exact in any order);
+// a fill workgroup then finds the offset of its first node as the sum of the
+// group sums before its group plus the aggregates before it in its group,
+// with no separate scan launch. Levels beyond AGG_MAX workgroups take the scan.
+constexpr int LEVEL_WAVES = 4;
+constexpr int LEVEL_THREADS = 64 * LEVEL_WAVES;
+constexpr int AGG_GROUP_LOG = 6;
+constexpr int32_t AGG_MAX = 65536;   // workgroups per level on the aggregate path
+
+__device__ __forceinline__ int64_t wave_sum64(int64_t x) {
+#pragma unroll
+    for (int d = 32; d > 0; d >>= 1) x += __shfl_xor(x, d, 64);
+    return x;
 }
 
-__global__ __launch_bounds__(256) void k_tree_fill(TreeStep st) {
-    const int32_t c = (int32_t)((blockIdx.x * 256u + threadIdx.x) >> 6);
-    if (c < st.ncap) tree_fill_node(st, c, threadIdx.x & 63);
+// Aggregate path, count side: node offsets inside the workgroup and the
+// workgroup's aggregate, from each wave's packed count v.
+__device__ __forceinline__ void level_local_offsets(int64_t v, int32_t c, int32_t ncap, int64_t* off,
+                                                    int64_t* wagg, int64_t* gsum, int64_t* lds) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane == 0) lds[wave] = v;
+    __syncthreads();
+    if (lane == 0 && c < ncap) {
+        int64_t pre = 0;
+        for (int w = 0; w < wave; ++w) pre += lds[w];
+        off[c] = pre;
+    }
+    if (threadIdx.x == 0) {
+        int64_t tot = 0;
+        for (int w = 0; w < LEVEL_WAVES; ++w) tot += lds[w];
+        wagg[blockIdx.x] = tot;
+        if (tot) atomicAdd((unsigned long long*)(gsum + (blockIdx.x >> AGG_GROUP_LOG)), (unsigned long long)tot);
+    }
+}
+
+// Aggregate path, fill side: the sum of the aggregates of all earlier
+// workgroups (every thread gets it).
+__device__ __forceinline__ int64_t level_base(const int64_t* wagg, const int64_t* gsum, int64_t* lds) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int32_t b = (int32_t)blockIdx.x, g = b >> AGG_GROUP_LOG, first = g << AGG_GROUP_LOG;
+    int64_t part = 0;
+    for (int32_t i = threadIdx.x; i < g; i += LEVEL_THREADS) part += gsum[i];
+    for (int32_t i = first + threadIdx.x; i < b; i += LEVEL_THREADS) part += wagg[i];
+    part = wave_sum64(part);
+    if (lane == 0) lds[wave] = part;
+    __syncthreads();
+    int64_t base = 0;
+    for (int w = 0; w < LEVEL_WAVES; ++w) base += lds[w];
+    return base;
+}
+
+// Only the first ncount of the ncap node slots hold C nodes: on the aggregate
+// path a workgroup whose slots are all past ncount has a zero aggregate and
+// nothing to fill, and only the last workgroup (which writes the level's
+// totals) still runs.
+__device__ __forceinline__ bool level_wg_empty(const int32_t* ncount) {
+    return (int64_t)blockIdx.x * LEVEL_WAVES >= *ncount;
+}
+
+__global__ __launch_bounds__(LEVEL_THREADS) void k_tree_count(TreeStep st) {
+    __shared__ int64_t lds[LEVEL_WAVES];
+    if (st.use_agg && level_wg_empty(st.ncount)) {
+        if (threadIdx.x == 0) st.wagg[blockIdx.x] = 0;
+        return;
+    }
+    const int32_t c = (int32_t)(blockIdx.x * LEVEL_WAVES + (threadIdx.x >> 6));
+    int64_t v = 0;
+    if (c < st.ncap) v = tree_count_node(st, c, threadIdx.x & 63);
+    if (st.use_agg) level_local_offsets(v, c, st.ncap, st.off, st.wagg, st.gsum, lds);
+}
+
+__global__ __launch_bounds__(LEVEL_THREADS) void k_tree_fill(TreeStep st) {
+    __shared__ int64_t lds[LEVEL_WAVES];
+    const int32_t c = (int32_t)(blockIdx.x * LEVEL_WAVES + (threadIdx.x >> 6));
+    const int lane = threadIdx.x & 63;
+    if (st.use_agg) {
+        if (level_wg_empty(st.ncount) && blockIdx.x != gridDim.x - 1) return;
+        const int64_t base = level_base(st.wagg, st.gsum, lds);
+        if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) tree_level_totals(st, base + st.wagg[blockIdx.x]);
+        if (c < st.ncap) tree_fill_node(st, c, lane, base + st.off[c]);
+    } else {
+        if (c == 0 && lane == 0) tree_level_totals(st, st.off[st.ncap]);
+        if (c < st.ncap) tree_fill_node(st, c, lane, st.off[c]);
+    }
 }
 
 // Level-0 frontier: the pair of roots, one C node.
@@ -252,18 +338,24 @@ struct RootInit {
     int32_t* cseg;
     uint64_t* ckey;
     int32_t* ncount;
+    int64_t* zero;            // the group sums of all levels, cleared here
+    int64_t nzero;
 };
 
+// Run by every thread of the first kernel of the traversal.
 __device__ void root_init(const RootInit& r) {
-    r.fa[0] = 0;
-    r.fb[0] = 0;
-    r.cseg[0] = 0;
-    r.cseg[1] = 1;
-    r.ckey[0] = 0;
-    r.ncount[0] = 1;
+    for (int64_t i = threadIdx.x; i < r.nzero; i += blockDim.x) r.zero[i] = 0;
+    if (threadIdx.x == 0) {
+        r.fa[0] = 0;
+        r.fb[0] = 0;
+        r.cseg[0] = 0;
+        r.cseg[1] = 1;
+        r.ckey[0] = 0;
+        r.ncount[0] = 1;
+    }
 }
 
-__global__ void k_root_init(RootInit r) { root_init(r); }
+__global__ __launch_bounds__(256) void k_root_init(RootInit r) { root_init(r); }
 
 // The top levels in one workgroup: count, workgroup scan, fill, per level.
 constexpr int TOP_THREADS = 1024;
@@ -312,7 +404,7 @@ __device__ void wg_scan_i64(const int64_t* in, int64_t* out, int32_t n, int64_t*
 __global__ __launch_bounds__(TOP_THREADS) void k_tree_top(TopArgs args) {
     __shared__ int64_t lds_waves[TOP_THREADS / 64];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    if (threadIdx.x == 0) root_init(args.root);
+    root_init(args.root);
     wg_sync();
     for (int l = 0; l < args.nlev; ++l) {
         const TreeStep& st = args.step[l];
@@ -320,7 +412,8 @@ __global__ __launch_bounds__(TOP_THREADS) void k_tree_top(TopArgs args) {
         wg_sync();
         wg_scan_i64(st.cnt, st.off, st.ncap, lds_waves);
         wg_sync();
-        for (int32_t c = wave; c < st.ncap; c += TOP_THREADS / 64) tree_fill_node(st, c, lane);
+        if (threadIdx.x == 0) tree_level_totals(st, st.off[st.ncap]);
+        for (int32_t c = wave; c < st.ncap; c += TOP_THREADS / 64) tree_fill_node(st, c, lane, st.off[c]);
         wg_sync();
     }
 }
@@ -342,7 +435,10 @@ struct LeafStep {
     const int32_t* Abase;
     const int32_t* Bbase;
     int64_t* cnt;             // per C leaf: (products, C blocks)
-    int64_t* off;
+    int64_t* off;             // scan path: exclusive scan of cnt; aggregate path: offset inside the workgroup
+    int64_t* wagg;            // aggregate path: per count workgroup, the sum of its leaves' cnt
+    int64_t* gsum;            // aggregate path: per group of 64 count workgroups, their sum (zeroed first)
+    int use_agg;
     int32_t* prodA;
     int32_t* prodB;
     int32_t P;
@@ -385,10 +481,10 @@ __device__ int leaf_lane_count(const LeafStep& st, int32_t s0, int32_t len, int 
     return cnt;
 }
 
-__device__ void leaf_count_node(const LeafStep& st, int32_t c, int lane) {
+__device__ int64_t leaf_count_node(const LeafStep& st, int32_t c, int lane) {
     if (c >= *st.ncount) {
         if (lane == 0) st.cnt[c] = 0;
-        return;
+        return 0;
     }
     const int lb = 1 << st.lb_log;
     const int i = (int)morton_row((uint64_t)lane), j = (int)morton_col((uint64_t)lane);
@@ -397,24 +493,27 @@ __device__ void leaf_count_node(const LeafStep& st, int32_t c, int lane) {
     const int cnt = leaf_lane_count(st, s0, len, lane, i, j, lb, on);
     const uint64_t em = __ballot(cnt > 0);
     const int tot = wave_sum(cnt);
-    if (lane == 0) st.cnt[c] = pack2(tot, __popcll(em));
+    const int64_t v = pack2(tot, __popcll(em));
+    if (lane == 0) st.cnt[c] = v;
+    return v;
 }
 
-__device__ void leaf_fill_node(const LeafStep& st, int32_t c, int lane) {
-    if (c == 0 && lane == 0) {
-        const int64_t T = st.off[st.ncap];
-        const int32_t nb = hi32(T);
-        *st.nblocks_out = nb;
-        if (nb <= st.cap) st.cbseg[nb] = lo32(T);
-        *st.check = lo32(T);
-    }
+// Totals T = (block products, C blocks) of the leaf level.
+__device__ void leaf_level_totals(const LeafStep& st, int64_t T) {
+    const int32_t nb = hi32(T);
+    *st.nblocks_out = nb;
+    if (nb <= st.cap) st.cbseg[nb] = lo32(T);
+    *st.check = lo32(T);
+}
+
+// o: (first product, first C block) of leaf c.
+__device__ void leaf_fill_node(const LeafStep& st, int32_t c, int lane, int64_t o) {
     if (c >= *st.ncount) return;
     const int lb = 1 << st.lb_log;
     const int i = (int)morton_row((uint64_t)lane), j = (int)morton_col((uint64_t)lane);
     const bool on = lane < lb * lb && leaf_block_kept(st, st.ckey[c], i, j);
     const int32_t s0 = st.cseg[c], len = st.cseg[c + 1] - s0;
     const int cnt = leaf_lane_count(st, s0, len, lane, i, j, lb, on);
-    const int64_t o = st.off[c];
     const bool exists = cnt > 0;
     const uint64_t em = __ballot(exists);
     const int32_t bidx = hi32(o) + __popcll(em & lanes_below(lane));
@@ -470,14 +569,31 @@ __device__ void leaf_fill_node(const LeafStep& st, int32_t c, int lane) {
     }
 }
 
-__global__ __launch_bounds__(256) void k_leaf_count(LeafStep st) {
-    const int32_t c = (int32_t)((blockIdx.x * 256u + threadIdx.x) >> 6);
-    if (c < st.ncap) leaf_count_node(st, c, threadIdx.x & 63);
+__global__ __launch_bounds__(LEVEL_THREADS) void k_leaf_count(LeafStep st) {
+    __shared__ int64_t lds[LEVEL_WAVES];
+    if (st.use_agg && level_wg_empty(st.ncount)) {
+        if (threadIdx.x == 0) st.wagg[blockIdx.x] = 0;
+        return;
+    }
+    const int32_t c = (int32_t)(blockIdx.x * LEVEL_WAVES + (threadIdx.x >> 6));
+    int64_t v = 0;
+    if (c < st.ncap) v = leaf_count_node(st, c, threadIdx.x & 63);
+    if (st.use_agg) level_local_offsets(v, c, st.ncap, st.off, st.wagg, st.gsum, lds);
 }
 
-__global__ __launch_bounds__(256) void k_leaf_fill(LeafStep st) {
-    const int32_t c = (int32_t)((blockIdx.x * 256u + threadIdx.x) >> 6);
-    if (c < st.ncap) leaf_fill_node(st, c, threadIdx.x & 63);
+__global__ __launch_bounds__(LEVEL_THREADS) void k_leaf_fill(LeafStep st) {
+    __shared__ int64_t lds[LEVEL_WAVES];
+    const int32_t c = (int32_t)(blockIdx.x * LEVEL_WAVES + (threadIdx.x >> 6));
+    const int lane = threadIdx.x & 63;
+    if (st.use_agg) {
+        if (level_wg_empty(st.ncount) && blockIdx.x != gridDim.x - 1) return;
+        const int64_t base = level_base(st.wagg, st.gsum, lds);
+        if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) leaf_level_totals(st, base + st.wagg[blockIdx.x]);
+        if (c < st.ncap) leaf_fill_node(st, c, lane, base + st.off[c]);
+    } else {
+        if (c == 0 && lane == 0) leaf_level_totals(st, st.off[st.ncap]);
+        if (c < st.ncap) leaf_fill_node(st, c, lane, st.off[c]);
+    }
 }
 
 // ----------------------------------------------------------- host side
@@ -559,9 +675,8 @@ static void read_back_counts(const int32_t* dcount, int n, hipStream_t s, int32_
     std::memcpy(out, (const void*)lease.slot->counts, n * sizeof(int32_t));
 }
 
-static inline unsigned waves_grid(int64_t nwaves) {
-    return (unsigned)std::max<int64_t>((nwaves + 3) / 4, 1);
-}
+// Workgroups of the per-level kernels for n C nodes (one wave each).
+static inline int64_t level_wgs(int64_t n) { return std::max<int64_t>((n + LEVEL_WAVES - 1) / LEVEL_WAVES, 1); }
 
 // A device-resident child table {0, -1, -1, -1}: the single node of a level
 // added above a shallower operand so both trees have the same depth (the
@@ -711,7 +826,10 @@ void symbolic(qt_matrix* A, qt_matrix* B, qt_prec prec, hipStream_t s, SymbolicO
     const size_t o_lrm = keep.take(pairs[L] * sizeof(uint64_t));
     const size_t o_lcm = keep.take(pairs[L] * sizeof(uint64_t));
     const size_t o_bkey = keep.take(cap * sizeof(uint64_t));
-    std::vector<size_t> o_fa(L + 1), o_fb(L + 1), o_cseg(L + 1), o_cnt(L + 1), o_off(L + 1), o_tot(L + 1);
+    std::vector<size_t> o_fa(L + 1), o_fb(L + 1), o_cseg(L + 1), o_cnt(L + 1), o_off(L + 1), o_tot(L + 1),
+        o_wagg(L + 1);
+    std::vector<int64_t> gsum_at(L + 1);
+    int64_t gsum_total = 0;
     size_t scan_elems = 0;
     for (int l = 0; l <= L; ++l) {
         o_fa[l] = tmp.take(pairs[l] * sizeof(int32_t));
@@ -720,8 +838,12 @@ void symbolic(qt_matrix* A, qt_matrix* B, qt_prec prec, hipStream_t s, SymbolicO
         o_cnt[l] = tmp.take(pairs[l] * sizeof(int64_t));
         o_off[l] = tmp.take((pairs[l] + 1) * sizeof(int64_t));
         o_tot[l] = tmp.take(pairs[l] * sizeof(int4));
+        o_wagg[l] = tmp.take(level_wgs(pairs[l]) * sizeof(int64_t));
+        gsum_at[l] = gsum_total;
+        gsum_total += (level_wgs(pairs[l]) + (1 << AGG_GROUP_LOG) - 1) >> AGG_GROUP_LOG;
         scan_elems = std::max(scan_elems, scan_tmp_elems(pairs[l]));
     }
+    const size_t o_gsum = tmp.take(std::max<int64_t>(gsum_total, 1) * sizeof(int64_t));
     const size_t o_scan = tmp.take((scan_elems + 1) * sizeof(int64_t));
     const size_t o_prodA = tmp.take(P * sizeof(int32_t));
     const size_t o_prodB = tmp.take(P * sizeof(int32_t));
@@ -761,6 +883,8 @@ void symbolic(qt_matrix* A, qt_matrix* B, qt_prec prec, hipStream_t s, SymbolicO
         st.Bch = (l < liftB) ? lift : B->levels[l - liftB].child.p;
         st.cnt = (int64_t*)at(W, o_cnt[l]);
         st.tot4 = (int4*)at(W, o_tot[l]);
+        st.wagg = (int64_t*)at(W, o_wagg[l]);
+        st.gsum = (int64_t*)at(W, o_gsum) + gsum_at[l];
         st.off = (int64_t*)at(W, o_off[l]);
         st.ncap = (int32_t)pairs[l];
         st.nfa = (int32_t*)at(W, o_fa[l + 1]);
@@ -777,7 +901,7 @@ void symbolic(qt_matrix* A, qt_matrix* B, qt_prec prec, hipStream_t s, SymbolicO
         return st;
     };
     RootInit root{(int32_t*)at(W, o_fa[0]), (int32_t*)at(W, o_fb[0]), (int32_t*)at(W, o_cseg[0]),
-                  (uint64_t*)at(K, o_key[0]), dcount};
+                  (uint64_t*)at(K, o_key[0]), dcount, (int64_t*)at(W, o_gsum), gsum_total};
 
     // top levels in one workgroup, while the frontier stays small
     int ltop = 0;
@@ -791,16 +915,19 @@ void symbolic(qt_matrix* A, qt_matrix* B, qt_prec prec, hipStream_t s, SymbolicO
         k_tree_top<<<1, TOP_THREADS, 0, s>>>(ta);
         QT_LAUNCH("k_tree_top");
     } else {
-        k_root_init<<<1, 1, 0, s>>>(root);
+        k_root_init<<<1, 256, 0, s>>>(root);
         QT_LAUNCH("k_root_init");
     }
     int64_t* scan_tmp = (int64_t*)at(W, o_scan);
     for (int l = ltop; l < L; ++l) {
         const TreeStep st = tree_step(l);
-        k_tree_count<<<waves_grid(pairs[l]), 256, 0, s>>>(st);
+        TreeStep sl = st;
+        const int64_t wgs = level_wgs(pairs[l]);
+        sl.use_agg = wgs <= AGG_MAX;
+        k_tree_count<<<(unsigned)wgs, LEVEL_THREADS, 0, s>>>(sl);
         QT_LAUNCH("k_tree_count");
-        exclusive_scan(st.cnt, st.off, pairs[l], scan_tmp, s);
-        k_tree_fill<<<waves_grid(pairs[l]), 256, 0, s>>>(st);
+        if (!sl.use_agg) exclusive_scan(sl.cnt, sl.off, pairs[l], scan_tmp, s);
+        k_tree_fill<<<(unsigned)wgs, LEVEL_THREADS, 0, s>>>(sl);
         QT_LAUNCH("k_tree_fill");
     }
 
@@ -825,6 +952,10 @@ void symbolic(qt_matrix* A, qt_matrix* B, qt_prec prec, hipStream_t s, SymbolicO
     ls.Bbase = B->leaves.base.p;
     ls.cnt = (int64_t*)at(W, o_cnt[L]);
     ls.off = (int64_t*)at(W, o_off[L]);
+    ls.wagg = (int64_t*)at(W, o_wagg[L]);
+    ls.gsum = (int64_t*)at(W, o_gsum) + gsum_at[L];
+    const int64_t leaf_wgs = level_wgs(pairs[L]);
+    ls.use_agg = leaf_wgs <= AGG_MAX;
     ls.prodA = (int32_t*)at(W, o_prodA);
     ls.prodB = (int32_t*)at(W, o_prodB);
     ls.P = (int32_t)P;
@@ -837,10 +968,10 @@ void symbolic(qt_matrix* A, qt_matrix* B, qt_prec prec, hipStream_t s, SymbolicO
     ls.lcm = (uint64_t*)at(K, o_lcm);
     ls.nblocks_out = dcount + L + 1;
     ls.check = dcount + 2 * L + 2;
-    k_leaf_count<<<waves_grid(pairs[L]), 256, 0, s>>>(ls);
+    k_leaf_count<<<(unsigned)leaf_wgs, LEVEL_THREADS, 0, s>>>(ls);
     QT_LAUNCH("k_leaf_count");
-    exclusive_scan(ls.cnt, ls.off, pairs[L], scan_tmp, s);
-    k_leaf_fill<<<waves_grid(pairs[L]), 256, 0, s>>>(ls);
+    if (!ls.use_agg) exclusive_scan(ls.cnt, ls.off, pairs[L], scan_tmp, s);
+    k_leaf_fill<<<(unsigned)leaf_wgs, LEVEL_THREADS, 0, s>>>(ls);
     QT_LAUNCH("k_leaf_fill");
     if (prof) QT_HIP(hipEventRecord(ev.e1, s));
 
