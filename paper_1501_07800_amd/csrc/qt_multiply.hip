@@ -12,14 +12,14 @@
 //          pairs present(A_m0) & present(B_0n) + present(A_m1) & present(B_1n)
 //          over its pairs, giving (child pairs, child C nodes) packed in an
 //          int64;
-//   scan:  one exclusive scan of those packed counts gives every C node the
-//          place of its child pairs and child C nodes in the next level;
+//   offsets: an exclusive prefix sum of those packed counts gives every C
+//          node the place of its child pairs and child C nodes in the next
+//          level (from per-workgroup aggregates, or a scan for large levels);
 //   fill:  it writes its child pairs, quadrant by quadrant, pairs in order and
 //          k' = 0 before k' = 1 (child k = 2k + k'), so the new frontier is
 //          again grouped by C node with k ascending; quadrants without pairs
 //          are NIL children and get no node.
-// The small top levels run in one workgroup (one launch for all of them); the
-// remaining levels take three launches each.
+// Each level takes two launches (count, fill), plus a scan on large levels.
 //
 // The leaf step gives a C leaf one wavefront whose lanes are the lb x lb
 // blocks of the leaf: lane (i, j) counts popcount(rowmask_A(i) & colmask_B(j))
@@ -243,13 +243,15 @@ __device__ void tree_fill_node(const TreeStep& st, int32_t c, int lane, int64_t 
 }
 
 // The per-level kernels run LEVEL_WAVES waves (one C node each) per
-// workgroup. On the aggregate path the count kernel stores each node's offset
+// workgroup: one, so that while a previous numeric kernel still fills the GPU
+// with single-wave workgroups the traversal's workgroups find room as soon as
+// any wave ends (a wider workgroup waits for several free slots on one CU). On the aggregate path the count kernel stores each node's offset
 // inside its workgroup, one aggregate per workgroup, and adds it into the sum
 // of its group of 64 workgroups (an integer atomic add: exact in any order);
 // a fill workgroup then finds the offset of its first node as the sum of the
 // group sums before its group plus the aggregates before it in its group,
 // with no separate scan launch. Levels beyond AGG_MAX workgroups take the scan.
-constexpr int LEVEL_WAVES = 4;
+constexpr int LEVEL_WAVES = 1;
 constexpr int LEVEL_THREADS = 64 * LEVEL_WAVES;
 constexpr int AGG_GROUP_LOG = 6;
 constexpr int32_t AGG_MAX = 65536;   // workgroups per level on the aggregate path
@@ -342,7 +344,7 @@ struct RootInit {
     int64_t nzero;
 };
 
-// Run by every thread of the first kernel of the traversal.
+// The first kernel of the traversal (every thread takes part in the clearing).
 __device__ void root_init(const RootInit& r) {
     for (int64_t i = threadIdx.x; i < r.nzero; i += blockDim.x) r.zero[i] = 0;
     if (threadIdx.x == 0) {
@@ -355,68 +357,7 @@ __device__ void root_init(const RootInit& r) {
     }
 }
 
-__global__ __launch_bounds__(256) void k_root_init(RootInit r) { root_init(r); }
-
-// The top levels in one workgroup: count, workgroup scan, fill, per level.
-constexpr int TOP_THREADS = 1024;
-constexpr int TOP_MAX_LEVELS = 12;
-constexpr int32_t TOP_MAX_PAIRS = 512;
-
-struct TopArgs {
-    RootInit root;
-    int32_t nlev;
-    TreeStep step[TOP_MAX_LEVELS];
-};
-
-// Every step of the top levels is done by this one workgroup, and all its
-// waves share one CU and its L1, so a workgroup barrier (which orders global
-// as well as LDS accesses at workgroup scope) makes one step's global writes
-// visible to the next; no device-scope fence (an L2 write-back and
-// invalidate on this GPU) is needed.
-__device__ __forceinline__ void wg_sync() { __syncthreads(); }
-
-__device__ void wg_scan_i64(const int64_t* in, int64_t* out, int32_t n, int64_t* lds_waves) {
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    int64_t carry = 0;
-    for (int32_t base = 0; base <= n; base += TOP_THREADS) {
-        const int32_t i = base + threadIdx.x;
-        const int64_t v = (i < n) ? in[i] : 0;
-        int64_t x = v;
-#pragma unroll
-        for (int d = 1; d < 64; d <<= 1) {
-            int64_t y = __shfl_up(x, d, 64);
-            if (lane >= d) x += y;
-        }
-        if (lane == 63) lds_waves[wave] = x;
-        __syncthreads();
-        int64_t before = 0, all = 0;
-        for (int w = 0; w < TOP_THREADS / 64; ++w) {
-            const int64_t t = lds_waves[w];
-            if (w < wave) before += t;
-            all += t;
-        }
-        if (i <= n) out[i] = carry + before + x - v;
-        carry += all;
-        __syncthreads();
-    }
-}
-
-__global__ __launch_bounds__(TOP_THREADS) void k_tree_top(TopArgs args) {
-    __shared__ int64_t lds_waves[TOP_THREADS / 64];
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    root_init(args.root);
-    wg_sync();
-    for (int l = 0; l < args.nlev; ++l) {
-        const TreeStep& st = args.step[l];
-        for (int32_t c = wave; c < st.ncap; c += TOP_THREADS / 64) tree_count_node(st, c, lane);
-        wg_sync();
-        wg_scan_i64(st.cnt, st.off, st.ncap, lds_waves);
-        wg_sync();
-        if (threadIdx.x == 0) tree_level_totals(st, st.off[st.ncap]);
-        for (int32_t c = wave; c < st.ncap; c += TOP_THREADS / 64) tree_fill_node(st, c, lane, st.off[c]);
-        wg_sync();
-    }
-}
+__global__ __launch_bounds__(64) void k_root_init(RootInit r) { root_init(r); }
 
 // ------------------------------------------------------ the leaf step
 
@@ -678,6 +619,28 @@ static void read_back_counts(const int32_t* dcount, int n, hipStream_t s, int32_
 // Workgroups of the per-level kernels for n C nodes (one wave each).
 static inline int64_t level_wgs(int64_t n) { return std::max<int64_t>((n + LEVEL_WAVES - 1) / LEVEL_WAVES, 1); }
 
+// The symbolic phase reads only the operands' structure (child tables, keys,
+// masks), which every handle has complete when the call that made it returns
+// (build and multiply both wait for it). So it runs on a library stream of its
+// own and overlaps whatever is still queued on the caller's stream -- in a
+// loop of multiplies, the previous numeric kernel. The numeric launch on the
+// caller's stream then waits for the symbolic phase through an event. The
+// stream has the default priority.
+static std::mutex g_side_mu;
+static std::map<int, hipStream_t> g_side;
+
+static hipStream_t side_stream() {
+    int dev = 0;
+    QT_HIP(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lk(g_side_mu);
+    auto it = g_side.find(dev);
+    if (it != g_side.end()) return it->second;
+    hipStream_t st = nullptr;
+    QT_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+    g_side[dev] = st;
+    return st;
+}
+
 // A device-resident child table {0, -1, -1, -1}: the single node of a level
 // added above a shallower operand so both trees have the same depth (the
 // shallower matrix sits in the top-left quadrant at every added level).
@@ -768,8 +731,9 @@ void symbolic(qt_matrix* A, qt_matrix* B, qt_prec prec, hipStream_t s, SymbolicO
         return;
     }
 
-    build_histograms(A, s);
-    build_histograms(B, s);
+    const hipStream_t ss = side_stream();   // the traversal's stream
+    build_histograms(A, ss);
+    build_histograms(B, ss);
 
     // pair counts per level and block products: exact, or upper bounds when
     // only the upper triangle of C is formed. Columns of op(A) are rows of A
@@ -854,8 +818,12 @@ void symbolic(qt_matrix* A, qt_matrix* B, qt_prec prec, hipStream_t s, SymbolicO
     qt_matrix* C = out.C.get();
     C->pairs = pairs;
     C->products = P;
-    C->arena.alloc(keep.bytes, s);
-    out.scratch.alloc(tmp.bytes, s);
+    // both live on past this call and are released on the caller's stream,
+    // after the numeric kernel that reads them
+    C->arena.alloc(keep.bytes, ss);
+    C->arena.s = s;
+    out.scratch.alloc(tmp.bytes, ss);
+    out.scratch.s = s;
     char* K = C->arena.p;
     char* W = out.scratch.p;
     auto at = [](char* base, size_t off) { return (void*)(base + off); };
@@ -868,7 +836,7 @@ void symbolic(qt_matrix* A, qt_matrix* B, qt_prec prec, hipStream_t s, SymbolicO
         timing_event(&ev.e1);
         timing_event(&ev.e2);
         timing_event(&ev.e3);
-        QT_HIP(hipEventRecord(ev.e0, s));
+        QT_HIP(hipEventRecord(ev.e0, ss));
     }
 
     const int32_t* lift = (liftA > 0 || liftB > 0) ? lift_table() : nullptr;
@@ -903,31 +871,18 @@ void symbolic(qt_matrix* A, qt_matrix* B, qt_prec prec, hipStream_t s, SymbolicO
     RootInit root{(int32_t*)at(W, o_fa[0]), (int32_t*)at(W, o_fb[0]), (int32_t*)at(W, o_cseg[0]),
                   (uint64_t*)at(K, o_key[0]), dcount, (int64_t*)at(W, o_gsum), gsum_total};
 
-    // top levels in one workgroup, while the frontier stays small
-    int ltop = 0;
-    while (ltop < L && ltop < TOP_MAX_LEVELS && pairs[ltop] <= TOP_MAX_PAIRS && pairs[ltop + 1] <= TOP_MAX_PAIRS)
-        ++ltop;
-    if (ltop > 0) {
-        TopArgs ta{};
-        ta.root = root;
-        ta.nlev = ltop;
-        for (int l = 0; l < ltop; ++l) ta.step[l] = tree_step(l);
-        k_tree_top<<<1, TOP_THREADS, 0, s>>>(ta);
-        QT_LAUNCH("k_tree_top");
-    } else {
-        k_root_init<<<1, 256, 0, s>>>(root);
-        QT_LAUNCH("k_root_init");
-    }
+    k_root_init<<<1, 64, 0, ss>>>(root);
+    QT_LAUNCH("k_root_init");
     int64_t* scan_tmp = (int64_t*)at(W, o_scan);
-    for (int l = ltop; l < L; ++l) {
+    for (int l = 0; l < L; ++l) {
         const TreeStep st = tree_step(l);
         TreeStep sl = st;
         const int64_t wgs = level_wgs(pairs[l]);
         sl.use_agg = wgs <= AGG_MAX;
-        k_tree_count<<<(unsigned)wgs, LEVEL_THREADS, 0, s>>>(sl);
+        k_tree_count<<<(unsigned)wgs, LEVEL_THREADS, 0, ss>>>(sl);
         QT_LAUNCH("k_tree_count");
-        if (!sl.use_agg) exclusive_scan(sl.cnt, sl.off, pairs[l], scan_tmp, s);
-        k_tree_fill<<<(unsigned)wgs, LEVEL_THREADS, 0, s>>>(sl);
+        if (!sl.use_agg) exclusive_scan(sl.cnt, sl.off, pairs[l], scan_tmp, ss);
+        k_tree_fill<<<(unsigned)wgs, LEVEL_THREADS, 0, ss>>>(sl);
         QT_LAUNCH("k_tree_fill");
     }
 
@@ -968,16 +923,25 @@ void symbolic(qt_matrix* A, qt_matrix* B, qt_prec prec, hipStream_t s, SymbolicO
     ls.lcm = (uint64_t*)at(K, o_lcm);
     ls.nblocks_out = dcount + L + 1;
     ls.check = dcount + 2 * L + 2;
-    k_leaf_count<<<(unsigned)leaf_wgs, LEVEL_THREADS, 0, s>>>(ls);
+    k_leaf_count<<<(unsigned)leaf_wgs, LEVEL_THREADS, 0, ss>>>(ls);
     QT_LAUNCH("k_leaf_count");
-    if (!ls.use_agg) exclusive_scan(ls.cnt, ls.off, pairs[L], scan_tmp, s);
-    k_leaf_fill<<<(unsigned)leaf_wgs, LEVEL_THREADS, 0, s>>>(ls);
+    if (!ls.use_agg) exclusive_scan(ls.cnt, ls.off, pairs[L], scan_tmp, ss);
+    k_leaf_fill<<<(unsigned)leaf_wgs, LEVEL_THREADS, 0, ss>>>(ls);
     QT_LAUNCH("k_leaf_fill");
-    if (prof) QT_HIP(hipEventRecord(ev.e1, s));
+    if (prof) QT_HIP(hipEventRecord(ev.e1, ss));
 
     // the one synchronization: node and block counts of C
     std::vector<int32_t> hc(2 * L + 4);
-    read_back_counts(dcount, (int)hc.size(), s, hc.data());
+    read_back_counts(dcount, (int)hc.size(), ss, hc.data());
+    {
+        // work the caller queues on s from here on (the numeric kernel first)
+        // follows the traversal
+        hipEvent_t done = nullptr;
+        QT_HIP(hipEventCreateWithFlags(&done, hipEventDisableTiming));
+        QT_HIP(hipEventRecord(done, ss));
+        QT_HIP(hipStreamWaitEvent(s, done, 0));
+        QT_HIP(hipEventDestroy(done));
+    }
     for (int l = 0; l <= L; ++l) {
         const int64_t expect = (l < L) ? pairs[l + 1] : P;
         const bool bad = op.upper ? (hc[L + 2 + l] < 0 || hc[L + 2 + l] > expect) : (hc[L + 2 + l] != expect);
