@@ -5,7 +5,10 @@ Workload (default): the 3D-decay matrix with 2048 atoms in a cube of side
 40, 16 basis functions per atom (n = 32768), block size 32, blocks below
 1e-10 dropped, leaf 256; inputs resident in HBM before timing. One step is
 one full qt_multiply (symbolic traversal + numeric MFMA kernel + C
-assembly). The metric counts 2*b^3 flops per nonzero block product.
+assembly), called back to back on one stream as an application would; the
+library runs each traversal on its own stream, beside the previous step's
+numeric kernel. The metric counts 2*b^3 flops per nonzero block product.
+The latency of a lone call on an idle GPU is reported beside it.
 
 Prints one JSON line with the fp64 path as the headline value, the
 roofline of the numeric kernel (HIP events on the multiply's stream), the
@@ -398,11 +401,27 @@ def main():
         flops = 2.0 * b ** 3 * P
         tflops = flops * args.steps / dt / 1e12
         num_ms = prof["numeric_ms"] / max(prof["calls"], 1)
-        sym_ms = prof["symbolic_ms"] / max(prof["calls"], 1)
+        span_ms = prof["symbolic_ms"] / max(prof["calls"], 1)
+        # one multiply on an idle GPU: the traversal's own time, and the latency of a lone call
+        single = []
+        sym_alone = []
+        for _ in range(5):
+            torch.cuda.synchronize()
+            qt.profile(True)
+            t0 = time.perf_counter()
+            qt.multiply(hA, hA, prec).free()
+            torch.cuda.synchronize()
+            single.append((time.perf_counter() - t0) * 1e3)
+            pr = qt.profile_read()
+            qt.profile(False)
+            sym_alone.append(pr["symbolic_ms"])
+        single_ms, sym_ms = float(np.median(single)), float(np.median(sym_alone))
         results[prec] = {"C": C, "P": P, "tflops": tflops, "ms_per_step": dt / args.steps * 1e3,
-                         "numeric_ms": num_ms, "symbolic_ms": sym_ms,
+                         "numeric_ms": num_ms, "symbolic_ms": sym_ms, "symbolic_span_in_loop_ms": span_ms,
+                         "single_call_ms": single_ms,
                          "numeric_tflops": flops / (num_ms * 1e-3) / 1e12, "nnz_C": C.nblocks}
-        log(f"bench: {prec}: {tflops:.2f} TFLOP/s end to end, numeric {num_ms:.3f} ms, symbolic {sym_ms:.3f} ms")
+        log(f"bench: {prec}: {tflops:.2f} TFLOP/s end to end, numeric {num_ms:.3f} ms, symbolic {sym_ms:.3f} ms "
+            f"alone ({span_ms:.3f} ms span beside the previous numeric kernel), lone call {single_ms:.3f} ms")
 
     # the same multiply with the boundary's host buffers included: build from
     # host block lists (PCIe in), multiply, copy C back to host (PCIe out)
@@ -460,7 +479,8 @@ def main():
     paths = {}
     for prec, r in results.items():
         entry = {"tflops": r["tflops"], "ms_per_step": r["ms_per_step"], "numeric_ms": r["numeric_ms"],
-                 "symbolic_ms": r["symbolic_ms"], "numeric_tflops": r["numeric_tflops"],
+                 "symbolic_ms": r["symbolic_ms"], "symbolic_span_in_loop_ms": r["symbolic_span_in_loop_ms"],
+                 "single_call_ms": r["single_call_ms"], "numeric_tflops": r["numeric_tflops"],
                  "mfma_peak_frac": r["numeric_tflops"] / (PEAK["f32"] if prec == "bf16x3" else PEAK[prec]),
                  "speedup_vs_f64": (r["tflops"] / results["f64"]["tflops"]) if "f64" in results else None}
         if ref is not None:
