@@ -242,17 +242,15 @@ __device__ void tree_fill_node(const TreeStep& st, int32_t c, int lane, int64_t 
     }
 }
 
-// The per-level kernels run LEVEL_WAVES waves (one C node each) per
-// workgroup: one, so that while a previous numeric kernel still fills the GPU
-// with single-wave workgroups the traversal's workgroups find room as soon as
-// any wave ends (a wider workgroup waits for several free slots on one CU). On the aggregate path the count kernel stores each node's offset
-// inside its workgroup, one aggregate per workgroup, and adds it into the sum
-// of its group of 64 workgroups (an integer atomic add: exact in any order);
-// a fill workgroup then finds the offset of its first node as the sum of the
-// group sums before its group plus the aggregates before it in its group,
-// with no separate scan launch. Levels beyond AGG_MAX workgroups take the scan.
-constexpr int LEVEL_WAVES = 1;
-constexpr int LEVEL_THREADS = 64 * LEVEL_WAVES;
+// The per-level kernels run W waves (one C node each) per workgroup: W = 1
+// for levels of up to WIDE_LEVEL nodes, so that while a previous numeric
+// kernel still fills the GPU with single-wave workgroups the traversal's
+// workgroups find room as soon as any wave ends (a wider workgroup waits for
+// several free slots on one CU); W = 4 above that, where the number of
+// workgroups itself costs.
+constexpr int64_t WIDE_LEVEL = 65536;
+static inline int level_waves(int64_t n) { return n <= WIDE_LEVEL ? 1 : 4; }
+
 constexpr int AGG_GROUP_LOG = 6;
 constexpr int32_t AGG_MAX = 65536;   // workgroups per level on the aggregate path
 
@@ -264,6 +262,7 @@ __device__ __forceinline__ int64_t wave_sum64(int64_t x) {
 
 // Aggregate path, count side: node offsets inside the workgroup and the
 // workgroup's aggregate, from each wave's packed count v.
+template <int W>
 __device__ __forceinline__ void level_local_offsets(int64_t v, int32_t c, int32_t ncap, int64_t* off,
                                                     int64_t* wagg, int64_t* gsum, int64_t* lds) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -276,7 +275,7 @@ __device__ __forceinline__ void level_local_offsets(int64_t v, int32_t c, int32_
     }
     if (threadIdx.x == 0) {
         int64_t tot = 0;
-        for (int w = 0; w < LEVEL_WAVES; ++w) tot += lds[w];
+        for (int w = 0; w < W; ++w) tot += lds[w];
         wagg[blockIdx.x] = tot;
         if (tot) atomicAdd((unsigned long long*)(gsum + (blockIdx.x >> AGG_GROUP_LOG)), (unsigned long long)tot);
     }
@@ -284,17 +283,18 @@ __device__ __forceinline__ void level_local_offsets(int64_t v, int32_t c, int32_
 
 // Aggregate path, fill side: the sum of the aggregates of all earlier
 // workgroups (every thread gets it).
+template <int W>
 __device__ __forceinline__ int64_t level_base(const int64_t* wagg, const int64_t* gsum, int64_t* lds) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int32_t b = (int32_t)blockIdx.x, g = b >> AGG_GROUP_LOG, first = g << AGG_GROUP_LOG;
     int64_t part = 0;
-    for (int32_t i = threadIdx.x; i < g; i += LEVEL_THREADS) part += gsum[i];
-    for (int32_t i = first + threadIdx.x; i < b; i += LEVEL_THREADS) part += wagg[i];
+    for (int32_t i = threadIdx.x; i < g; i += 64 * W) part += gsum[i];
+    for (int32_t i = first + threadIdx.x; i < b; i += 64 * W) part += wagg[i];
     part = wave_sum64(part);
     if (lane == 0) lds[wave] = part;
     __syncthreads();
     int64_t base = 0;
-    for (int w = 0; w < LEVEL_WAVES; ++w) base += lds[w];
+    for (int w = 0; w < W; ++w) base += lds[w];
     return base;
 }
 
@@ -302,29 +302,32 @@ __device__ __forceinline__ int64_t level_base(const int64_t* wagg, const int64_t
 // path a workgroup whose slots are all past ncount has a zero aggregate and
 // nothing to fill, and only the last workgroup (which writes the level's
 // totals) still runs.
+template <int W>
 __device__ __forceinline__ bool level_wg_empty(const int32_t* ncount) {
-    return (int64_t)blockIdx.x * LEVEL_WAVES >= *ncount;
+    return (int64_t)blockIdx.x * W >= *ncount;
 }
 
-__global__ __launch_bounds__(LEVEL_THREADS) void k_tree_count(TreeStep st) {
-    __shared__ int64_t lds[LEVEL_WAVES];
-    if (st.use_agg && level_wg_empty(st.ncount)) {
+template <int W>
+__global__ __launch_bounds__(64 * W) void k_tree_count(TreeStep st) {
+    __shared__ int64_t lds[W];
+    if (st.use_agg && level_wg_empty<W>(st.ncount)) {
         if (threadIdx.x == 0) st.wagg[blockIdx.x] = 0;
         return;
     }
-    const int32_t c = (int32_t)(blockIdx.x * LEVEL_WAVES + (threadIdx.x >> 6));
+    const int32_t c = (int32_t)(blockIdx.x * W + (threadIdx.x >> 6));
     int64_t v = 0;
     if (c < st.ncap) v = tree_count_node(st, c, threadIdx.x & 63);
-    if (st.use_agg) level_local_offsets(v, c, st.ncap, st.off, st.wagg, st.gsum, lds);
+    if (st.use_agg) level_local_offsets<W>(v, c, st.ncap, st.off, st.wagg, st.gsum, lds);
 }
 
-__global__ __launch_bounds__(LEVEL_THREADS) void k_tree_fill(TreeStep st) {
-    __shared__ int64_t lds[LEVEL_WAVES];
-    const int32_t c = (int32_t)(blockIdx.x * LEVEL_WAVES + (threadIdx.x >> 6));
+template <int W>
+__global__ __launch_bounds__(64 * W) void k_tree_fill(TreeStep st) {
+    __shared__ int64_t lds[W];
+    const int32_t c = (int32_t)(blockIdx.x * W + (threadIdx.x >> 6));
     const int lane = threadIdx.x & 63;
     if (st.use_agg) {
-        if (level_wg_empty(st.ncount) && blockIdx.x != gridDim.x - 1) return;
-        const int64_t base = level_base(st.wagg, st.gsum, lds);
+        if (level_wg_empty<W>(st.ncount) && blockIdx.x != gridDim.x - 1) return;
+        const int64_t base = level_base<W>(st.wagg, st.gsum, lds);
         if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) tree_level_totals(st, base + st.wagg[blockIdx.x]);
         if (c < st.ncap) tree_fill_node(st, c, lane, base + st.off[c]);
     } else {
@@ -510,25 +513,27 @@ __device__ void leaf_fill_node(const LeafStep& st, int32_t c, int lane, int64_t 
     }
 }
 
-__global__ __launch_bounds__(LEVEL_THREADS) void k_leaf_count(LeafStep st) {
-    __shared__ int64_t lds[LEVEL_WAVES];
-    if (st.use_agg && level_wg_empty(st.ncount)) {
+template <int W>
+__global__ __launch_bounds__(64 * W) void k_leaf_count(LeafStep st) {
+    __shared__ int64_t lds[W];
+    if (st.use_agg && level_wg_empty<W>(st.ncount)) {
         if (threadIdx.x == 0) st.wagg[blockIdx.x] = 0;
         return;
     }
-    const int32_t c = (int32_t)(blockIdx.x * LEVEL_WAVES + (threadIdx.x >> 6));
+    const int32_t c = (int32_t)(blockIdx.x * W + (threadIdx.x >> 6));
     int64_t v = 0;
     if (c < st.ncap) v = leaf_count_node(st, c, threadIdx.x & 63);
-    if (st.use_agg) level_local_offsets(v, c, st.ncap, st.off, st.wagg, st.gsum, lds);
+    if (st.use_agg) level_local_offsets<W>(v, c, st.ncap, st.off, st.wagg, st.gsum, lds);
 }
 
-__global__ __launch_bounds__(LEVEL_THREADS) void k_leaf_fill(LeafStep st) {
-    __shared__ int64_t lds[LEVEL_WAVES];
-    const int32_t c = (int32_t)(blockIdx.x * LEVEL_WAVES + (threadIdx.x >> 6));
+template <int W>
+__global__ __launch_bounds__(64 * W) void k_leaf_fill(LeafStep st) {
+    __shared__ int64_t lds[W];
+    const int32_t c = (int32_t)(blockIdx.x * W + (threadIdx.x >> 6));
     const int lane = threadIdx.x & 63;
     if (st.use_agg) {
-        if (level_wg_empty(st.ncount) && blockIdx.x != gridDim.x - 1) return;
-        const int64_t base = level_base(st.wagg, st.gsum, lds);
+        if (level_wg_empty<W>(st.ncount) && blockIdx.x != gridDim.x - 1) return;
+        const int64_t base = level_base<W>(st.wagg, st.gsum, lds);
         if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) leaf_level_totals(st, base + st.wagg[blockIdx.x]);
         if (c < st.ncap) leaf_fill_node(st, c, lane, base + st.off[c]);
     } else {
@@ -617,7 +622,20 @@ static void read_back_counts(const int32_t* dcount, int n, hipStream_t s, int32_
 }
 
 // Workgroups of the per-level kernels for n C nodes (one wave each).
-static inline int64_t level_wgs(int64_t n) { return std::max<int64_t>((n + LEVEL_WAVES - 1) / LEVEL_WAVES, 1); }
+static inline int64_t level_wgs(int64_t n) {
+    const int w = level_waves(n);
+    return std::max<int64_t>((n + w - 1) / w, 1);
+}
+
+// Launch kernel template K (count or fill) with the level's workgroup width.
+#define QT_LEVEL_LAUNCH(K, n, wgs, stream, arg)                                  \
+    do {                                                                          \
+        if (level_waves(n) == 1)                                                  \
+            K<1><<<(unsigned)(wgs), 64, 0, (stream)>>>(arg);                      \
+        else                                                                      \
+            K<4><<<(unsigned)(wgs), 256, 0, (stream)>>>(arg);                     \
+        QT_LAUNCH(#K);                                                            \
+    } while (0)
 
 // The symbolic phase reads only the operands' structure (child tables, keys,
 // masks), which every handle has complete when the call that made it returns
@@ -879,11 +897,9 @@ void symbolic(qt_matrix* A, qt_matrix* B, qt_prec prec, hipStream_t s, SymbolicO
         TreeStep sl = st;
         const int64_t wgs = level_wgs(pairs[l]);
         sl.use_agg = wgs <= AGG_MAX;
-        k_tree_count<<<(unsigned)wgs, LEVEL_THREADS, 0, ss>>>(sl);
-        QT_LAUNCH("k_tree_count");
+        QT_LEVEL_LAUNCH(k_tree_count, pairs[l], wgs, ss, sl);
         if (!sl.use_agg) exclusive_scan(sl.cnt, sl.off, pairs[l], scan_tmp, ss);
-        k_tree_fill<<<(unsigned)wgs, LEVEL_THREADS, 0, ss>>>(sl);
-        QT_LAUNCH("k_tree_fill");
+        QT_LEVEL_LAUNCH(k_tree_fill, pairs[l], wgs, ss, sl);
     }
 
     // leaf step
@@ -923,11 +939,9 @@ void symbolic(qt_matrix* A, qt_matrix* B, qt_prec prec, hipStream_t s, SymbolicO
     ls.lcm = (uint64_t*)at(K, o_lcm);
     ls.nblocks_out = dcount + L + 1;
     ls.check = dcount + 2 * L + 2;
-    k_leaf_count<<<(unsigned)leaf_wgs, LEVEL_THREADS, 0, ss>>>(ls);
-    QT_LAUNCH("k_leaf_count");
+    QT_LEVEL_LAUNCH(k_leaf_count, pairs[L], leaf_wgs, ss, ls);
     if (!ls.use_agg) exclusive_scan(ls.cnt, ls.off, pairs[L], scan_tmp, ss);
-    k_leaf_fill<<<(unsigned)leaf_wgs, LEVEL_THREADS, 0, ss>>>(ls);
-    QT_LAUNCH("k_leaf_fill");
+    QT_LEVEL_LAUNCH(k_leaf_fill, pairs[L], leaf_wgs, ss, ls);
     if (prof) QT_HIP(hipEventRecord(ev.e1, ss));
 
     // the one synchronization: node and block counts of C
