@@ -686,9 +686,36 @@ qt_matrix* symmetric_full(qt_matrix* A, hipStream_t s) {
 
 // ------------------------------------------------------------- C = A + B
 
-__global__ void k_iota(int32_t* p, int64_t n) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) p[i] = (int32_t)i;
+// Merge of two ascending key lists without a sort: A's key i lands at
+// i + #{B keys < it}, B's key j at j + #{A keys <= it}, so a key present in
+// both comes out as A's entry followed by B's. src: s < na for A block s,
+// na + j for B block j.
+__device__ __forceinline__ int64_t count_below(const uint64_t* __restrict__ k, int64_t n, uint64_t x, bool le) {
+    int64_t lo = 0, hi = n;   // first position whose key is >= x (le: > x)
+    while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        const bool left = le ? (k[mid] <= x) : (k[mid] < x);
+        if (left)
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    return lo;
+}
+
+__global__ void k_merge_keys(const uint64_t* __restrict__ ka, int64_t na, const uint64_t* __restrict__ kb,
+                             int64_t nb, uint64_t* __restrict__ keys, int32_t* __restrict__ src) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < na) {
+        const int64_t pos = t + count_below(kb, nb, ka[t], false);
+        keys[pos] = ka[t];
+        src[pos] = (int32_t)t;
+    } else if (t < na + nb) {
+        const int64_t j = t - na;
+        const int64_t pos = j + count_below(ka, na, kb[j], true);
+        keys[pos] = kb[j];
+        src[pos] = (int32_t)t;
+    }
 }
 
 __global__ void k_key_flags(const uint64_t* __restrict__ keys, int64_t n, int32_t* __restrict__ flags) {
@@ -728,15 +755,11 @@ qt_matrix* add(qt_matrix* A, qt_matrix* B, hipStream_t s) {
     if (n > (int64_t(1) << 31) - 2) fail(QT_ERR_UNSUPPORTED, "too many blocks");
     if (n == 0) return build(A->n_rows, A->n_cols, A->b, A->leaf, 0, nullptr, nullptr, nullptr, QT_MEM_DEVICE, s);
     const int bb = A->b * A->b;
-    int64_t npow2 = 1;
-    while (npow2 < n) npow2 <<= 1;
-    DBuf<uint64_t> keys(npow2, s);
-    DBuf<int32_t> src(npow2, s);
-    if (na) QT_HIP(hipMemcpyAsync(keys.p, A->bkey.p, na * sizeof(uint64_t), hipMemcpyDeviceToDevice, s));
-    if (nb) QT_HIP(hipMemcpyAsync(keys.p + na, B->bkey.p, nb * sizeof(uint64_t), hipMemcpyDeviceToDevice, s));
-    k_iota<<<grid_for(n), 256, 0, s>>>(src.p, n);
-    QT_LAUNCH("k_iota");
-    bitonic_sort(keys.p, src.p, n, s);
+    // both key lists are ascending (Morton order): merge them
+    DBuf<uint64_t> keys(n, s);
+    DBuf<int32_t> src(n, s);
+    k_merge_keys<<<grid_for(n), 256, 0, s>>>(A->bkey.p, na, B->bkey.p, nb, keys.p, src.p);
+    QT_LAUNCH("k_merge_keys");
     DBuf<int32_t> flags(n, s), ex(n + 1, s), tmp(scan_tmp_elems(n) + 1, s);
     k_key_flags<<<grid_for(n), 256, 0, s>>>(keys.p, n, flags.p);
     QT_LAUNCH("k_key_flags");

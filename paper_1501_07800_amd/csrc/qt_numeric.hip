@@ -284,8 +284,105 @@ __global__ __launch_bounds__(64) void k_numeric_bf16x3(const uint16_t* __restric
                           (int)(tile % WPB));
 }
 
+// b = 64 fp64 with the operands shared through LDS, as for the split path
+// below: one workgroup of four waves per 64 x 64 C block, wave w the 32 x 32
+// tile (w / 2, w % 2). A block product is staged in two halves of the inner
+// index: A's 64 x 32 and B's 32 x 64 half (16 KiB each) go to LDS once and
+// each wave reads its panels from there (32 KiB per half per workgroup from
+// L2 instead of 64 KiB). LDS rows are padded so that the 16 lanes of a group
+// reading 16 rows of A hit distinct banks (34 doubles), and the four groups
+// reading four rows of B fall in different halves of the banks (72 doubles).
+constexpr int F64L_AROW = 34;
+constexpr int F64L_BROW = 72;
+
+__global__ __launch_bounds__(256, 4) void k_numeric_f64_b64(const double* __restrict__ A, const double* __restrict__ B,
+                                                         const int32_t* __restrict__ prodA,
+                                                         const int32_t* __restrict__ prodB,
+                                                         const int32_t* __restrict__ seg, int32_t nseg,
+                                                         double* __restrict__ C) {
+    constexpr int BS = 64, MT = 2, KH = 32;
+    typedef double v2d_t __attribute__((ext_vector_type(2)));
+    __shared__ __attribute__((aligned(16))) double la[64 * F64L_AROW];   // A[:, half]
+    __shared__ __attribute__((aligned(16))) double lb[KH * F64L_BROW];   // B[half, :]
+    const int64_t s = xcd_logical<8>(blockIdx.x);
+    if (s >= nseg) return;   // uniform over the workgroup
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int r16 = lane & 15, g = lane >> 4;
+    const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+    const int32_t t0 = seg[s], t1 = seg[s + 1];
+
+    v4d acc[MT][MT];
+#pragma unroll
+    for (int i = 0; i < MT; ++i)
+#pragma unroll
+        for (int j = 0; j < MT; ++j) acc[i][j] = v4d{0, 0, 0, 0};
+
+    for (int32_t t = t0; t < t1; ++t) {
+        const double* a = A + (size_t)prodA[t] * (BS * BS);
+        const double* b = B + (size_t)prodB[t] * (BS * BS);
+#pragma unroll 1
+        for (int h = 0; h < 2; ++h) {
+            // 16-byte pieces: A half is 64 rows x 16 pieces, B half 32 rows x 32 pieces;
+            // thread tid moves pieces tid + 256 r, r = 0..3, of each
+            v2d_t pa[4], pb[4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int q = tid + 256 * r;
+                pa[r] = *reinterpret_cast<const v2d_t*>(a + (q >> 4) * BS + h * KH + (q & 15) * 2);
+                pb[r] = *reinterpret_cast<const v2d_t*>(b + (h * KH + (q >> 5)) * BS + (q & 31) * 2);
+            }
+            __syncthreads();   // every wave is done reading the previous half
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int q = tid + 256 * r;
+                *reinterpret_cast<v2d_t*>(la + (q >> 4) * F64L_AROW + (q & 15) * 2) = pa[r];
+                *reinterpret_cast<v2d_t*>(lb + (q >> 5) * F64L_BROW + (q & 31) * 2) = pb[r];
+            }
+            __syncthreads();
+            // step ks gives lane group g the inner index k = 8 (ks / 2) + 2 g + ks % 2
+            double ar[MT][8], br[MT][8];
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const v2d_t x = *reinterpret_cast<const v2d_t*>(la + (wm + mt * 16 + r16) * F64L_AROW + 8 * v + 2 * g);
+                    ar[mt][2 * v] = x[0];
+                    ar[mt][2 * v + 1] = x[1];
+                }
+#pragma unroll
+            for (int nt = 0; nt < MT; ++nt)
+#pragma unroll
+                for (int ks = 0; ks < 8; ++ks)
+                    br[nt][ks] = lb[(8 * (ks >> 1) + 2 * g + (ks & 1)) * F64L_BROW + wn + nt * 16 + r16];
+#pragma unroll
+            for (int ks = 0; ks < 8; ++ks)
+#pragma unroll
+                for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+                    for (int nt = 0; nt < MT; ++nt)
+                        acc[mt][nt] = Mfma<double>::step(ar[mt][ks], br[nt][ks], acc[mt][nt]);
+        }
+    }
+    double* c = C + (size_t)s * (BS * BS);
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+        for (int nt = 0; nt < MT; ++nt)
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+                __builtin_nontemporal_store(acc[mt][nt][i],
+                                            c + (wm + mt * 16 + Mfma<double>::row(g, i)) * BS + wn + nt * 16 + r16);
+}
+
 template <class T, int BS>
 static void launch_t(const NumericArgs& a, hipStream_t s) {
+    if (sizeof(T) == 8 && BS == 64) {
+        k_numeric_f64_b64<<<xcd_grid<8>(a.nseg), 256, 0, s>>>((const double*)a.A, (const double*)a.B, a.prodA,
+                                                             a.prodB, a.seg, a.nseg, (double*)a.C);
+        QT_LAUNCH("k_numeric_f64_b64");
+        return;
+    }
     typedef Geo<BS> G;
     const unsigned grid = xcd_grid<>((int64_t)a.nseg * G::WPB);
     k_numeric<T, BS><<<grid, 64, 0, s>>>((const T*)a.A, (const T*)a.B, a.prodA, a.prodB, a.seg, a.nseg,
