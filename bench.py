@@ -120,19 +120,21 @@ def timed_steps(qt, torch, hA, prec, steps, warmup):
 
 
 def _time_call(torch, fn, reps):
-    """Mean wall time (ms) of fn() over reps calls, device-synchronized; fn's
-    result is freed between calls."""
+    """Mean wall time (ms) of fn() over reps back-to-back calls, device-
+    synchronized; each result is freed just before the next call (as in the
+    headline loop)."""
     r = fn()
     torch.cuda.synchronize()
-    if hasattr(r, "free"):
-        r.free()
     t0 = time.perf_counter()
     for _ in range(reps):
-        r = fn()
         if hasattr(r, "free"):
             r.free()
+        r = fn()
     torch.cuda.synchronize()
-    return (time.perf_counter() - t0) / reps * 1e3
+    dt = (time.perf_counter() - t0) / reps * 1e3
+    if hasattr(r, "free"):
+        r.free()
+    return dt
 
 
 def bench_ops(args, qt, torch, wl):
