@@ -127,6 +127,22 @@ __global__ void k_parent_fill(const uint64_t* __restrict__ ck, int64_t nc, const
     if (flags[t]) pkey[p] = ck[t] >> 2;
 }
 
+// Node counts of every level at once from the sorted block keys: node
+// boundaries at level l are where the key prefix above shift(l) changes.
+// cnt[l] for l = 0 .. L (L: the leaves); one ballot per wave and level.
+__global__ void k_level_counts(const uint64_t* __restrict__ keys, int64_t n, int L, int leaf_shift,
+                               int32_t* __restrict__ cnt) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const bool in = t < n;
+    const uint64_t k = in ? keys[t] : 0, kp = (in && t > 0) ? keys[t - 1] : 0;
+    for (int l = 0; l <= L; ++l) {
+        const int sh = leaf_shift + 2 * (L - l);
+        const bool first = in && (t == 0 || (sh < 64 ? (k >> sh) != (kp >> sh) : false));
+        const uint64_t m = __ballot(first);
+        if ((threadIdx.x & 63) == 0 && m) atomicAdd(cnt + l, (int32_t)__popcll(m));
+    }
+}
+
 __global__ void k_hist(const uint64_t* __restrict__ keys, int64_t n, int32_t* __restrict__ rowcnt,
                        int32_t* __restrict__ colcnt) {
     int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -525,11 +541,23 @@ qt_matrix* build(int64_t n_rows, int64_t n_cols, int32_t b, int32_t leaf, int64_
 void build_tree_levels(qt_matrix* M, hipStream_t s) {
     const int64_t n = M->nblocks;
     const int shift = 2 * M->lb_log;
+    // all node counts in one pass and one read-back, so the levels below
+    // are built without further synchronization
+    std::vector<int32_t> counts(M->L + 1);
+    {
+        DBuf<int32_t> dcnt(M->L + 1, s);
+        k_fill_i32<<<1, 64, 0, s>>>(dcnt.p, M->L + 1, 0);
+        QT_LAUNCH("k_fill_i32");
+        k_level_counts<<<grid_for(n), 256, 0, s>>>(M->bkey.p, n, M->L, shift, dcnt.p);
+        QT_LAUNCH("k_level_counts");
+        QT_HIP(hipMemcpyAsync(counts.data(), dcnt.p, counts.size() * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        QT_HIP(hipStreamSynchronize(s));
+    }
     DBuf<int32_t> flags(n, s), ex(n + 1, s), tmp(scan_tmp_elems(n) + 1, s);
     k_run_flags<<<grid_for(n), 256, 0, s>>>(M->bkey.p, n, shift, flags.p);
     QT_LAUNCH("k_run_flags");
     exclusive_scan(flags.p, ex.p, n, tmp.p, s);
-    const int32_t nleaves = read_scalar(ex.p + n, s);
+    const int32_t nleaves = counts[M->L];
     LeafLevel& lv = M->leaves;
     lv.n = nleaves;
     lv.base.alloc(nleaves, s);
@@ -548,7 +576,7 @@ void build_tree_levels(qt_matrix* M, hipStream_t s) {
         k_run_flags<<<grid_for(nc), 256, 0, s>>>(ck, nc, 2, f.p);
         QT_LAUNCH("k_run_flags");
         exclusive_scan(f.p, e.p, nc, t2.p, s);
-        const int32_t np = read_scalar(e.p + nc, s);
+        const int32_t np = counts[l];
         TreeLevel& tl = M->levels[l];
         tl.n = np;
         tl.child.alloc(4 * (int64_t)np, s);
@@ -686,6 +714,31 @@ qt_matrix* symmetric_full(qt_matrix* A, hipStream_t s) {
 
 // ------------------------------------------------------------- C = A + B
 
+// A matrix shaped like `like` from nb blocks whose keys are already in
+// ascending Morton order (adopts keys and values).
+static qt_matrix* assemble_sorted(const qt_matrix* like, int L, int64_t nb, DBuf<uint64_t>&& keys,
+                                  DBuf<double>&& values, hipStream_t s) {
+    std::unique_ptr<qt_matrix> C(new qt_matrix);
+    C->n_rows = like->n_rows;
+    C->n_cols = like->n_cols;
+    C->b = like->b;
+    C->leaf = like->leaf;
+    C->lb = like->lb;
+    C->lb_log = like->lb_log;
+    C->L = L;
+    C->vtype = QT_F64;
+    C->nblocks = nb;
+    C->stream = s;
+    QT_HIP(hipGetDevice(&C->device));
+    C->levels.resize(L);
+    C->bkey = std::move(keys);
+    C->v64 = std::move(values);
+    if (nb > 0) build_tree_levels(C.get(), s);
+    build_histograms(C.get(), s);
+    QT_HIP(hipStreamSynchronize(s));
+    return C.release();
+}
+
 // Merge of two ascending key lists without a sort: A's key i lands at
 // i + #{B keys < it}, B's key j at j + #{A keys <= it}, so a key present in
 // both comes out as A's entry followed by B's. src: s < na for A block s,
@@ -766,27 +819,11 @@ qt_matrix* add(qt_matrix* A, qt_matrix* B, hipStream_t s) {
     exclusive_scan(flags.p, ex.p, n, tmp.p, s);
     const int32_t nc = read_scalar(ex.p + n, s);
 
-    std::unique_ptr<qt_matrix> C(new qt_matrix);
-    C->n_rows = A->n_rows;
-    C->n_cols = A->n_cols;
-    C->b = A->b;
-    C->leaf = A->leaf;
-    C->lb = A->lb;
-    C->lb_log = A->lb_log;
-    C->L = std::max(A->L, B->L);
-    C->vtype = QT_F64;
-    C->nblocks = nc;
-    C->stream = s;
-    QT_HIP(hipGetDevice(&C->device));
-    C->levels.resize(C->L);
-    C->bkey.alloc(nc, s);
-    C->v64.alloc((size_t)nc * bb, s);
-    k_add_blocks<<<block_grid(n), 256, 0, s>>>(keys.p, src.p, n, flags.p, ex.p, na, va, vb, bb, C->bkey.p, C->v64.p);
+    DBuf<uint64_t> ck(nc, s);
+    DBuf<double> cv((size_t)nc * bb, s);
+    k_add_blocks<<<block_grid(n), 256, 0, s>>>(keys.p, src.p, n, flags.p, ex.p, na, va, vb, bb, ck.p, cv.p);
     QT_LAUNCH("k_add_blocks");
-    build_tree_levels(C.get(), s);
-    build_histograms(C.get(), s);
-    QT_HIP(hipStreamSynchronize(s));
-    return C.release();
+    return assemble_sorted(A, std::max(A->L, B->L), nc, std::move(ck), std::move(cv), s);
 }
 
 // --------------------------------------------------- value truncation
@@ -831,19 +868,19 @@ __global__ void k_trunc_flags(const double* __restrict__ excl, const double* __r
     if (p < n) keep[idx[p]] = (excl[p] + sorted[p] < eps2) ? 0 : 1;
 }
 
+// Kept blocks, in their (Morton) order: keys and values of the result.
 __global__ void k_compact_blocks(const uint64_t* __restrict__ bkey, const double* __restrict__ v, int64_t n, int bb,
                                  const int32_t* __restrict__ keep, const int32_t* __restrict__ pos,
-                                 int32_t* __restrict__ I, int32_t* __restrict__ J, double* __restrict__ out) {
+                                 uint64_t* __restrict__ okey, double* __restrict__ out) {
     for (int64_t t = blockIdx.x; t < n; t += gridDim.x) {
         if (!keep[t]) continue;
         const int64_t o = pos[t];
-        if (threadIdx.x == 0) {
-            I[o] = (int32_t)morton_row(bkey[t]);
-            J[o] = (int32_t)morton_col(bkey[t]);
-        }
+        if (threadIdx.x == 0) okey[o] = bkey[t];
         for (int e = threadIdx.x; e < bb; e += blockDim.x) out[(size_t)o * bb + e] = v[(size_t)t * bb + e];
     }
 }
+
+
 
 qt_matrix* truncate(qt_matrix* M, double eps, hipStream_t s, int64_t* removed, double* removed_norm2) {
     if (!(eps >= 0.0)) fail(QT_ERR_ARG, "eps must be a non-negative number");
@@ -868,10 +905,12 @@ qt_matrix* truncate(qt_matrix* M, double eps, hipStream_t s, int64_t* removed, d
     QT_LAUNCH("k_trunc_flags");
     exclusive_scan(keep.p, pos.p, n, itmp.p, s);
     const int32_t nk = read_scalar(pos.p + n, s);
-    DBuf<int32_t> I(std::max<int64_t>(nk, 1), s), J(std::max<int64_t>(nk, 1), s);
-    DBuf<double> V(std::max<size_t>((size_t)nk * bb, 1), s);
-    k_compact_blocks<<<block_grid(n), 256, 0, s>>>(M->bkey.p, v, n, bb, keep.p, pos.p, I.p, J.p, V.p);
-    QT_LAUNCH("k_compact_blocks");
+    DBuf<uint64_t> K(nk, s);
+    DBuf<double> V((size_t)nk * bb, s);
+    if (nk > 0) {
+        k_compact_blocks<<<block_grid(n), 256, 0, s>>>(M->bkey.p, v, n, bb, keep.p, pos.p, K.p, V.p);
+        QT_LAUNCH("k_compact_blocks");
+    }
     if (removed || removed_norm2) {
         const int64_t k = n - nk;   // the k smallest blocks were removed
         if (removed) *removed = k;
@@ -883,7 +922,7 @@ qt_matrix* truncate(qt_matrix* M, double eps, hipStream_t s, int64_t* removed, d
             *removed_norm2 = e + last;
         }
     }
-    return build(M->n_rows, M->n_cols, M->b, M->leaf, nk, I.p, J.p, V.p, QT_MEM_DEVICE, s);
+    return assemble_sorted(M, M->L, nk, std::move(K), std::move(V), s);
 }
 
 void get_blocks(const qt_matrix* M, int64_t count, const int32_t* I, const int32_t* J, void* values,

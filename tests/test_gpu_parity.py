@@ -183,6 +183,36 @@ def test_chained_product_f64(qt):
     assert same and e_cw <= TOL64
 
 
+def test_back_to_back_chain_on_streams(qt):
+    """C_1 = A*A, C_{k+1} = C_k*A, issued back to back with no host sync
+    between the calls, on the default stream and on a torch stream: each
+    traversal overlaps the previous numeric kernel (it reads only C_k's
+    structure) while each numeric kernel waits for the previous values. The
+    earlier results are freed while later ones are still being computed."""
+    import torch
+    rng = np.random.default_rng(16)
+    A = random_pattern(rng, 48, 48, 0.06, 32)
+    refs, absrefs = [], []
+    ref, absref = A, A
+    absA = wl.BlockMatrix(A.n_rows, A.n_cols, 32, A.I, A.J, np.abs(A.V))
+    for _ in range(4):
+        ref, _ = oracle.multiply(ref, A, 128)
+        absref, _ = oracle.multiply(absref if len(refs) else absA, absA, 128)
+        refs.append(ref)
+        absrefs.append(absref)
+    for stream in (None, torch.cuda.Stream()):
+        hA = qt.from_blockmatrix(A, 128, stream=stream)
+        chain = [hA]
+        for _ in range(4):
+            chain.append(qt.multiply(chain[-1], hA, stream=stream))
+            if len(chain) >= 4:
+                chain[-3].free()     # C_{k-1}: freed in stream order, after the multiply that read it
+        I, J, V = chain[-1].to_blocks(stream=stream)
+        got = wl.BlockMatrix(A.n_rows, A.n_cols, 32, I, J, V)
+        same, _, _, e_cw = compare(refs[-1], got, absrefs[-1])
+        assert same and e_cw <= 4 * TOL64, e_cw
+
+
 def test_decay_small_f64(qt):
     A = wl.decay3d(1024, 25.0, 16, 32, seed=7)
     check_f64(qt, A, A, 256, same=True)
