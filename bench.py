@@ -80,8 +80,11 @@ def traffic_from_counters(fetch_csv, write_csv, copy_fetch_csv, copy_write_csv, 
     WRITE_SIZE (KiB per dispatch), each scaled so that the plain copy of
     COPY_BYTES reads as COPY_BYTES."""
     import hashlib
-    kname = {"f64": f"k_numeric<double, {b}>", "f32": f"k_numeric<float, {b}>",
-             "bf16x3": f"k_numeric_bf16x3<{b}>"}[prec]
+    if b == 64:   # the LDS-shared kernels of the 64-wide blocks
+        kname = {"f64": "k_numeric_f64_b64", "f32": "k_numeric<float, 64>", "bf16x3": "k_numeric_bf16x3_b64"}[prec]
+    else:
+        kname = {"f64": f"k_numeric<double, {b}>", "f32": f"k_numeric<float, {b}>",
+                 "bf16x3": f"k_numeric_bf16x3<{b}>"}[prec]
     cf, _ = _pmc_mean_kib(copy_fetch_csv, "FETCH_SIZE", "copyBuffer")
     cw, _ = _pmc_mean_kib(copy_write_csv, "WRITE_SIZE", "copyBuffer")
     f_scale = COPY_BYTES / (cf * 1024.0)
