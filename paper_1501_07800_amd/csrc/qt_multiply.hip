@@ -106,7 +106,7 @@ struct TreeStep {
     int64_t* wagg;            // aggregate path: per count workgroup, the sum of its nodes' cnt
     int64_t* gsum;            // aggregate path: per group of 64 count workgroups, their sum (zeroed first)
     int use_agg;              // offsets from workgroup aggregates instead of a scan
-    int32_t ncap;             // bound on C nodes (= pairs at this level)
+    int32_t ncap;             // bound on C nodes at this level
     // next level
     int32_t* nfa;
     int32_t* nfb;
@@ -115,6 +115,7 @@ struct TreeStep {
     int32_t* cchild;          // C's child table at this level (4 per node)
     int32_t* ncount_next;
     int32_t np_next;          // bound on pairs at the next level (exact unless `upper`)
+    int32_t nc_next;          // bound on C nodes at the next level
     int32_t* check;           // device total of child pairs, for the host check
     int ta, tb;               // operand used transposed: child (m, k) of op(A) is child (k, m) of A
     int upper;                // keep only C nodes on or above the block diagonal
@@ -174,7 +175,7 @@ __device__ int64_t tree_count_node(const TreeStep& st, int32_t c, int lane) {
 __device__ void tree_level_totals(const TreeStep& st, int64_t T) {
     const int32_t nc_next = hi32(T);
     *st.ncount_next = nc_next;
-    if (nc_next <= st.np_next) st.ncseg[nc_next] = lo32(T);
+    if (nc_next <= st.nc_next) st.ncseg[nc_next] = lo32(T);
     *st.check = lo32(T);
 }
 
@@ -200,7 +201,7 @@ __device__ void tree_fill_node(const TreeStep& st, int32_t c, int lane, int64_t 
                 my_run = run[mn];
             }
         st.cchild[4 * (int64_t)c + lane] = my_c;
-        if (my_c >= 0 && my_c < st.np_next) {
+        if (my_c >= 0 && my_c < st.nc_next) {
             st.nckey[my_c] = st.ckey[c] * 4 + (uint64_t)lane;
             st.ncseg[my_c] = my_run;
         }
@@ -770,6 +771,19 @@ void symbolic(qt_matrix* A, qt_matrix* B, qt_prec prec, hipStream_t s, SymbolicO
     const int64_t lb2 = int64_t(1) << (2 * lb_log);
     for (int l = 0; l <= L; ++l)
         if (4 * pairs[l] > kMaxI32) fail(QT_ERR_UNSUPPORTED, "too many node pairs at one level");
+    // bound on C nodes per level: every C node has at least one pair, and
+    // there are only so many node positions in C's shape at that level (the
+    // per-node arrays and the level kernels' grids are sized by this; at the
+    // deep levels of an unstructured product it is far below the pair count)
+    std::vector<int64_t> ncap(L + 1);
+    {
+        const int64_t c_rows = op.ta ? A->n_cols : A->n_rows, c_cols = op.tb ? B->n_rows : B->n_cols;
+        for (int l = 0; l <= L; ++l) {
+            const int64_t side = (int64_t)A->leaf << (L - l);
+            const int64_t pos = ((c_rows + side - 1) / side) * ((c_cols + side - 1) / side);
+            ncap[l] = std::max<int64_t>(std::min(pairs[l], pos), 1);
+        }
+    }
     if (P > kMaxI32) fail(QT_ERR_UNSUPPORTED, "too many block products");
     if (P == 0) {
         out.C.reset(empty_result(A, B, L, prec, s, op));
@@ -798,15 +812,15 @@ void symbolic(qt_matrix* A, qt_matrix* B, qt_prec prec, hipStream_t s, SymbolicO
     }
 
     // ---- plan the two allocations
-    const int64_t cap = std::min<int64_t>(P, lb2 * pairs[L]);   // bound on C blocks
+    const int64_t cap = std::min<int64_t>(P, lb2 * ncap[L]);   // bound on C blocks
     ArenaPlan keep, tmp;   // keep: C's tree; tmp: scratch freed after the call
     std::vector<size_t> o_child(L), o_key(L + 1);
-    for (int l = 0; l < L; ++l) o_child[l] = keep.take(4 * pairs[l] * sizeof(int32_t));
-    for (int l = 0; l <= L; ++l) o_key[l] = keep.take(pairs[l] * sizeof(uint64_t));
-    const size_t o_lbase = keep.take(pairs[L] * sizeof(int32_t));
-    const size_t o_lmo = keep.take(pairs[L] * sizeof(uint64_t));
-    const size_t o_lrm = keep.take(pairs[L] * sizeof(uint64_t));
-    const size_t o_lcm = keep.take(pairs[L] * sizeof(uint64_t));
+    for (int l = 0; l < L; ++l) o_child[l] = keep.take(4 * ncap[l] * sizeof(int32_t));
+    for (int l = 0; l <= L; ++l) o_key[l] = keep.take(ncap[l] * sizeof(uint64_t));
+    const size_t o_lbase = keep.take(ncap[L] * sizeof(int32_t));
+    const size_t o_lmo = keep.take(ncap[L] * sizeof(uint64_t));
+    const size_t o_lrm = keep.take(ncap[L] * sizeof(uint64_t));
+    const size_t o_lcm = keep.take(ncap[L] * sizeof(uint64_t));
     const size_t o_bkey = keep.take(cap * sizeof(uint64_t));
     std::vector<size_t> o_fa(L + 1), o_fb(L + 1), o_cseg(L + 1), o_cnt(L + 1), o_off(L + 1), o_tot(L + 1),
         o_wagg(L + 1);
@@ -816,14 +830,14 @@ void symbolic(qt_matrix* A, qt_matrix* B, qt_prec prec, hipStream_t s, SymbolicO
     for (int l = 0; l <= L; ++l) {
         o_fa[l] = tmp.take(pairs[l] * sizeof(int32_t));
         o_fb[l] = tmp.take(pairs[l] * sizeof(int32_t));
-        o_cseg[l] = tmp.take((pairs[l] + 1) * sizeof(int32_t));
-        o_cnt[l] = tmp.take(pairs[l] * sizeof(int64_t));
-        o_off[l] = tmp.take((pairs[l] + 1) * sizeof(int64_t));
-        o_tot[l] = tmp.take(pairs[l] * sizeof(int4));
-        o_wagg[l] = tmp.take(level_wgs(pairs[l]) * sizeof(int64_t));
+        o_cseg[l] = tmp.take((ncap[l] + 1) * sizeof(int32_t));
+        o_cnt[l] = tmp.take(ncap[l] * sizeof(int64_t));
+        o_off[l] = tmp.take((ncap[l] + 1) * sizeof(int64_t));
+        o_tot[l] = tmp.take(ncap[l] * sizeof(int4));
+        o_wagg[l] = tmp.take(level_wgs(ncap[l]) * sizeof(int64_t));
         gsum_at[l] = gsum_total;
-        gsum_total += (level_wgs(pairs[l]) + (1 << AGG_GROUP_LOG) - 1) >> AGG_GROUP_LOG;
-        scan_elems = std::max(scan_elems, scan_tmp_elems(pairs[l]));
+        gsum_total += (level_wgs(ncap[l]) + (1 << AGG_GROUP_LOG) - 1) >> AGG_GROUP_LOG;
+        scan_elems = std::max(scan_elems, scan_tmp_elems(ncap[l]));
     }
     const size_t o_gsum = tmp.take(std::max<int64_t>(gsum_total, 1) * sizeof(int64_t));
     const size_t o_scan = tmp.take((scan_elems + 1) * sizeof(int64_t));
@@ -872,7 +886,7 @@ void symbolic(qt_matrix* A, qt_matrix* B, qt_prec prec, hipStream_t s, SymbolicO
         st.wagg = (int64_t*)at(W, o_wagg[l]);
         st.gsum = (int64_t*)at(W, o_gsum) + gsum_at[l];
         st.off = (int64_t*)at(W, o_off[l]);
-        st.ncap = (int32_t)pairs[l];
+        st.ncap = (int32_t)ncap[l];
         st.nfa = (int32_t*)at(W, o_fa[l + 1]);
         st.nfb = (int32_t*)at(W, o_fb[l + 1]);
         st.ncseg = (int32_t*)at(W, o_cseg[l + 1]);
@@ -880,6 +894,7 @@ void symbolic(qt_matrix* A, qt_matrix* B, qt_prec prec, hipStream_t s, SymbolicO
         st.cchild = (int32_t*)at(K, o_child[l]);
         st.ncount_next = dcount + l + 1;
         st.np_next = (int32_t)pairs[l + 1];
+        st.nc_next = (int32_t)ncap[l + 1];
         st.check = dcount + L + 2 + l;
         st.ta = op.ta;
         st.tb = op.tb;
@@ -895,11 +910,11 @@ void symbolic(qt_matrix* A, qt_matrix* B, qt_prec prec, hipStream_t s, SymbolicO
     for (int l = 0; l < L; ++l) {
         const TreeStep st = tree_step(l);
         TreeStep sl = st;
-        const int64_t wgs = level_wgs(pairs[l]);
+        const int64_t wgs = level_wgs(ncap[l]);
         sl.use_agg = wgs <= AGG_MAX;
-        QT_LEVEL_LAUNCH(k_tree_count, pairs[l], wgs, ss, sl);
-        if (!sl.use_agg) exclusive_scan(sl.cnt, sl.off, pairs[l], scan_tmp, ss);
-        QT_LEVEL_LAUNCH(k_tree_fill, pairs[l], wgs, ss, sl);
+        QT_LEVEL_LAUNCH(k_tree_count, ncap[l], wgs, ss, sl);
+        if (!sl.use_agg) exclusive_scan(sl.cnt, sl.off, ncap[l], scan_tmp, ss);
+        QT_LEVEL_LAUNCH(k_tree_fill, ncap[l], wgs, ss, sl);
     }
 
     // leaf step
@@ -909,7 +924,7 @@ void symbolic(qt_matrix* A, qt_matrix* B, qt_prec prec, hipStream_t s, SymbolicO
     ls.cseg = (const int32_t*)at(W, o_cseg[L]);
     ls.ckey = (const uint64_t*)at(K, o_key[L]);
     ls.ncount = dcount + L;
-    ls.ncap = (int32_t)pairs[L];
+    ls.ncap = (int32_t)ncap[L];
     ls.lb_log = lb_log;
     // rows of op(A) are columns of A when transposed; columns of op(B) rows of B
     ls.Arm = op.ta ? A->leaves.mask_cm.p : A->leaves.mask_rm.p;
@@ -925,7 +940,7 @@ void symbolic(qt_matrix* A, qt_matrix* B, qt_prec prec, hipStream_t s, SymbolicO
     ls.off = (int64_t*)at(W, o_off[L]);
     ls.wagg = (int64_t*)at(W, o_wagg[L]);
     ls.gsum = (int64_t*)at(W, o_gsum) + gsum_at[L];
-    const int64_t leaf_wgs = level_wgs(pairs[L]);
+    const int64_t leaf_wgs = level_wgs(ncap[L]);
     ls.use_agg = leaf_wgs <= AGG_MAX;
     ls.prodA = (int32_t*)at(W, o_prodA);
     ls.prodB = (int32_t*)at(W, o_prodB);
@@ -939,9 +954,9 @@ void symbolic(qt_matrix* A, qt_matrix* B, qt_prec prec, hipStream_t s, SymbolicO
     ls.lcm = (uint64_t*)at(K, o_lcm);
     ls.nblocks_out = dcount + L + 1;
     ls.check = dcount + 2 * L + 2;
-    QT_LEVEL_LAUNCH(k_leaf_count, pairs[L], leaf_wgs, ss, ls);
-    if (!ls.use_agg) exclusive_scan(ls.cnt, ls.off, pairs[L], scan_tmp, ss);
-    QT_LEVEL_LAUNCH(k_leaf_fill, pairs[L], leaf_wgs, ss, ls);
+    QT_LEVEL_LAUNCH(k_leaf_count, ncap[L], leaf_wgs, ss, ls);
+    if (!ls.use_agg) exclusive_scan(ls.cnt, ls.off, ncap[L], scan_tmp, ss);
+    QT_LEVEL_LAUNCH(k_leaf_fill, ncap[L], leaf_wgs, ss, ls);
     if (prof) QT_HIP(hipEventRecord(ev.e1, ss));
 
     // the one synchronization: node and block counts of C
@@ -957,6 +972,7 @@ void symbolic(qt_matrix* A, qt_matrix* B, qt_prec prec, hipStream_t s, SymbolicO
         QT_HIP(hipEventDestroy(done));
     }
     for (int l = 0; l <= L; ++l) {
+        if (hc[l] < 0 || hc[l] > ncap[l]) fail(QT_ERR_DEVICE, "symbolic phase: C node count out of range");
         const int64_t expect = (l < L) ? pairs[l + 1] : P;
         const bool bad = op.upper ? (hc[L + 2 + l] < 0 || hc[L + 2 + l] > expect) : (hc[L + 2 + l] != expect);
         if (bad) fail(QT_ERR_DEVICE, "symbolic phase: pair count mismatch");
