@@ -400,6 +400,16 @@ struct LeafStep {
     int upper;                // keep only blocks on or above the diagonal
 };
 
+// Lane t's value in every lane, for a t that is the same in every lane: a
+// read of one lane into a scalar register, with no LDS round trip (a general
+// shuffle goes through the LDS crossbar).
+__device__ __forceinline__ uint32_t lane_value(uint32_t v, int t) {
+    return (uint32_t)__builtin_amdgcn_readlane((int)v, t);
+}
+__device__ __forceinline__ uint64_t lane_value(uint64_t v, int t) {
+    return (uint64_t)lane_value((uint32_t)v, t) | ((uint64_t)lane_value((uint32_t)(v >> 32), t) << 32);
+}
+
 // Block q of a C leaf is kept unless only the upper triangle is wanted and
 // it lies below the diagonal of a diagonal leaf.
 __device__ __forceinline__ bool leaf_block_kept(const LeafStep& st, uint64_t leafkey, int i, int j) {
@@ -418,8 +428,8 @@ __device__ int leaf_lane_count(const LeafStep& st, int32_t s0, int32_t len, int 
             cb = st.Bcm[st.fb[s0 + base + lane]];
         }
         for (int t = 0; t < nb; ++t) {
-            const uint64_t rat = __shfl(ra, t, 64);
-            const uint64_t cbt = __shfl(cb, t, 64);
+            const uint64_t rat = lane_value(ra, t);
+            const uint64_t cbt = lane_value(cb, t);
             if (on) cnt += __popc(mask_row(rat, i, lb) & mask_row(cbt, j, lb));
         }
     }
@@ -481,12 +491,12 @@ __device__ void leaf_fill_node(const LeafStep& st, int32_t c, int lane, int64_t 
             bb = st.Bbase[b];
         }
         for (int t = 0; t < nb; ++t) {
-            const uint64_t rat = __shfl(ra, t, 64);
-            const uint64_t cbt = __shfl(cb, t, 64);
-            const uint64_t amot = __shfl(amo, t, 64);
-            const uint64_t bmot = __shfl(bmo, t, 64);
-            const int32_t abt = __shfl(ab, t, 64);
-            const int32_t bbt = __shfl(bb, t, 64);
+            const uint64_t rat = lane_value(ra, t);
+            const uint64_t cbt = lane_value(cb, t);
+            const uint64_t amot = lane_value(amo, t);
+            const uint64_t bmot = lane_value(bmo, t);
+            const int32_t abt = (int32_t)lane_value((uint32_t)ab, t);
+            const int32_t bbt = (int32_t)lane_value((uint32_t)bb, t);
             uint32_t m = on ? (mask_row(rat, i, lb) & mask_row(cbt, j, lb)) : 0u;
             while (m) {
                 const int k = __ffs(m) - 1;
