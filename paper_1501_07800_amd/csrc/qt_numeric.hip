@@ -100,6 +100,7 @@ __device__ __forceinline__ void wave_block(const T* __restrict__ A, const T* __r
     constexpr int VEC = 16 / sizeof(T);            // elements per 16-byte load
     constexpr int NV = G::KS / VEC;                // 16-byte loads per A row per chunk
     typedef T vec_t __attribute__((ext_vector_type(VEC)));
+    typedef T pair_t __attribute__((ext_vector_type(2)));
     const int lane = threadIdx.x & 63;
     const int r16 = lane & 15;
     const int g = lane >> 4;
@@ -138,13 +139,26 @@ __device__ __forceinline__ void wave_block(const T* __restrict__ A, const T* __r
                     for (int e = 0; e < VEC; ++e) ar[mt][v * VEC + e] = x[e];
                 }
             }
+            if constexpr (G::MT == 2) {
+                // the two 16-column tiles of a wave interleave: lane r16 holds
+                // column 2 r16 of the 32 in tile 0 and 2 r16 + 1 in tile 1, so
+                // one load of two adjacent entries feeds both tiles
 #pragma unroll
-            for (int nt = 0; nt < G::MT; ++nt)
+                for (int v = 0; v < NV; ++v)
+#pragma unroll
+                    for (int e = 0; e < VEC; ++e) {
+                        const pair_t x = *reinterpret_cast<const pair_t*>(
+                            b + (ch * G::KC + v * 4 * VEC + g * VEC + e) * BS + wn + 2 * r16);
+                        br[0][v * VEC + e] = x[0];
+                        br[1][v * VEC + e] = x[1];
+                    }
+            } else {
 #pragma unroll
                 for (int v = 0; v < NV; ++v)
 #pragma unroll
                     for (int e = 0; e < VEC; ++e)
-                        br[nt][v * VEC + e] = b[(ch * G::KC + v * 4 * VEC + g * VEC + e) * BS + wn + nt * 16 + r16];
+                        br[0][v * VEC + e] = b[(ch * G::KC + v * 4 * VEC + g * VEC + e) * BS + wn + r16];
+            }
 #pragma unroll
             for (int ks = 0; ks < G::KS; ++ks)
 #pragma unroll
@@ -154,14 +168,20 @@ __device__ __forceinline__ void wave_block(const T* __restrict__ A, const T* __r
                         acc[mt][nt] = Mfma<T>::step(ar[mt][ks], br[nt][ks], acc[mt][nt]);
         }
     }
+    if constexpr (G::MT == 2) {
 #pragma unroll
-    for (int mt = 0; mt < G::MT; ++mt)
+        for (int mt = 0; mt < G::MT; ++mt)
 #pragma unroll
-        for (int nt = 0; nt < G::MT; ++nt)
+            for (int i = 0; i < 4; ++i) {
+                const pair_t v = {acc[mt][0][i], acc[mt][1][i]};
+                __builtin_nontemporal_store(
+                    v, reinterpret_cast<pair_t*>(c + (wm + mt * 16 + Mfma<T>::row(g, i)) * BS + wn + 2 * r16));
+            }
+    } else {
 #pragma unroll
-            for (int i = 0; i < 4; ++i)
-                __builtin_nontemporal_store(acc[mt][nt][i],
-                                            c + (wm + mt * 16 + Mfma<T>::row(g, i)) * BS + wn + nt * 16 + r16);
+        for (int i = 0; i < 4; ++i)
+            __builtin_nontemporal_store(acc[0][0][i], c + (wm + Mfma<T>::row(g, i)) * BS + wn + r16);
+    }
 }
 
 // Split-bf16 path: per block product, F = lo_a*hi_b + hi_a*lo_b + hi_a*hi_b
@@ -247,12 +267,19 @@ __device__ __forceinline__ void wave_block_bf16x3(const uint16_t* __restrict__ A
 
 // ------------------------------------------------------ one multiply
 
-// Waves per SIMD the compiler must fit: for the b = 32 fp64 kernel five
-// (accumulators then live in ordinary VGPRs), about 1.5% faster than the
-// four it picks by itself and 3% faster than seven (measured on gfx950);
-// the other instances already fit enough waves, and forcing more would spill.
+// Waves per SIMD. The b = 32 fp64 kernel runs best at six: it needs 62
+// VGPRs, so eight would fit, but at eight it is 8% slower, at five 3% and at
+// four 6% (measured on gfx950; more waves per CU means more operand blocks
+// in flight through one L2). MinWaves makes the compiler fit at least that
+// many; the launch caps the count at six by reserving LDS that the kernel
+// does not use: a CU's 160 KiB hold 24 workgroups of 6656 bytes, six
+// single-wave workgroups per SIMD. The other instances run at what their
+// registers allow.
+constexpr int LDS_PER_CU = 160 * 1024;
 template <class T, int BS> struct MinWaves { static constexpr int value = 1; };
-template <> struct MinWaves<double, 32> { static constexpr int value = 5; };
+template <> struct MinWaves<double, 32> { static constexpr int value = 6; };
+template <class T, int BS> struct WaveCapLds { static constexpr unsigned bytes = 0; };
+template <> struct WaveCapLds<double, 32> { static constexpr unsigned bytes = (LDS_PER_CU / (4 * 6)) & ~511u; };
 
 template <class T, int BS>
 __global__ __launch_bounds__(64, (MinWaves<T, BS>::value)) void k_numeric(const T* __restrict__ A, const T* __restrict__ B,
@@ -385,8 +412,8 @@ static void launch_t(const NumericArgs& a, hipStream_t s) {
     }
     typedef Geo<BS> G;
     const unsigned grid = xcd_grid<>((int64_t)a.nseg * G::WPB);
-    k_numeric<T, BS><<<grid, 64, 0, s>>>((const T*)a.A, (const T*)a.B, a.prodA, a.prodB, a.seg, a.nseg,
-                                         (T*)a.C);
+    k_numeric<T, BS><<<grid, 64, WaveCapLds<T, BS>::bytes, s>>>((const T*)a.A, (const T*)a.B, a.prodA, a.prodB,
+                                                                a.seg, a.nseg, (T*)a.C);
     QT_LAUNCH("k_numeric");
 }
 
