@@ -345,20 +345,25 @@ __global__ __launch_bounds__(256, 4) void k_numeric_f64_b64(const double* __rest
 #pragma unroll
         for (int j = 0; j < MT; ++j) acc[i][j] = v4d{0, 0, 0, 0};
 
+    // 16-byte pieces: A's half is 64 rows x 16 pieces, B's half 32 rows x 32
+    // pieces; thread tid moves pieces tid + 256 r, r = 0..3, of each. The
+    // loads of the next half are issued right after the current half is in
+    // LDS, so they are in flight during its MFMAs.
+    v2d_t pa[4], pb[4];
+#define QT_F64L_FETCH(TT, HH)                                                                          \
+    do {                                                                                               \
+        const double* a_ = A + (size_t)prodA[TT] * (BS * BS);                                          \
+        const double* b_ = B + (size_t)prodB[TT] * (BS * BS);                                          \
+        _Pragma("unroll") for (int r = 0; r < 4; ++r) {                                                \
+            const int q = tid + 256 * r;                                                               \
+            pa[r] = *reinterpret_cast<const v2d_t*>(a_ + (q >> 4) * BS + (HH) * KH + (q & 15) * 2);    \
+            pb[r] = *reinterpret_cast<const v2d_t*>(b_ + ((HH) * KH + (q >> 5)) * BS + (q & 31) * 2);  \
+        }                                                                                              \
+    } while (0)
+    QT_F64L_FETCH(t0, 0);   // a segment holds at least one product
     for (int32_t t = t0; t < t1; ++t) {
-        const double* a = A + (size_t)prodA[t] * (BS * BS);
-        const double* b = B + (size_t)prodB[t] * (BS * BS);
 #pragma unroll 1
         for (int h = 0; h < 2; ++h) {
-            // 16-byte pieces: A half is 64 rows x 16 pieces, B half 32 rows x 32 pieces;
-            // thread tid moves pieces tid + 256 r, r = 0..3, of each
-            v2d_t pa[4], pb[4];
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int q = tid + 256 * r;
-                pa[r] = *reinterpret_cast<const v2d_t*>(a + (q >> 4) * BS + h * KH + (q & 15) * 2);
-                pb[r] = *reinterpret_cast<const v2d_t*>(b + (h * KH + (q >> 5)) * BS + (q & 31) * 2);
-            }
             __syncthreads();   // every wave is done reading the previous half
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
@@ -367,6 +372,10 @@ __global__ __launch_bounds__(256, 4) void k_numeric_f64_b64(const double* __rest
                 *reinterpret_cast<v2d_t*>(lb + (q >> 5) * F64L_BROW + (q & 31) * 2) = pb[r];
             }
             __syncthreads();
+            if (h == 0)
+                QT_F64L_FETCH(t, 1);
+            else if (t + 1 < t1)
+                QT_F64L_FETCH(t + 1, 0);
             // step ks gives lane group g the inner index k = 8 (ks / 2) + 2 g + ks % 2
             double ar[MT][8], br[MT][8];
 #pragma unroll
@@ -391,6 +400,7 @@ __global__ __launch_bounds__(256, 4) void k_numeric_f64_b64(const double* __rest
                         acc[mt][nt] = Mfma<double>::step(ar[mt][ks], br[nt][ks], acc[mt][nt]);
         }
     }
+#undef QT_F64L_FETCH
     double* c = C + (size_t)s * (BS * BS);
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt)
