@@ -412,12 +412,121 @@ __global__ __launch_bounds__(256, 4) void k_numeric_f64_b64(const double* __rest
                                             c + (wm + mt * 16 + Mfma<double>::row(g, i)) * BS + wn + nt * 16 + r16);
 }
 
+// b = 64 fp32 with the operands shared through LDS, like the fp64 kernel
+// above: halves of the inner index, each loaded once per workgroup, and the
+// next half's loads in flight during the current half's MFMAs. A half of A
+// is 64 x 32 and a half of B 32 x 64 floats (8 KiB each). LDS rows are padded
+// to 36 and 72 floats: the 16 lanes of a group reading 16 rows of A then
+// cover the 64 banks once, and the four groups reading rows of B four apart
+// touch every bank exactly twice. The two column tiles of a wave interleave
+// as in the per-wave kernel and the k order is that kernel's, so the result
+// is bitwise the same.
+constexpr int F32L_AROW = 36;
+constexpr int F32L_BROW = 72;
+
+__global__ __launch_bounds__(256) void k_numeric_f32_b64(const float* __restrict__ A, const float* __restrict__ B,
+                                                         const int32_t* __restrict__ prodA,
+                                                         const int32_t* __restrict__ prodB,
+                                                         const int32_t* __restrict__ seg, int32_t nseg,
+                                                         float* __restrict__ C) {
+    constexpr int BS = 64, MT = 2, KH = 32;
+    typedef float v2f_t __attribute__((ext_vector_type(2)));
+    __shared__ __attribute__((aligned(16))) float la[64 * F32L_AROW];   // A[:, half]
+    __shared__ __attribute__((aligned(16))) float lb[KH * F32L_BROW];   // B[half, :]
+    const int64_t s = xcd_logical<8>(blockIdx.x);
+    if (s >= nseg) return;   // uniform over the workgroup
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int r16 = lane & 15, g = lane >> 4;
+    const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+    const int32_t t0 = seg[s], t1 = seg[s + 1];
+
+    v4f acc[MT][MT];
+#pragma unroll
+    for (int i = 0; i < MT; ++i)
+#pragma unroll
+        for (int j = 0; j < MT; ++j) acc[i][j] = v4f{0, 0, 0, 0};
+
+    // 16-byte pieces: A's half is 64 rows x 8 pieces, B's half 32 rows x 16
+    // pieces; thread tid moves pieces tid and tid + 256 of each
+    v4f pa[2], pb[2];
+#define QT_F32L_FETCH(TT, HH)                                                                         \
+    do {                                                                                              \
+        const float* a_ = A + (size_t)prodA[TT] * (BS * BS);                                          \
+        const float* b_ = B + (size_t)prodB[TT] * (BS * BS);                                          \
+        _Pragma("unroll") for (int r = 0; r < 2; ++r) {                                               \
+            const int q = tid + 256 * r;                                                              \
+            pa[r] = *reinterpret_cast<const v4f*>(a_ + (q >> 3) * BS + (HH) * KH + (q & 7) * 4);      \
+            pb[r] = *reinterpret_cast<const v4f*>(b_ + ((HH) * KH + (q >> 4)) * BS + (q & 15) * 4);   \
+        }                                                                                             \
+    } while (0)
+    QT_F32L_FETCH(t0, 0);   // a segment holds at least one product
+    for (int32_t t = t0; t < t1; ++t) {
+#pragma unroll 1
+        for (int h = 0; h < 2; ++h) {
+            __syncthreads();   // every wave is done reading the previous half
+#pragma unroll
+            for (int r = 0; r < 2; ++r) {
+                const int q = tid + 256 * r;
+                *reinterpret_cast<v4f*>(la + (q >> 3) * F32L_AROW + (q & 7) * 4) = pa[r];
+                *reinterpret_cast<v4f*>(lb + (q >> 4) * F32L_BROW + (q & 15) * 4) = pb[r];
+            }
+            __syncthreads();
+            if (h == 0)
+                QT_F32L_FETCH(t, 1);
+            else if (t + 1 < t1)
+                QT_F32L_FETCH(t + 1, 0);
+            // step ks gives lane group g the inner index k = 16 (ks / 4) + 4 g + ks % 4;
+            // lane r16 holds columns 2 r16 (tile 0) and 2 r16 + 1 (tile 1)
+            float ar[MT][8], br[MT][8];
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+                for (int v = 0; v < 2; ++v) {
+                    const v4f x = *reinterpret_cast<const v4f*>(la + (wm + mt * 16 + r16) * F32L_AROW + 16 * v + 4 * g);
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) ar[mt][4 * v + e] = x[e];
+                }
+#pragma unroll
+            for (int ks = 0; ks < 8; ++ks) {
+                const v2f_t x = *reinterpret_cast<const v2f_t*>(
+                    lb + (16 * (ks >> 2) + 4 * g + (ks & 3)) * F32L_BROW + wn + 2 * r16);
+                br[0][ks] = x[0];
+                br[1][ks] = x[1];
+            }
+#pragma unroll
+            for (int ks = 0; ks < 8; ++ks)
+#pragma unroll
+                for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+                    for (int nt = 0; nt < MT; ++nt)
+                        acc[mt][nt] = Mfma<float>::step(ar[mt][ks], br[nt][ks], acc[mt][nt]);
+        }
+    }
+#undef QT_F32L_FETCH
+    float* c = C + (size_t)s * (BS * BS);
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const v2f_t v = {acc[mt][0][i], acc[mt][1][i]};
+            __builtin_nontemporal_store(
+                v, reinterpret_cast<v2f_t*>(c + (wm + mt * 16 + Mfma<float>::row(g, i)) * BS + wn + 2 * r16));
+        }
+}
+
 template <class T, int BS>
 static void launch_t(const NumericArgs& a, hipStream_t s) {
     if (sizeof(T) == 8 && BS == 64) {
         k_numeric_f64_b64<<<xcd_grid<8>(a.nseg), 256, 0, s>>>((const double*)a.A, (const double*)a.B, a.prodA,
                                                              a.prodB, a.seg, a.nseg, (double*)a.C);
         QT_LAUNCH("k_numeric_f64_b64");
+        return;
+    }
+    if (sizeof(T) == 4 && BS == 64) {
+        k_numeric_f32_b64<<<xcd_grid<8>(a.nseg), 256, 0, s>>>((const float*)a.A, (const float*)a.B, a.prodA,
+                                                             a.prodB, a.seg, a.nseg, (float*)a.C);
+        QT_LAUNCH("k_numeric_f32_b64");
         return;
     }
     typedef Geo<BS> G;

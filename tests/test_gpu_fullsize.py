@@ -114,7 +114,7 @@ def test_banded1024_bench_config(qt):
 
 @pytest.mark.slow
 def test_decay131072_sampled(qt):
-    """b = 64, leaf 512: fp64 and split-bf16 paths; exact C block count."""
+    """b = 64, leaf 512: fp64, fp32 and split-bf16 paths; exact C block count."""
     name = "decay131072"
     A = wl.config(name)
     leaf = wl.CONFIGS[name]["leaf"]
@@ -125,7 +125,7 @@ def test_decay131072_sampled(qt):
     Ip, Jp, Ia, Ja = _sample_present_absent(pos_ref, A.nb_cols, A.nb_rows * A.nb_cols, rng, 40)
     refs, absrefs, ks = _ref_blocks(A, Ip, Jp)
     b = A.b
-    for prec in ("f64", "bf16x3"):
+    for prec in ("f64", "f32", "bf16x3"):
         _say(name, prec)
         C = qt.multiply(h, h, prec)
         assert C.nblocks == pos_ref.size
@@ -134,6 +134,9 @@ def test_decay131072_sampled(qt):
         if prec == "f64":
             w = _check_samples(C, "f64", Ip, Jp, refs, absrefs, ks, lambda k: 1e-12, b=b)
             assert w <= 1e-12
+        elif prec == "f32":
+            _check_samples(C, "f32", Ip, Jp, refs, absrefs, ks, lambda k: (k * b + 2) * 2.0 ** -24,
+                           4 * 2.0 ** -126, b)
         else:
             _check_samples(C, "f64", Ip, Jp, refs, absrefs, ks,
                            lambda k: 3 * 2.0 ** -16 + (3 * b + 4) * 2.0 ** -24, 4 * 2.0 ** -126, b)
