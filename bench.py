@@ -32,19 +32,28 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def code_digest(path: str) -> str:
+    """SHA-256 of a C++/HIP source with its comments and whitespace removed:
+    it changes when the code changes, not when only a comment does."""
+    import hashlib
+    import re
+    text = open(path, encoding="utf-8").read()
+    text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", " ", text)
+    return hashlib.sha256("".join(text.split()).encode()).hexdigest()
+
+
 def measured_traffic(kernel_source: str, workload: str, prec: str):
     """HBM bytes per launch of the numeric kernel from the committed rocprofv3
     counter summary (FETCH_SIZE and WRITE_SIZE, scaled by a plain copy's
-    reading), or None when there is none for this workload or the kernel's
-    source has changed since the counters were taken."""
-    import hashlib
+    reading), or None when there is none for this workload or the kernels'
+    code has changed since the counters were taken."""
     path = os.path.join(ROOT, "profiles", f"traffic_{prec}_{workload}.json")
     if not os.path.exists(path):
         return None
     rec = json.load(open(path))
     src = os.path.join(ROOT, "paper_1501_07800_amd", "csrc", kernel_source)
-    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
-    if rec.get("source_sha256") != sha:
+    if rec.get("code_sha256") != code_digest(src):
         return None
     return rec.get("traffic_bytes")
 
@@ -79,7 +88,6 @@ def traffic_from_counters(fetch_csv, write_csv, copy_fetch_csv, copy_write_csv, 
     launch of the numeric kernel from rocprofv3 --pmc FETCH_SIZE and
     WRITE_SIZE (KiB per dispatch), each scaled so that the plain copy of
     COPY_BYTES reads as COPY_BYTES."""
-    import hashlib
     if b == 64:   # the LDS-shared kernels of the 64-wide blocks
         kname = {"f64": "k_numeric_f64_b64", "f32": "k_numeric<float, 64>", "bf16x3": "k_numeric_bf16x3_b64"}[prec]
     else:
@@ -98,7 +106,7 @@ def traffic_from_counters(fetch_csv, write_csv, copy_fetch_csv, copy_write_csv, 
            "fetch_kib_per_dispatch": kf, "write_kib_per_dispatch": kw, "dispatches": [nf, nw],
            "copy_fetch_kib": cf, "copy_write_kib": cw, "fetch_scale": f_scale, "write_scale": w_scale,
            "fetch_bytes": fetch, "write_bytes": write, "traffic_bytes": fetch + write,
-           "source_sha256": hashlib.sha256(open(src, "rb").read()).hexdigest()}
+           "code_sha256": code_digest(src)}
     out = os.path.join(ROOT, "profiles", f"traffic_{prec}_{workload}.json")
     json.dump(rec, open(out, "w"), indent=1)
     print(json.dumps(rec), flush=True)

@@ -3,29 +3,35 @@
 //
 // This replaces the paper's leaf library, which ran every outer product
 // batch of a leaf through a batched GEMM (Sec. 4.1, Fig. 2) and accumulated
-// into C in memory. Here one wavefront owns a 32 x 32 (or 16 x 16) tile of a
-// C block for the whole segment: the tile stays in MFMA accumulators across
-// all its block products and is stored once, so C is never re-read and no
-// two waves ever write the same C entry (no atomics).
+// into C in memory. Here the waves that own a C block keep it in MFMA
+// accumulators across all its block products and store it once, so C is
+// never re-read and no two waves ever write the same C entry (no atomics).
 //
 // MFMA operand layout (16 x 16 x 4 for fp64/fp32): lane l = 16*g + r supplies
 // A[r][kk = g] and B[kk = g][r] of one 4-deep step; its four accumulator
 // values are D[4*g + i][r] (i = 0..3) for fp32, but D[4*i + g][r] for fp64
 // (the fp64 instruction interleaves the row groups; checked on gfx950 with a
 // known-input product). The inner index is a free summation variable, which
-// lets each lane read its A entries with 16-byte loads (see wave_block),
-// while the 16 lanes of a group read 16 consecutive entries of one B row.
+// lets each lane read its A entries with 16-byte loads (see wave_block); the
+// output columns are free to permute too, which lets a lane read two adjacent
+// B entries for the two column tiles of its wave in one load.
 //
-// Launch shape. Each workgroup is a single wave that owns one 32 x 32 (or
-// 16 x 16) tile of a C block: a finished wave frees its slot at once, so a
-// short segment never holds a SIMD while a long neighbour runs. The
-// dispatcher hands workgroup w to XCD w % 8, and each XCD has its own L2.
+// Two launch shapes:
+//  * b = 16 and 32: each workgroup is a single wave that owns one C block
+//    (the batch kernels use the same shape at b = 64, one wave per 32 x 32
+//    tile): a finished wave frees its slot at once, so a short segment never
+//    holds a SIMD while a long neighbour runs.
+//  * b = 64: one workgroup of four waves per C block, each wave a 32 x 32
+//    tile; the block products are staged in LDS once per workgroup and every
+//    wave reads its operand panels from there (k_numeric_f64_b64,
+//    k_numeric_f32_b64, k_numeric_bf16x3_b64).
+// The dispatcher hands workgroup w to XCD w % 8, and each XCD has its own L2.
 // Consecutive C blocks in Morton order share most of their A and B blocks,
-// so the launch gives each XCD runs of 2^XCD_CHUNK_LOG (1024) consecutive tiles
-// (XCD x takes runs x, x+8, x+16, ...) instead of every eighth tile:
-// neighbours then meet in the same L2, while the interleaved runs keep the
-// eight XCDs equally loaded. C is written with non-temporal stores, since no
-// later step of the multiply reads it.
+// so the launch gives each XCD runs of consecutive tiles (1024 single-wave
+// tiles, or 256 four-wave C blocks; XCD x takes runs x, x+8, x+16, ...)
+// instead of every eighth tile: neighbours then meet in the same L2, while
+// the interleaved runs keep the eight XCDs equally loaded. C is written with
+// non-temporal stores, since no later step of the multiply reads it.
 //
 // The same per-wave routines serve one multiply (k_numeric: one launch over
 // the C blocks of C) and a batch of independent multiplies (k_batch_*: one
