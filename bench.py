@@ -26,6 +26,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "block-product TFLOP/s and MFMA-peak fraction, split vs FP64 path at stated error"
 PEAK = {"f64": 78.6, "f32": 157.3, "bf16x3": 2516.6}   # dense MFMA TFLOP/s, MI355X
+HBM_PEAK_GBS = 8000.0                                   # HBM3E, MI355X
 
 
 def log(*a):
@@ -521,6 +522,23 @@ def main():
         paths[prec] = entry
 
     peak = PEAK[args.prec] if args.prec != "bf16x3" else PEAK["f32"]
+    # the numeric kernel's bound: MFMA when its arithmetic intensity over the
+    # algorithmic bytes is above the ridge point peak / HBM bandwidth, else HBM
+    intensity = flops / alg_bytes
+    ridge = peak * 1e12 / (HBM_PEAK_GBS * 1e9)
+    num_s = main_r["numeric_ms"] * 1e-3
+    if intensity >= ridge:
+        roof = {"bound": "mfma", "achieved": main_r["numeric_tflops"], "peak": peak, "unit": "TFLOP/s",
+                "frac": main_r["numeric_tflops"] / peak}
+    else:
+        gbs = alg_bytes / num_s / 1e9
+        roof = {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS,
+                "achieved_tflops": main_r["numeric_tflops"]}
+    roof.update({"traffic": measured_traffic("qt_numeric.hip", args.workload, args.prec),
+                 "algorithmic_bytes": alg_bytes, "arithmetic_intensity": intensity, "ridge": ridge,
+                 "kernel": "k_numeric (block GEMM per C block)",
+                 "probe_tflops": probe,
+                 "frac_of_probe": main_r["numeric_tflops"] / (probe if args.prec != "bf16x3" else probe / 3.0)})
     out = {
         "metric": METRIC,
         "value": main_r["tflops"],
@@ -537,13 +555,7 @@ def main():
         "config": {"workload": args.workload, "n": A.n_rows, "b": b, "leaf": leaf, "nnz_A": A.nnz,
                    "block_products": P, "nnz_C": main_r["nnz_C"], "prec": args.prec, "op": "C = A*A"},
         "mfma_peak_frac": main_r["tflops"] / peak,
-        "roofline": {"bound": "mfma", "achieved": main_r["numeric_tflops"], "peak": peak, "unit": "TFLOP/s",
-                     "frac": main_r["numeric_tflops"] / peak,
-                     "traffic": measured_traffic("qt_numeric.hip", args.workload, args.prec),
-                     "algorithmic_bytes": alg_bytes,
-                     "kernel": "k_numeric (block GEMM per C block)",
-                     "probe_tflops": probe,
-                     "frac_of_probe": main_r["numeric_tflops"] / (probe if args.prec != "bf16x3" else probe / 3.0)},
+        "roofline": roof,
         "cpu_baseline": cpu,
         "host_to_host": None if pcie_ms is None else {
             "ms": pcie_ms, "tflops": flops / (pcie_ms * 1e-3) / 1e12,
