@@ -202,6 +202,8 @@ struct NumericArgs {
     const int32_t* prodB;     // per product: block index into B
     const int32_t* seg;       // nseg + 1 offsets into the product lists
     int32_t nseg;
+    const int32_t* order;     // launch slot q computes C block order[q] (a permutation
+                              // of 0 .. nseg-1); nullptr: block q, i.e. Morton order
     void* C;                  // fp64 or fp32 C blocks, one per segment
 };
 void launch_numeric(const NumericArgs& a, hipStream_t s);

@@ -553,6 +553,59 @@ __global__ __launch_bounds__(64 * W) void k_leaf_fill(LeafStep st) {
     }
 }
 
+// ------------------------------------------------ launch order of C's blocks
+//
+// The numeric kernels give each XCD runs of consecutive launch slots. With
+// the blocks taken leaf row by leaf row (leaves left to right, the blocks of
+// a leaf in Morton order), a run of about a thousand blocks is a strip a leaf
+// high across many leaf columns: the strip's A block rows stay in the XCD's
+// L2 while B streams past, instead of the square patch of C that a run in
+// Morton order covers. Measured on gfx950 this helps only the fp64 kernel at
+// b <= 32 when a C block has several block products (decay32768: 2.3%
+// faster); where C blocks average about one product the kernel is bound by
+// writing C, which Morton order keeps contiguous (random65536: 10% slower in
+// strips), and the fp32, split and b = 64 kernels gain nothing or lose. So
+// the order is built for fp64 at b <= 32 and used when the products are at
+// least twice the C blocks. It comes from a table of leaf positions,
+// row-major: position p holds the C leaf there (or -1), and a scan over the
+// positions' block counts gives each leaf its first slot.
+__global__ void k_order_clear(int32_t* __restrict__ table, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) table[i] = -1;
+}
+
+__global__ void k_order_place(const uint64_t* __restrict__ lkey, const int32_t* __restrict__ ncount, int32_t ncap,
+                              int64_t rows, int64_t cols, int32_t* __restrict__ table) {
+    const int32_t c = (int32_t)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (c >= ncap || c >= *ncount) return;
+    const uint64_t k = lkey[c];
+    const int64_t r = morton_row(k), q = morton_col(k);
+    if (r < rows && q < cols) table[r * cols + q] = c;   // always true for a leaf of C
+}
+
+__global__ void k_order_counts(const int32_t* __restrict__ table, int64_t n, const uint64_t* __restrict__ lmo,
+                               int32_t* __restrict__ cnt) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int32_t c = table[i];
+    cnt[i] = c >= 0 ? __popcll(lmo[c]) : 0;
+}
+
+__global__ void k_order_fill(const int32_t* __restrict__ table, int64_t n, const int32_t* __restrict__ lbase,
+                             const int32_t* __restrict__ cnt, const int32_t* __restrict__ off, int32_t cap,
+                             int32_t* __restrict__ order) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int32_t c = table[i];
+    if (c < 0) return;
+    const int32_t o = off[i], b0 = lbase[c], m = cnt[i];
+    for (int32_t j = 0; j < m; ++j)
+        if (o + j < cap) order[o + j] = b0 + j;
+}
+
+// leaf positions up to which the launch order is built (a 16 MiB table)
+constexpr int64_t ORDER_MAX_POSITIONS = int64_t(1) << 22;
+
 // ----------------------------------------------------------- host side
 
 // Reading C's counts back. Instead of a device-to-host copy followed by a
@@ -823,6 +876,11 @@ void symbolic(qt_matrix* A, qt_matrix* B, qt_prec prec, hipStream_t s, SymbolicO
 
     // ---- plan the two allocations
     const int64_t cap = std::min<int64_t>(P, lb2 * ncap[L]);   // bound on C blocks
+    // leaf grid of C (row-major positions) for the launch order in leaf-row strips
+    const int64_t c_rows_all = op.ta ? A->n_cols : A->n_rows, c_cols_all = op.tb ? B->n_rows : B->n_cols;
+    const int64_t lrows = (c_rows_all + A->leaf - 1) / A->leaf, lcols = (c_cols_all + A->leaf - 1) / A->leaf;
+    const int64_t lpos = lrows * lcols;
+    const bool make_order = prec == QT_F64 && A->b <= 32 && lpos <= ORDER_MAX_POSITIONS;
     ArenaPlan keep, tmp;   // keep: C's tree; tmp: scratch freed after the call
     std::vector<size_t> o_child(L), o_key(L + 1);
     for (int l = 0; l < L; ++l) o_child[l] = keep.take(4 * ncap[l] * sizeof(int32_t));
@@ -854,6 +912,14 @@ void symbolic(qt_matrix* A, qt_matrix* B, qt_prec prec, hipStream_t s, SymbolicO
     const size_t o_prodA = tmp.take(P * sizeof(int32_t));
     const size_t o_prodB = tmp.take(P * sizeof(int32_t));
     const size_t o_cbseg = tmp.take((cap + 1) * sizeof(int32_t));
+    size_t o_otab = 0, o_ocnt = 0, o_ooff = 0, o_oscan = 0, o_order = 0;
+    if (make_order) {
+        o_otab = tmp.take(lpos * sizeof(int32_t));
+        o_ocnt = tmp.take(lpos * sizeof(int32_t));
+        o_ooff = tmp.take((lpos + 1) * sizeof(int32_t));
+        o_oscan = tmp.take((scan_tmp_elems(lpos) + 1) * sizeof(int32_t));
+        o_order = tmp.take(cap * sizeof(int32_t));
+    }
     const size_t o_count = tmp.take((2 * L + 4) * sizeof(int32_t));
 
     out.C.reset(new_result(A, B, L, prec, s, op));
@@ -967,6 +1033,24 @@ void symbolic(qt_matrix* A, qt_matrix* B, qt_prec prec, hipStream_t s, SymbolicO
     QT_LEVEL_LAUNCH(k_leaf_count, ncap[L], leaf_wgs, ss, ls);
     if (!ls.use_agg) exclusive_scan(ls.cnt, ls.off, ncap[L], scan_tmp, ss);
     QT_LEVEL_LAUNCH(k_leaf_fill, ncap[L], leaf_wgs, ss, ls);
+    int32_t* order = nullptr;
+    if (make_order) {
+        int32_t* tab = (int32_t*)at(W, o_otab);
+        int32_t* ocnt = (int32_t*)at(W, o_ocnt);
+        int32_t* ooff = (int32_t*)at(W, o_ooff);
+        order = (int32_t*)at(W, o_order);
+        const unsigned gp = (unsigned)((lpos + 255) / 256);
+        k_order_clear<<<gp, 256, 0, ss>>>(tab, lpos);
+        QT_LAUNCH("k_order_clear");
+        k_order_place<<<(unsigned)((ncap[L] + 255) / 256), 256, 0, ss>>>(ls.ckey, ls.ncount, ls.ncap, lrows, lcols,
+                                                                          tab);
+        QT_LAUNCH("k_order_place");
+        k_order_counts<<<gp, 256, 0, ss>>>(tab, lpos, ls.lmo, ocnt);
+        QT_LAUNCH("k_order_counts");
+        exclusive_scan(ocnt, ooff, lpos, (int32_t*)at(W, o_oscan), ss);
+        k_order_fill<<<gp, 256, 0, ss>>>(tab, lpos, ls.lbase, ocnt, ooff, ls.cap, order);
+        QT_LAUNCH("k_order_fill");
+    }
     if (prof) QT_HIP(hipEventRecord(ev.e1, ss));
 
     // the one synchronization: node and block counts of C
@@ -1016,6 +1100,7 @@ void symbolic(qt_matrix* A, qt_matrix* B, qt_prec prec, hipStream_t s, SymbolicO
     na.prodA = ls.prodA;
     na.prodB = ls.prodB;
     na.seg = ls.cbseg;
+    na.order = (order && C->products >= 2 * (int64_t)nnzC) ? order : nullptr;
     na.nseg = nnzC;
     na.C = (prec == QT_F32) ? (void*)C->v32.p : (void*)C->v64.p;
     out.na = na;

@@ -292,11 +292,12 @@ __global__ __launch_bounds__(64, (MinWaves<T, BS>::value)) void k_numeric(const 
                                                 const int32_t* __restrict__ prodA,
                                                 const int32_t* __restrict__ prodB,
                                                 const int32_t* __restrict__ seg, int32_t nseg,
-                                                T* __restrict__ C) {
+                                                const int32_t* __restrict__ order, T* __restrict__ C) {
     typedef Geo<BS> G;
     const int64_t tile = xcd_logical<>(blockIdx.x);
-    const int64_t s = tile / G::WPB;
-    if (s >= nseg) return;
+    const int64_t q = tile / G::WPB;
+    if (q >= nseg) return;
+    const int64_t s = order ? order[q] : q;
     wave_block<T, BS>(A, B, prodA, prodB, seg[s], seg[s + 1], C + (size_t)s * (BS * BS), (int)(tile % G::WPB));
 }
 
@@ -308,11 +309,12 @@ __global__ __launch_bounds__(64) void k_numeric_bf16x3(const uint16_t* __restric
                                                        const int32_t* __restrict__ prodA,
                                                        const int32_t* __restrict__ prodB,
                                                        const int32_t* __restrict__ seg, int32_t nseg,
-                                                       double* __restrict__ C) {
+                                                       const int32_t* __restrict__ order, double* __restrict__ C) {
     constexpr int WPB = (BS / 32) * (BS / 32);
     const int64_t tile = xcd_logical<>(blockIdx.x);
-    const int64_t s = tile / WPB;
-    if (s >= nseg) return;
+    const int64_t q = tile / WPB;
+    if (q >= nseg) return;
+    const int64_t s = order ? order[q] : q;
     wave_block_bf16x3<BS>(Ahi, Alo, Bhi_t, Blo_t, prodA, prodB, seg[s], seg[s + 1], C + (size_t)s * (BS * BS),
                           (int)(tile % WPB));
 }
@@ -332,13 +334,14 @@ __global__ __launch_bounds__(256, 4) void k_numeric_f64_b64(const double* __rest
                                                          const int32_t* __restrict__ prodA,
                                                          const int32_t* __restrict__ prodB,
                                                          const int32_t* __restrict__ seg, int32_t nseg,
-                                                         double* __restrict__ C) {
+                                                         const int32_t* __restrict__ order, double* __restrict__ C) {
     constexpr int BS = 64, MT = 2, KH = 32;
     typedef double v2d_t __attribute__((ext_vector_type(2)));
     __shared__ __attribute__((aligned(16))) double la[64 * F64L_AROW];   // A[:, half]
     __shared__ __attribute__((aligned(16))) double lb[KH * F64L_BROW];   // B[half, :]
-    const int64_t s = xcd_logical<8>(blockIdx.x);
-    if (s >= nseg) return;   // uniform over the workgroup
+    const int64_t q = xcd_logical<8>(blockIdx.x);
+    if (q >= nseg) return;   // uniform over the workgroup
+    const int64_t s = order ? order[q] : q;
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
     const int r16 = lane & 15, g = lane >> 4;
@@ -434,13 +437,14 @@ __global__ __launch_bounds__(256) void k_numeric_f32_b64(const float* __restrict
                                                          const int32_t* __restrict__ prodA,
                                                          const int32_t* __restrict__ prodB,
                                                          const int32_t* __restrict__ seg, int32_t nseg,
-                                                         float* __restrict__ C) {
+                                                         const int32_t* __restrict__ order, float* __restrict__ C) {
     constexpr int BS = 64, MT = 2, KH = 32;
     typedef float v2f_t __attribute__((ext_vector_type(2)));
     __shared__ __attribute__((aligned(16))) float la[64 * F32L_AROW];   // A[:, half]
     __shared__ __attribute__((aligned(16))) float lb[KH * F32L_BROW];   // B[half, :]
-    const int64_t s = xcd_logical<8>(blockIdx.x);
-    if (s >= nseg) return;   // uniform over the workgroup
+    const int64_t q = xcd_logical<8>(blockIdx.x);
+    if (q >= nseg) return;   // uniform over the workgroup
+    const int64_t s = order ? order[q] : q;
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
     const int r16 = lane & 15, g = lane >> 4;
@@ -525,20 +529,20 @@ template <class T, int BS>
 static void launch_t(const NumericArgs& a, hipStream_t s) {
     if (sizeof(T) == 8 && BS == 64) {
         k_numeric_f64_b64<<<xcd_grid<8>(a.nseg), 256, 0, s>>>((const double*)a.A, (const double*)a.B, a.prodA,
-                                                             a.prodB, a.seg, a.nseg, (double*)a.C);
+                                                             a.prodB, a.seg, a.nseg, a.order, (double*)a.C);
         QT_LAUNCH("k_numeric_f64_b64");
         return;
     }
     if (sizeof(T) == 4 && BS == 64) {
         k_numeric_f32_b64<<<xcd_grid<8>(a.nseg), 256, 0, s>>>((const float*)a.A, (const float*)a.B, a.prodA,
-                                                             a.prodB, a.seg, a.nseg, (float*)a.C);
+                                                             a.prodB, a.seg, a.nseg, a.order, (float*)a.C);
         QT_LAUNCH("k_numeric_f32_b64");
         return;
     }
     typedef Geo<BS> G;
     const unsigned grid = xcd_grid<>((int64_t)a.nseg * G::WPB);
     k_numeric<T, BS><<<grid, 64, WaveCapLds<T, BS>::bytes, s>>>((const T*)a.A, (const T*)a.B, a.prodA, a.prodB,
-                                                                a.seg, a.nseg, (T*)a.C);
+                                                                a.seg, a.nseg, a.order, (T*)a.C);
     QT_LAUNCH("k_numeric");
 }
 
@@ -562,11 +566,13 @@ __global__ __launch_bounds__(256, 2) void k_numeric_bf16x3_b64(const uint16_t* _
                                                                 const int32_t* __restrict__ prodA,
                                                                 const int32_t* __restrict__ prodB,
                                                                 const int32_t* __restrict__ seg, int32_t nseg,
+                                                                const int32_t* __restrict__ order,
                                                                 double* __restrict__ C) {
     constexpr int BS = 64, MT = 2;
     __shared__ __attribute__((aligned(16))) uint16_t lds[4 * BFL_ARR];   // Ahi, Alo, Bhi^T, Blo^T
-    const int64_t s = xcd_logical<8>(blockIdx.x);
-    if (s >= nseg) return;   // uniform over the workgroup
+    const int64_t q = xcd_logical<8>(blockIdx.x);
+    if (q >= nseg) return;   // uniform over the workgroup
+    const int64_t s = order ? order[q] : q;
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
     const int r16 = lane & 15, g = lane >> 4;
@@ -662,14 +668,14 @@ static void launch_bf(const NumericArgs& a, hipStream_t s) {
     if (BS == 64) {
         const unsigned grid = xcd_grid<8>(a.nseg);
         k_numeric_bf16x3_b64<<<grid, 256, 0, s>>>(a.Ahi, a.Alo, a.Bhi_t, a.Blo_t, a.prodA, a.prodB, a.seg,
-                                                  a.nseg, (double*)a.C);
+                                                  a.nseg, a.order, (double*)a.C);
         QT_LAUNCH("k_numeric_bf16x3_b64");
         return;
     }
     constexpr int WPB = (BS / 32) * (BS / 32);
     const unsigned grid = xcd_grid<>((int64_t)a.nseg * WPB);
     k_numeric_bf16x3<BS><<<grid, 64, 0, s>>>(a.Ahi, a.Alo, a.Bhi_t, a.Blo_t, a.prodA, a.prodB, a.seg, a.nseg,
-                                             (double*)a.C);
+                                             a.order, (double*)a.C);
     QT_LAUNCH("k_numeric_bf16x3");
 }
 
