@@ -393,10 +393,18 @@ def main():
     b = A.b
     log(f"bench: n={A.n_rows} b={b} nnz(A)={A.nnz}; building on the GPU (leaf {leaf})")
     hA = qt.from_blockmatrix(A, leaf)
+    # the one-time operand forms of each path (fp32 copy, bf16 hi/lo split, and
+    # the block-transposed bf16 B), timed on the handle: the "cold" cost a first
+    # multiply at that precision pays on top of the warm step
+    prepare_ms = {}
     for p in ("f64", "f32", "bf16x3"):
         if p == "bf16x3" and b == 16:
             continue
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
         qt.prepare(hA, p)
+        torch.cuda.synchronize()
+        prepare_ms[p] = (time.perf_counter() - t0) * 1e3
     torch.cuda.synchronize()
 
     # the rate a register-only loop of the same MFMA instruction reaches on this GPU; run first, it also
@@ -495,6 +503,7 @@ def main():
         entry = {"tflops": r["tflops"], "ms_per_step": r["ms_per_step"], "numeric_ms": r["numeric_ms"],
                  "symbolic_ms": r["symbolic_ms"], "symbolic_span_in_loop_ms": r["symbolic_span_in_loop_ms"],
                  "single_call_ms": r["single_call_ms"], "numeric_tflops": r["numeric_tflops"],
+                 "prepare_ms": prepare_ms.get(prec),
                  "mfma_peak_frac": r["numeric_tflops"] / (PEAK["f32"] if prec == "bf16x3" else PEAK[prec]),
                  "speedup_vs_f64": (r["tflops"] / results["f64"]["tflops"]) if "f64" in results else None}
         if ref is not None:

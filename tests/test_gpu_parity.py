@@ -285,3 +285,34 @@ def test_bf16x3_split_form_is_what_is_computed(qt):
         same, e_max, e_f, e_cw = compare(ref, C, absAB)
         assert same
         assert e_cw <= 1.05 * (3 * b + 4) * 2.0 ** -24, e_cw
+
+
+@pytest.mark.parametrize("prec,b", [("f64", 32), ("f64", 16), ("bf16x3", 64)])
+def test_launch_order_shapes(qt, prec, b):
+    """Products with several block products per C block, where the fp64 (b <= 32)
+    and split (b = 64) kernels launch C blocks in leaf-row strips: rectangular,
+    ragged and transposed shapes against the oracle."""
+    from tests._util import transpose
+    rng = np.random.default_rng(700 + b)
+    m, k, n = (23, 41, 17) if b == 64 else (45, 61, 37)
+    for ta, tb, lb in ((False, False, 2), (True, False, 4), (False, True, 1), (True, True, 2)):
+        A = random_pattern(rng, k if ta else m, m if ta else k, 0.45, b)
+        B = random_pattern(rng, n if tb else k, k if tb else n, 0.45, b)
+        opA = transpose(A) if ta else A
+        opB = transpose(B) if tb else B
+        _say("launch order", prec, "b", b, "trans", ta, tb, "leaf", lb * b)
+        ref, ost = oracle.multiply(opA, opB, lb * b)
+        absref, _ = oracle.multiply(opA, opB, lb * b, use_abs=True)
+        hC = qt.multiply_ex(qt.from_blockmatrix(A, lb * b), qt.from_blockmatrix(B, lb * b), trans_a=ta,
+                            trans_b=tb, prec=prec)
+        st = hC.stats()
+        assert st["products"] == ost.block_products
+        assert st["products"] >= 2 * ref.nnz      # the strips are used for such products
+        I, J, V = hC.to_blocks("f64")
+        C = wl.BlockMatrix(m * b, n * b, b, I, J, V)
+        same, e_max, e_f, e_cw = compare(ref, C, absref)
+        assert same
+        if prec == "f64":
+            assert e_cw <= TOL64 and e_f <= TOL64, (e_cw, e_f)
+        else:
+            assert e_cw <= 3 * 2.0 ** -16 + (3 * b + 4) * 2.0 ** -24, e_cw
