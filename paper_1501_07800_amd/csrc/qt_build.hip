@@ -143,6 +143,70 @@ __global__ void k_level_counts(const uint64_t* __restrict__ keys, int64_t n, int
     }
 }
 
+// Every level's tables in one pass. flags[l*n + t] = 1 when block t starts a
+// node of level l (l = 0 .. L, L the leaves); with ex the exclusive scan of
+// the concatenated flags, block t lies in node rank(l, t) = ex[l*n + t + 1] -
+// ex[l*n] - 1 of level l.
+constexpr int MAX_FUSED_LEVELS = 32;
+struct LevelTables {
+    int32_t* child[MAX_FUSED_LEVELS];     // levels 0 .. L-1: 4 per node, -1 for NIL (cleared first)
+    uint64_t* key[MAX_FUSED_LEVELS];
+    int32_t* base;                         // leaves
+    uint64_t* lkey;
+    uint64_t* mo;
+    uint64_t* rm;
+    uint64_t* cm;
+};
+
+__device__ __forceinline__ int level_shift(int l, int L, int leaf_shift) { return leaf_shift + 2 * (L - l); }
+
+__global__ void k_level_flags(const uint64_t* __restrict__ keys, int64_t n, int L, int leaf_shift,
+                              int32_t* __restrict__ flags) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n) return;
+    const uint64_t k = keys[t], kp = t > 0 ? keys[t - 1] : 0;
+    for (int l = 0; l <= L; ++l) {
+        const int sh = level_shift(l, L, leaf_shift);
+        flags[(int64_t)l * n + t] = (t == 0 || (sh < 64 && (k >> sh) != (kp >> sh))) ? 1 : 0;
+    }
+}
+
+__global__ void k_level_fill(const uint64_t* __restrict__ keys, int64_t n, int L, int lb_log,
+                             const int32_t* __restrict__ flags, const int32_t* __restrict__ ex, LevelTables tb) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n) return;
+    const int leaf_shift = 2 * lb_log;
+    const uint64_t k = keys[t];
+    auto rank = [&](int l) { return ex[(int64_t)l * n + t + 1] - ex[(int64_t)l * n] - 1; };
+    for (int l = 0; l < L; ++l) {
+        const int sh = level_shift(l, L, leaf_shift);
+        if (flags[(int64_t)l * n + t]) tb.key[l][rank(l)] = sh < 64 ? (k >> sh) : 0;
+        if (flags[(int64_t)(l + 1) * n + t]) {   // t starts a child node: link it to its parent
+            const int shc = sh - 2;                 // the child level's shift
+            const int q = shc < 64 ? (int)((k >> shc) & 3) : 0;
+            tb.child[l][4 * (int64_t)rank(l) + q] = rank(l + 1);
+        }
+    }
+    if (!flags[(int64_t)L * n + t]) return;
+    // t starts a leaf: its base, key and masks
+    const int lb = 1 << lb_log;
+    const uint64_t lk = k >> leaf_shift;
+    const int32_t li = rank(L);
+    uint64_t m0 = 0, m1 = 0, m2 = 0;
+    for (int64_t u = t; u < n && (keys[u] >> leaf_shift) == lk; ++u) {
+        const uint32_t q = (uint32_t)(keys[u] & ((1ull << leaf_shift) - 1));
+        const uint32_t r = morton_row(q), c = morton_col(q);
+        m0 |= 1ull << q;
+        m1 |= 1ull << (r * lb + c);
+        m2 |= 1ull << (c * lb + r);
+    }
+    tb.base[li] = (int32_t)t;
+    tb.lkey[li] = lk;
+    tb.mo[li] = m0;
+    tb.rm[li] = m1;
+    tb.cm[li] = m2;
+}
+
 __global__ void k_hist(const uint64_t* __restrict__ keys, int64_t n, int32_t* __restrict__ rowcnt,
                        int32_t* __restrict__ colcnt) {
     int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -553,11 +617,64 @@ void build_tree_levels(qt_matrix* M, hipStream_t s) {
         QT_HIP(hipMemcpyAsync(counts.data(), dcnt.p, counts.size() * sizeof(int32_t), hipMemcpyDeviceToHost, s));
         QT_HIP(hipStreamSynchronize(s));
     }
+    const int32_t nleaves = counts[M->L];
+    const int64_t nflags = (int64_t)(M->L + 1) * n;
+    if (M->L < MAX_FUSED_LEVELS && nflags < (int64_t(1) << 31) - 2) {
+        // every level in a few launches: the tables live in one arena
+        ArenaPlan plan;
+        std::vector<size_t> o_child(M->L), o_key(M->L);
+        for (int l = 0; l < M->L; ++l) {
+            o_child[l] = plan.take(4 * (size_t)counts[l] * sizeof(int32_t));
+            o_key[l] = plan.take((size_t)counts[l] * sizeof(uint64_t));
+        }
+        const size_t child_end = plan.bytes;   // the child tables come first: one clear covers them
+        const size_t o_base = plan.take((size_t)nleaves * sizeof(int32_t));
+        const size_t o_lkey = plan.take((size_t)nleaves * sizeof(uint64_t));
+        const size_t o_mo = plan.take((size_t)nleaves * sizeof(uint64_t));
+        const size_t o_rm = plan.take((size_t)nleaves * sizeof(uint64_t));
+        const size_t o_cm = plan.take((size_t)nleaves * sizeof(uint64_t));
+        M->arena.alloc(plan.bytes, s);
+        char* base = M->arena.p;
+        LevelTables tb{};
+        for (int l = 0; l < M->L; ++l) {
+            TreeLevel& tl = M->levels[l];
+            tl.n = counts[l];
+            tl.child.view(base + o_child[l], 4 * (size_t)counts[l]);
+            tl.key.view(base + o_key[l], counts[l]);
+            tb.child[l] = tl.child.p;
+            tb.key[l] = tl.key.p;
+        }
+        LeafLevel& lv = M->leaves;
+        lv.n = nleaves;
+        lv.base.view(base + o_base, nleaves);
+        lv.key.view(base + o_lkey, nleaves);
+        lv.mask_mo.view(base + o_mo, nleaves);
+        lv.mask_rm.view(base + o_rm, nleaves);
+        lv.mask_cm.view(base + o_cm, nleaves);
+        tb.base = lv.base.p;
+        tb.lkey = lv.key.p;
+        tb.mo = lv.mask_mo.p;
+        tb.rm = lv.mask_rm.p;
+        tb.cm = lv.mask_cm.p;
+        if (child_end > 0) {
+            k_fill_i32<<<grid_for((int64_t)(child_end / sizeof(int32_t))), 256, 0, s>>>(
+                (int32_t*)base, (int64_t)(child_end / sizeof(int32_t)), -1);
+            QT_LAUNCH("k_fill_i32");
+        }
+        DBuf<int32_t> flags(nflags, s), ex(nflags + 1, s), tmp(scan_tmp_elems(nflags) + 1, s);
+        k_level_flags<<<grid_for(n), 256, 0, s>>>(M->bkey.p, n, M->L, shift, flags.p);
+        QT_LAUNCH("k_level_flags");
+        exclusive_scan(flags.p, ex.p, nflags, tmp.p, s);
+        k_level_fill<<<grid_for(n), 256, 0, s>>>(M->bkey.p, n, M->L, M->lb_log, flags.p, ex.p, tb);
+        QT_LAUNCH("k_level_fill");
+        return;
+    }
+
+    // very large inputs: level by level
     DBuf<int32_t> flags(n, s), ex(n + 1, s), tmp(scan_tmp_elems(n) + 1, s);
     k_run_flags<<<grid_for(n), 256, 0, s>>>(M->bkey.p, n, shift, flags.p);
     QT_LAUNCH("k_run_flags");
     exclusive_scan(flags.p, ex.p, n, tmp.p, s);
-    const int32_t nleaves = counts[M->L];
     LeafLevel& lv = M->leaves;
     lv.n = nleaves;
     lv.base.alloc(nleaves, s);

@@ -136,8 +136,9 @@ struct qt_matrix {
 
     std::vector<qt::TreeLevel> levels;   // levels 0 .. L-1
     qt::LeafLevel leaves;                // level L
-    qt::DBuf<char> arena;                // owns the tree arrays of a multiply result;
-                                         // for such a matrix the DBufs below view into it
+    qt::DBuf<char> arena;                // owns the tree arrays (of a multiply result, and of
+                                         // a built matrix unless it is very large); the DBufs
+                                         // below then view into it
 
     // derived operand forms (built on demand, guarded by mu)
     std::mutex mu;
