@@ -84,49 +84,6 @@ __global__ void k_gather_blocks(const T* __restrict__ src, const int32_t* __rest
     }
 }
 
-__global__ void k_run_flags(const uint64_t* __restrict__ keys, int64_t n, int shift, int32_t* __restrict__ flags) {
-    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= n) return;
-    flags[t] = (t == 0 || (keys[t] >> shift) != (keys[t - 1] >> shift)) ? 1 : 0;
-}
-
-// The first block of every leaf fills the leaf's base, key and masks.
-__global__ void k_leaf_fill(const uint64_t* __restrict__ keys, int64_t n, int lb_log,
-                            const int32_t* __restrict__ flags, const int32_t* __restrict__ ex,
-                            int32_t* __restrict__ base, uint64_t* __restrict__ lkey,
-                            uint64_t* __restrict__ mo, uint64_t* __restrict__ rm, uint64_t* __restrict__ cm) {
-    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= n || !flags[t]) return;
-    const int shift = 2 * lb_log;
-    const int lb = 1 << lb_log;
-    const uint64_t lk = keys[t] >> shift;
-    const int32_t li = ex[t];
-    uint64_t m0 = 0, m1 = 0, m2 = 0;
-    for (int64_t u = t; u < n && (keys[u] >> shift) == lk; ++u) {
-        uint32_t q = (uint32_t)(keys[u] & ((1ull << shift) - 1));
-        uint32_t r = morton_row(q), c = morton_col(q);
-        m0 |= 1ull << q;
-        m1 |= 1ull << (r * lb + c);
-        m2 |= 1ull << (c * lb + r);
-    }
-    base[li] = (int32_t)t;
-    lkey[li] = lk;
-    mo[li] = m0;
-    rm[li] = m1;
-    cm[li] = m2;
-}
-
-// Parents of a sorted, unique list of child keys.
-__global__ void k_parent_fill(const uint64_t* __restrict__ ck, int64_t nc, const int32_t* __restrict__ flags,
-                              const int32_t* __restrict__ ex, int32_t* __restrict__ child,
-                              uint64_t* __restrict__ pkey) {
-    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= nc) return;
-    int32_t p = ex[t + 1] - 1;
-    child[4 * p + (int)(ck[t] & 3)] = (int32_t)t;
-    if (flags[t]) pkey[p] = ck[t] >> 2;
-}
-
 // Node counts of every level at once from the sorted block keys: node
 // boundaries at level l are where the key prefix above shift(l) changes.
 // cnt[l] for l = 0 .. L (L: the leaves); one ballot per wave and level.
@@ -146,7 +103,8 @@ __global__ void k_level_counts(const uint64_t* __restrict__ keys, int64_t n, int
 // Every level's tables in one pass. flags[l*n + t] = 1 when block t starts a
 // node of level l (l = 0 .. L, L the leaves); with ex the exclusive scan of
 // the concatenated flags, block t lies in node rank(l, t) = ex[l*n + t + 1] -
-// ex[l*n] - 1 of level l.
+// ex[l*n] - 1 of level l. The flags and their scan are int32 while (L+1) n
+// fits, int64 beyond.
 constexpr int MAX_FUSED_LEVELS = 32;
 struct LevelTables {
     int32_t* child[MAX_FUSED_LEVELS];     // levels 0 .. L-1: 4 per node, -1 for NIL (cleared first)
@@ -160,8 +118,9 @@ struct LevelTables {
 
 __device__ __forceinline__ int level_shift(int l, int L, int leaf_shift) { return leaf_shift + 2 * (L - l); }
 
+template <class I>
 __global__ void k_level_flags(const uint64_t* __restrict__ keys, int64_t n, int L, int leaf_shift,
-                              int32_t* __restrict__ flags) {
+                              I* __restrict__ flags) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= n) return;
     const uint64_t k = keys[t], kp = t > 0 ? keys[t - 1] : 0;
@@ -171,13 +130,14 @@ __global__ void k_level_flags(const uint64_t* __restrict__ keys, int64_t n, int 
     }
 }
 
+template <class I>
 __global__ void k_level_fill(const uint64_t* __restrict__ keys, int64_t n, int L, int lb_log,
-                             const int32_t* __restrict__ flags, const int32_t* __restrict__ ex, LevelTables tb) {
+                             const I* __restrict__ flags, const I* __restrict__ ex, LevelTables tb) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= n) return;
     const int leaf_shift = 2 * lb_log;
     const uint64_t k = keys[t];
-    auto rank = [&](int l) { return ex[(int64_t)l * n + t + 1] - ex[(int64_t)l * n] - 1; };
+    auto rank = [&](int l) { return (int32_t)(ex[(int64_t)l * n + t + 1] - ex[(int64_t)l * n] - 1); };
     for (int l = 0; l < L; ++l) {
         const int sh = level_shift(l, L, leaf_shift);
         if (flags[(int64_t)l * n + t]) tb.key[l][rank(l)] = sh < 64 ? (k >> sh) : 0;
@@ -602,6 +562,18 @@ qt_matrix* build(int64_t n_rows, int64_t n_cols, int32_t b, int32_t leaf, int64_
 }
 
 // Leaves and levels above, from the sorted block keys of M.
+// The node-start flags of every level, their scan, and the tables from them.
+template <class I>
+static void fill_levels(qt_matrix* M, int64_t nflags, int shift, const LevelTables& tb, hipStream_t s) {
+    const int64_t n = M->nblocks;
+    DBuf<I> flags(nflags, s), ex(nflags + 1, s), tmp(scan_tmp_elems(nflags) + 1, s);
+    k_level_flags<I><<<grid_for(n), 256, 0, s>>>(M->bkey.p, n, M->L, shift, flags.p);
+    QT_LAUNCH("k_level_flags");
+    exclusive_scan(flags.p, ex.p, nflags, tmp.p, s);
+    k_level_fill<I><<<grid_for(n), 256, 0, s>>>(M->bkey.p, n, M->L, M->lb_log, flags.p, ex.p, tb);
+    QT_LAUNCH("k_level_fill");
+}
+
 void build_tree_levels(qt_matrix* M, hipStream_t s) {
     const int64_t n = M->nblocks;
     const int shift = 2 * M->lb_log;
@@ -619,92 +591,51 @@ void build_tree_levels(qt_matrix* M, hipStream_t s) {
     }
     const int32_t nleaves = counts[M->L];
     const int64_t nflags = (int64_t)(M->L + 1) * n;
-    if (M->L < MAX_FUSED_LEVELS && nflags < (int64_t(1) << 31) - 2) {
-        // every level in a few launches: the tables live in one arena
-        ArenaPlan plan;
-        std::vector<size_t> o_child(M->L), o_key(M->L);
-        for (int l = 0; l < M->L; ++l) {
-            o_child[l] = plan.take(4 * (size_t)counts[l] * sizeof(int32_t));
-            o_key[l] = plan.take((size_t)counts[l] * sizeof(uint64_t));
-        }
-        const size_t child_end = plan.bytes;   // the child tables come first: one clear covers them
-        const size_t o_base = plan.take((size_t)nleaves * sizeof(int32_t));
-        const size_t o_lkey = plan.take((size_t)nleaves * sizeof(uint64_t));
-        const size_t o_mo = plan.take((size_t)nleaves * sizeof(uint64_t));
-        const size_t o_rm = plan.take((size_t)nleaves * sizeof(uint64_t));
-        const size_t o_cm = plan.take((size_t)nleaves * sizeof(uint64_t));
-        M->arena.alloc(plan.bytes, s);
-        char* base = M->arena.p;
-        LevelTables tb{};
-        for (int l = 0; l < M->L; ++l) {
-            TreeLevel& tl = M->levels[l];
-            tl.n = counts[l];
-            tl.child.view(base + o_child[l], 4 * (size_t)counts[l]);
-            tl.key.view(base + o_key[l], counts[l]);
-            tb.child[l] = tl.child.p;
-            tb.key[l] = tl.key.p;
-        }
-        LeafLevel& lv = M->leaves;
-        lv.n = nleaves;
-        lv.base.view(base + o_base, nleaves);
-        lv.key.view(base + o_lkey, nleaves);
-        lv.mask_mo.view(base + o_mo, nleaves);
-        lv.mask_rm.view(base + o_rm, nleaves);
-        lv.mask_cm.view(base + o_cm, nleaves);
-        tb.base = lv.base.p;
-        tb.lkey = lv.key.p;
-        tb.mo = lv.mask_mo.p;
-        tb.rm = lv.mask_rm.p;
-        tb.cm = lv.mask_cm.p;
-        if (child_end > 0) {
-            k_fill_i32<<<grid_for((int64_t)(child_end / sizeof(int32_t))), 256, 0, s>>>(
-                (int32_t*)base, (int64_t)(child_end / sizeof(int32_t)), -1);
-            QT_LAUNCH("k_fill_i32");
-        }
-        DBuf<int32_t> flags(nflags, s), ex(nflags + 1, s), tmp(scan_tmp_elems(nflags) + 1, s);
-        k_level_flags<<<grid_for(n), 256, 0, s>>>(M->bkey.p, n, M->L, shift, flags.p);
-        QT_LAUNCH("k_level_flags");
-        exclusive_scan(flags.p, ex.p, nflags, tmp.p, s);
-        k_level_fill<<<grid_for(n), 256, 0, s>>>(M->bkey.p, n, M->L, M->lb_log, flags.p, ex.p, tb);
-        QT_LAUNCH("k_level_fill");
-        return;
+    if (M->L >= MAX_FUSED_LEVELS) fail(QT_ERR_UNSUPPORTED, "quadtree too deep");
+    ArenaPlan plan;
+    std::vector<size_t> o_child(M->L), o_key(M->L);
+    for (int l = 0; l < M->L; ++l) {
+        o_child[l] = plan.take(4 * (size_t)counts[l] * sizeof(int32_t));
+        o_key[l] = plan.take((size_t)counts[l] * sizeof(uint64_t));
     }
-
-    // very large inputs: level by level
-    DBuf<int32_t> flags(n, s), ex(n + 1, s), tmp(scan_tmp_elems(n) + 1, s);
-    k_run_flags<<<grid_for(n), 256, 0, s>>>(M->bkey.p, n, shift, flags.p);
-    QT_LAUNCH("k_run_flags");
-    exclusive_scan(flags.p, ex.p, n, tmp.p, s);
+    const size_t child_end = plan.bytes;   // the child tables come first: one clear covers them
+    const size_t o_base = plan.take((size_t)nleaves * sizeof(int32_t));
+    const size_t o_lkey = plan.take((size_t)nleaves * sizeof(uint64_t));
+    const size_t o_mo = plan.take((size_t)nleaves * sizeof(uint64_t));
+    const size_t o_rm = plan.take((size_t)nleaves * sizeof(uint64_t));
+    const size_t o_cm = plan.take((size_t)nleaves * sizeof(uint64_t));
+    M->arena.alloc(plan.bytes, s);
+    char* base = M->arena.p;
+    LevelTables tb{};
+    for (int l = 0; l < M->L; ++l) {
+        TreeLevel& tl = M->levels[l];
+        tl.n = counts[l];
+        tl.child.view(base + o_child[l], 4 * (size_t)counts[l]);
+        tl.key.view(base + o_key[l], counts[l]);
+        tb.child[l] = tl.child.p;
+        tb.key[l] = tl.key.p;
+    }
     LeafLevel& lv = M->leaves;
     lv.n = nleaves;
-    lv.base.alloc(nleaves, s);
-    lv.key.alloc(nleaves, s);
-    lv.mask_mo.alloc(nleaves, s);
-    lv.mask_rm.alloc(nleaves, s);
-    lv.mask_cm.alloc(nleaves, s);
-    k_leaf_fill<<<grid_for(n), 256, 0, s>>>(M->bkey.p, n, M->lb_log, flags.p, ex.p, lv.base.p, lv.key.p,
-                                            lv.mask_mo.p, lv.mask_rm.p, lv.mask_cm.p);
-    QT_LAUNCH("k_leaf_fill");
-
-    const uint64_t* ck = lv.key.p;
-    int64_t nc = nleaves;
-    for (int l = M->L - 1; l >= 0; --l) {
-        DBuf<int32_t> f(nc, s), e(nc + 1, s), t2(scan_tmp_elems(nc) + 1, s);
-        k_run_flags<<<grid_for(nc), 256, 0, s>>>(ck, nc, 2, f.p);
-        QT_LAUNCH("k_run_flags");
-        exclusive_scan(f.p, e.p, nc, t2.p, s);
-        const int32_t np = counts[l];
-        TreeLevel& tl = M->levels[l];
-        tl.n = np;
-        tl.child.alloc(4 * (int64_t)np, s);
-        tl.key.alloc(np, s);
-        k_fill_i32<<<grid_for(4 * (int64_t)np), 256, 0, s>>>(tl.child.p, 4 * (int64_t)np, -1);
+    lv.base.view(base + o_base, nleaves);
+    lv.key.view(base + o_lkey, nleaves);
+    lv.mask_mo.view(base + o_mo, nleaves);
+    lv.mask_rm.view(base + o_rm, nleaves);
+    lv.mask_cm.view(base + o_cm, nleaves);
+    tb.base = lv.base.p;
+    tb.lkey = lv.key.p;
+    tb.mo = lv.mask_mo.p;
+    tb.rm = lv.mask_rm.p;
+    tb.cm = lv.mask_cm.p;
+    if (child_end > 0) {
+        const int64_t words = (int64_t)(child_end / sizeof(int32_t));
+        k_fill_i32<<<grid_for(words), 256, 0, s>>>((int32_t*)base, words, -1);
         QT_LAUNCH("k_fill_i32");
-        k_parent_fill<<<grid_for(nc), 256, 0, s>>>(ck, nc, f.p, e.p, tl.child.p, tl.key.p);
-        QT_LAUNCH("k_parent_fill");
-        ck = tl.key.p;
-        nc = np;
     }
+    if (nflags < (int64_t(1) << 31) - 2)
+        fill_levels<int32_t>(M, nflags, shift, tb, s);
+    else
+        fill_levels<int64_t>(M, nflags, shift, tb, s);
 }
 
 // ------------------------------------------------------------ copy out
