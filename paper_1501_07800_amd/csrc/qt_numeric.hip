@@ -66,14 +66,14 @@ template <> struct Mfma<float> {
 // Tile geometry for block size BS: each wave computes a WT x WT tile made of
 // MT x MT 16x16 MFMA tiles; WPB waves cover one C block; the inner dimension
 // is walked in chunks of KC with KS 4-deep MFMA steps each. A chunk's loads
-// are issued together and then consumed by its MFMAs; chunks of 16 (rather
-// than a whole 32-deep product) keep each wave's bursts of loads short, which
-// interleaves the waves of a SIMD better (measured on gfx950).
+// are issued together and then consumed by its MFMAs. With the paired B
+// loads a whole 32-deep product per chunk is 2% faster than chunks of 16 for
+// fp64 at b = 32 and the same for fp32 (measured on gfx950).
 template <int BS> struct Geo {
     static constexpr int WT = BS < 32 ? BS : 32;
     static constexpr int MT = WT / 16;
     static constexpr int WPB = (BS / WT) * (BS / WT);
-    static constexpr int KC = 16;
+    static constexpr int KC = BS < 32 ? BS : 32;
     static constexpr int KS = KC / 4;
     static constexpr int NCH = BS / KC;
 };
