@@ -65,15 +65,18 @@ template <> struct Mfma<float> {
 
 // Tile geometry for block size BS: each wave computes a WT x WT tile made of
 // MT x MT 16x16 MFMA tiles; WPB waves cover one C block; the inner dimension
-// is walked in chunks of KC with KS 4-deep MFMA steps each. A chunk's loads
-// are issued together and then consumed by its MFMAs. With the paired B
-// loads a whole 32-deep product per chunk is 2% faster than chunks of 16 for
-// fp64 at b = 32 and the same for fp32 (measured on gfx950).
+// is walked in chunks of KC with KS 4-deep MFMA steps each. All of a chunk's
+// loads are issued before its MFMAs (a scheduling barrier keeps the compiler
+// from sinking them next to their first use, which left each wave only one
+// to three loads in flight); the next chunk's loads may still rise above the
+// current chunk's MFMAs. Measured on gfx950 at b = 32 against the compiler's
+// own interleaving: fp64 6% and fp32 8% faster on decay32768, fp64 6% faster
+// and fp32 6% slower on random65536.
 template <int BS> struct Geo {
     static constexpr int WT = BS < 32 ? BS : 32;
     static constexpr int MT = WT / 16;
     static constexpr int WPB = (BS / WT) * (BS / WT);
-    static constexpr int KC = BS < 32 ? BS : 32;
+    static constexpr int KC = 16;
     static constexpr int KS = KC / 4;
     static constexpr int NCH = BS / KC;
 };
@@ -165,6 +168,7 @@ __device__ __forceinline__ void wave_block(const T* __restrict__ A, const T* __r
                     for (int e = 0; e < VEC; ++e)
                         br[0][v * VEC + e] = b[(ch * G::KC + v * 4 * VEC + g * VEC + e) * BS + wn + r16];
             }
+            __builtin_amdgcn_sched_barrier(0);   // the chunk's loads stay above this point
 #pragma unroll
             for (int ks = 0; ks < G::KS; ++ks)
 #pragma unroll
@@ -246,6 +250,7 @@ __device__ __forceinline__ void wave_block_bf16x3(const uint16_t* __restrict__ A
                 bh[nt] = load8(Bhi_t + o);
                 bl[nt] = load8(Blo_t + o);
             }
+            __builtin_amdgcn_sched_barrier(0);   // as in wave_block: loads first (5% faster at b = 32)
 #pragma unroll
             for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
@@ -273,19 +278,12 @@ __device__ __forceinline__ void wave_block_bf16x3(const uint16_t* __restrict__ A
 
 // ------------------------------------------------------ one multiply
 
-// Waves per SIMD. The b = 32 fp64 kernel runs best at six: it needs 62
-// VGPRs, so eight would fit, but at eight it is 8% slower, at five 3% and at
-// four 6% (measured on gfx950; more waves per CU means more operand blocks
-// in flight through one L2). MinWaves makes the compiler fit at least that
-// many; the launch caps the count at six by reserving LDS that the kernel
-// does not use: a CU's 160 KiB hold 24 workgroups of 6656 bytes, six
-// single-wave workgroups per SIMD. The other instances run at what their
-// registers allow.
-constexpr int LDS_PER_CU = 160 * 1024;
+// Waves per SIMD the compiler must fit: five for the b = 32 fp64 kernel
+// (82 VGPRs with a whole chunk's operands in flight), which measured best on
+// gfx950 (four and six within 1%, three 7% slower); the other instances fit
+// eight by themselves.
 template <class T, int BS> struct MinWaves { static constexpr int value = 1; };
-template <> struct MinWaves<double, 32> { static constexpr int value = 6; };
-template <class T, int BS> struct WaveCapLds { static constexpr unsigned bytes = 0; };
-template <> struct WaveCapLds<double, 32> { static constexpr unsigned bytes = (LDS_PER_CU / (4 * 6)) & ~511u; };
+template <> struct MinWaves<double, 32> { static constexpr int value = 5; };
 
 template <class T, int BS>
 __global__ __launch_bounds__(64, (MinWaves<T, BS>::value)) void k_numeric(const T* __restrict__ A, const T* __restrict__ B,
@@ -541,8 +539,8 @@ static void launch_t(const NumericArgs& a, hipStream_t s) {
     }
     typedef Geo<BS> G;
     const unsigned grid = xcd_grid<>((int64_t)a.nseg * G::WPB);
-    k_numeric<T, BS><<<grid, 64, WaveCapLds<T, BS>::bytes, s>>>((const T*)a.A, (const T*)a.B, a.prodA, a.prodB,
-                                                                a.seg, a.nseg, a.order, (T*)a.C);
+    k_numeric<T, BS><<<grid, 64, 0, s>>>((const T*)a.A, (const T*)a.B, a.prodA, a.prodB, a.seg, a.nseg, a.order,
+                                         (T*)a.C);
     QT_LAUNCH("k_numeric");
 }
 
