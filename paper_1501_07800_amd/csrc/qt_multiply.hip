@@ -560,13 +560,15 @@ __global__ __launch_bounds__(64 * W) void k_leaf_fill(LeafStep st) {
 // a leaf in Morton order), a run of about a thousand blocks is a strip a leaf
 // high across many leaf columns: the strip's A block rows stay in the XCD's
 // L2 while B streams past, instead of the square patch of C that a run in
-// Morton order covers. Measured on gfx950 this helps the fp64 kernel at
-// b <= 32 and the split kernel at b = 64 when a C block has several block
-// products (decay32768 fp64: 2.3% faster, decay131072 split: 2.4%); where C
-// blocks average about one product the kernel is bound by writing C, which
-// Morton order keeps contiguous (random65536 fp64: 10% slower in strips), and
-// the other kernels gain nothing or lose. So the order is built for those
-// two kernels and used when the products are at least twice the C blocks. It comes from a table of leaf positions,
+// Morton order covers. Measured on gfx950 this helps only the split kernel at
+// b = 64 when a C block has several block products (decay131072: 2.4%
+// faster); where C blocks average about one product a kernel is bound by
+// writing C, which Morton order keeps contiguous (random65536 fp64: 10%
+// slower in strips), and the other kernels gain nothing or lose (the b = 32
+// fp64 kernel gained 2.3% before its loads were issued ahead of the MFMAs,
+// and is 1% slower in strips since). So the order is built for the split
+// kernel at b = 64 and used when the products are at least twice the C
+// blocks. It comes from a table of leaf positions,
 // row-major: position p holds the C leaf there (or -1), and a scan over the
 // positions' block counts gives each leaf its first slot.
 __global__ void k_order_clear(int32_t* __restrict__ table, int64_t n) {
@@ -880,8 +882,7 @@ void symbolic(qt_matrix* A, qt_matrix* B, qt_prec prec, hipStream_t s, SymbolicO
     const int64_t c_rows_all = op.ta ? A->n_cols : A->n_rows, c_cols_all = op.tb ? B->n_rows : B->n_cols;
     const int64_t lrows = (c_rows_all + A->leaf - 1) / A->leaf, lcols = (c_cols_all + A->leaf - 1) / A->leaf;
     const int64_t lpos = lrows * lcols;
-    const bool make_order = ((prec == QT_F64 && A->b <= 32) || (prec == QT_BF16X3 && A->b == 64)) &&
-                            lpos <= ORDER_MAX_POSITIONS;
+    const bool make_order = prec == QT_BF16X3 && A->b == 64 && lpos <= ORDER_MAX_POSITIONS;
     ArenaPlan keep, tmp;   // keep: C's tree; tmp: scratch freed after the call
     std::vector<size_t> o_child(L), o_key(L + 1);
     for (int l = 0; l < L; ++l) o_child[l] = keep.take(4 * ncap[l] * sizeof(int32_t));

@@ -289,9 +289,9 @@ def test_bf16x3_split_form_is_what_is_computed(qt):
 
 @pytest.mark.parametrize("prec,b", [("f64", 32), ("f64", 16), ("bf16x3", 64)])
 def test_launch_order_shapes(qt, prec, b):
-    """Products with several block products per C block, where the fp64 (b <= 32)
-    and split (b = 64) kernels launch C blocks in leaf-row strips: rectangular,
-    ragged and transposed shapes against the oracle."""
+    """Products with several block products per C block (the split kernel at
+    b = 64 launches their C blocks in leaf-row strips; fp64 keeps Morton
+    order): rectangular, ragged and transposed shapes against the oracle."""
     from tests._util import transpose
     rng = np.random.default_rng(700 + b)
     m, k, n = (23, 41, 17) if b == 64 else (45, 61, 37)
@@ -307,7 +307,7 @@ def test_launch_order_shapes(qt, prec, b):
                             trans_b=tb, prec=prec)
         st = hC.stats()
         assert st["products"] == ost.block_products
-        assert st["products"] >= 2 * ref.nnz      # the strips are used for such products
+        assert st["products"] >= 2 * ref.nnz      # where the split kernel uses the strips
         I, J, V = hC.to_blocks("f64")
         C = wl.BlockMatrix(m * b, n * b, b, I, J, V)
         same, e_max, e_f, e_cw = compare(ref, C, absref)
