@@ -142,3 +142,54 @@ def test_decay131072_sampled(qt):
                            lambda k: 3 * 2.0 ** -16 + (3 * b + 4) * 2.0 ** -24, 4 * 2.0 ** -126, b)
         assert C.stats()["products"] == oracle.product_count(A, A)
         C.free()
+
+
+def test_random65536_split_full(qt):
+    e = _full_case(qt, "random65536", ["bf16x3"])
+    assert e["bf16x3"] <= 3 * 2.0 ** -16 + (3 * 32 + 4) * 2.0 ** -24
+
+
+@pytest.mark.slow
+def test_batch64_full(qt):
+    """The 64-problem batch at its full size in the benchmark's launch
+    configuration (leaf size per pattern class from the tuner, the tuned
+    schedule, graph replay, fp32): every plan result equals the single
+    multiply bit for bit, its pattern equals the boolean product, and sampled
+    blocks of every problem agree with the definition within the fp32 bound."""
+    import math
+    probs = wl.batch_mix(64, 5)
+    b = probs[0][0].b
+    cache, hs = {}, []
+    for A, B in probs:
+        fill = max(A.nnz, 1) / float(A.nb_rows * A.nb_cols)
+        cls = (A.meta.get("pattern"), int(round(math.log2(A.nb_rows))), int(round(math.log2(fill * 1000))))
+        if cls not in cache:
+            cache[cls], _ = qt.tune_leaf(qt.from_blockmatrix(A, 8 * b), qt.from_blockmatrix(B, 8 * b), "f32", reps=1)
+        hs.append((qt.from_blockmatrix(A, cache[cls]), qt.from_blockmatrix(B, cache[cls])))
+    _say("batch64: leaves", sorted(set(cache.values())))
+    plan = qt.Plan([a for a, _ in hs], [h for _, h in hs], "f32")
+    sched, _ = plan.tune(reps=1)
+    _say("batch64: schedule", sched)
+    for _ in range(2):
+        plan.execute(graph=True)
+    rng = np.random.default_rng(55)
+    for i, ((A, B), (ha, hb)) in enumerate(zip(probs, hs)):
+        Cp = plan.result(i)
+        Cs = qt.multiply(ha, hb, "f32")
+        Ip, Jp, Vp = Cp.to_blocks("f32")
+        Is, Js, Vs = Cs.to_blocks("f32")
+        assert np.array_equal(Ip, Is) and np.array_equal(Jp, Js) and np.array_equal(Vp, Vs), i
+        pos_ref = oracle.pattern_by_definition(A, B)
+        assert np.array_equal(Ip.astype(np.int64) * B.nb_cols + Jp, pos_ref), i
+        if len(Ip) == 0:
+            continue
+        idx = oracle.make_index(A, B)
+        absA = wl.BlockMatrix(A.n_rows, A.n_cols, b, A.I, A.J, np.abs(A.V))
+        absB = wl.BlockMatrix(B.n_rows, B.n_cols, b, B.I, B.J, np.abs(B.V))
+        for t in rng.choice(len(Ip), size=min(3, len(Ip)), replace=False):
+            ref = oracle.block_by_definition(A, B, Ip[t], Jp[t], idx)
+            absref = oracle.block_by_definition(absA, absB, Ip[t], Jp[t], idx)
+            k = len(set(idx[0].get(int(Ip[t]), {})) & set(idx[1].get(int(Jp[t]), {})))
+            err = np.abs(Vp[t].astype(np.float64) - ref)
+            assert np.all(err <= (k * b + 2) * 2.0 ** -24 * absref + 4 * 2.0 ** -126 * k * b), (i, t)
+        Cs.free()
