@@ -90,8 +90,12 @@ qt_status qt_build(int64_t n_rows, int64_t n_cols, int32_t block_size, int32_t l
  * numeric phase runs one MFMA block GEMM per C block, accumulating in
  * registers, and stores each C block once. The result's value type follows
  * `prec` (F64 and BF16X3 give fp64 C, F32 gives fp32 C).
- * Synchronizes `stream` once, to read the number of C blocks before C's
- * values are allocated.
+ * The symbolic phase runs on a stream of the library (one per device, default
+ * priority), since it reads only the operands' structure; the host waits for
+ * it once, to read the number of C blocks before C's values are allocated,
+ * but does not wait for work already queued on `stream`. The numeric kernel
+ * is queued on `stream` behind an event of that phase, and the call returns
+ * without waiting for it: C is ready in stream order on `stream`.
  * Errors: ARG, SHAPE, OOM, DEVICE, UNSUPPORTED (more than 2^31 - 1 products).
  */
 qt_status qt_multiply(const qt_matrix* A, const qt_matrix* B, qt_prec prec,
