@@ -33,7 +33,11 @@
 // known on the host before any launch (from per-level row/column counts of
 // both operands), so all buffers are sized up front in two allocations (the
 // result's tree, and scratch); the single synchronization reads back how many
-// C blocks there are before C's values are allocated.
+// C blocks there are before C's values are allocated. A level's per-node
+// arrays and its grids are sized by a bound on its C nodes: the smaller of its
+// pair count and the number of node positions C's shape has at that level.
+// The whole phase runs on a stream of the library, beside the caller's (see
+// side_stream below).
 #include "qt_internal.h"
 #include "qt_morton.h"
 
