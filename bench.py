@@ -75,6 +75,25 @@ def calibrate_copy():
     print(json.dumps({"copy_bytes": COPY_BYTES, "copies": 3}), flush=True)
 
 
+def roofline_bound(flops: float, alg_bytes: float, numeric_ms: float, peak_tflops: float) -> dict:
+    """The numeric kernel's roofline: MFMA-bound when its arithmetic intensity
+    over the algorithmic bytes is at least the ridge point (peak / HBM
+    bandwidth), reported in TFLOP/s; else HBM-bound, reported in GB/s of
+    algorithmic bytes against the HBM peak."""
+    intensity = flops / alg_bytes
+    ridge = peak_tflops * 1e12 / (HBM_PEAK_GBS * 1e9)
+    tflops = flops / (numeric_ms * 1e-3) / 1e12
+    if intensity >= ridge:
+        roof = {"bound": "mfma", "achieved": tflops, "peak": peak_tflops, "unit": "TFLOP/s",
+                "frac": tflops / peak_tflops}
+    else:
+        gbs = alg_bytes / (numeric_ms * 1e-3) / 1e9
+        roof = {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS,
+                "achieved_tflops": tflops}
+    roof.update({"algorithmic_bytes": alg_bytes, "arithmetic_intensity": intensity, "ridge": ridge})
+    return roof
+
+
 def _pmc_mean_kib(csv_path, counter, name_part):
     import csv
     vals = [float(r["Counter_Value"]) for r in csv.DictReader(open(csv_path))
@@ -531,20 +550,8 @@ def main():
         paths[prec] = entry
 
     peak = PEAK[args.prec] if args.prec != "bf16x3" else PEAK["f32"]
-    # the numeric kernel's bound: MFMA when its arithmetic intensity over the
-    # algorithmic bytes is above the ridge point peak / HBM bandwidth, else HBM
-    intensity = flops / alg_bytes
-    ridge = peak * 1e12 / (HBM_PEAK_GBS * 1e9)
-    num_s = main_r["numeric_ms"] * 1e-3
-    if intensity >= ridge:
-        roof = {"bound": "mfma", "achieved": main_r["numeric_tflops"], "peak": peak, "unit": "TFLOP/s",
-                "frac": main_r["numeric_tflops"] / peak}
-    else:
-        gbs = alg_bytes / num_s / 1e9
-        roof = {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS,
-                "achieved_tflops": main_r["numeric_tflops"]}
+    roof = roofline_bound(flops, alg_bytes, main_r["numeric_ms"], peak)
     roof.update({"traffic": measured_traffic("qt_numeric.hip", args.workload, args.prec),
-                 "algorithmic_bytes": alg_bytes, "arithmetic_intensity": intensity, "ridge": ridge,
                  "kernel": "k_numeric (block GEMM per C block)",
                  "probe_tflops": probe,
                  "frac_of_probe": main_r["numeric_tflops"] / (probe if args.prec != "bf16x3" else probe / 3.0)})

@@ -1,0 +1,58 @@
+"""CPU: the host-side logic of bench.py (no GPU): the roofline's choice of
+bound, the digest that keys measured traffic to the kernels' code, and the
+refusal to run on more than one GPU."""
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+import bench  # noqa: E402
+
+
+def test_roofline_bound_mfma_and_hbm():
+    # decay32768: 58.25 GFLOP over 1.355 GB (43 flop/B) -> MFMA-bound at fp64
+    r = bench.roofline_bound(58.25e9, 1.355e9, 1.2, bench.PEAK["f64"])
+    assert r["bound"] == "mfma" and r["unit"] == "TFLOP/s"
+    assert r["achieved"] == pytest.approx(58.25e9 / 1.2e-3 / 1e12)
+    assert r["frac"] == pytest.approx(r["achieved"] / 78.6)
+    # random65536: 56.24 GFLOP over 6.70 GB (8.4 flop/B) is below the fp64 ridge (9.8) -> HBM-bound
+    r = bench.roofline_bound(56.24e9, 6.70e9, 2.6, bench.PEAK["f64"])
+    assert r["bound"] == "hbm" and r["unit"] == "GB/s" and r["peak"] == 8000.0
+    assert r["achieved"] == pytest.approx(6.70e9 / 2.6e-3 / 1e9)
+    assert r["ridge"] == pytest.approx(78.6e12 / 8e12)
+    # the same bytes at fp32 (half the C bytes) against the fp32 ridge (19.7)
+    assert bench.roofline_bound(56.24e9, 3.35e9, 1.3, bench.PEAK["f32"])["bound"] == "hbm"
+
+
+def test_code_digest_ignores_comments_only(tmp_path):
+    a = tmp_path / "a.hip"
+    b = tmp_path / "b.hip"
+    c = tmp_path / "c.hip"
+    a.write_text("int f(int x) { return x + 1; }  // add one\n/* block */\n")
+    b.write_text("// a comment first\nint f(int x)\n{\n    return x + 1;\n}\n")
+    c.write_text("int f(int x) { return x + 2; }\n")
+    assert bench.code_digest(str(a)) == bench.code_digest(str(b))
+    assert bench.code_digest(str(a)) != bench.code_digest(str(c))
+
+
+def test_measured_traffic_keyed_to_code():
+    # a workload with no counter record has no traffic; a committed record is
+    # used only while the numeric source's code is the one it was taken with
+    assert bench.measured_traffic("qt_numeric.hip", "no-such-workload", "f64") is None
+    rec = os.path.join(ROOT, "profiles", "traffic_f64_decay32768.json")
+    if os.path.exists(rec):
+        import json
+        d = json.load(open(rec))
+        src = os.path.join(ROOT, "paper_1501_07800_amd", "csrc", "qt_numeric.hip")
+        expect = d["traffic_bytes"] if d.get("code_sha256") == bench.code_digest(src) else None
+        assert bench.measured_traffic("qt_numeric.hip", "decay32768", "f64") == expect
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
