@@ -33,28 +33,36 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def code_digest(path: str) -> str:
-    """SHA-256 of a C++/HIP source with its comments and whitespace removed:
+def code_digest(*paths: str) -> str:
+    """SHA-256 of C++/HIP sources with their comments and whitespace removed:
     it changes when the code changes, not when only a comment does."""
     import hashlib
     import re
-    text = open(path, encoding="utf-8").read()
-    text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
-    text = re.sub(r"//[^\n]*", " ", text)
-    return hashlib.sha256("".join(text.split()).encode()).hexdigest()
+    h = hashlib.sha256()
+    for path in paths:
+        text = open(path, encoding="utf-8").read()
+        text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", " ", text)
+        h.update("".join(text.split()).encode() + b"\0")
+    return h.hexdigest()
 
 
-def measured_traffic(kernel_source: str, workload: str, prec: str):
+# what a numeric kernel's HBM traffic depends on: the kernels, and the order
+# in which the multiply launches C's blocks
+TRAFFIC_SOURCES = tuple(os.path.join(ROOT, "paper_1501_07800_amd", "csrc", f)
+                        for f in ("qt_numeric.hip", "qt_multiply.hip"))
+
+
+def measured_traffic(workload: str, prec: str):
     """HBM bytes per launch of the numeric kernel from the committed rocprofv3
     counter summary (FETCH_SIZE and WRITE_SIZE, scaled by a plain copy's
     reading), or None when there is none for this workload or the kernels'
-    code has changed since the counters were taken."""
+    code or launch order has changed since the counters were taken."""
     path = os.path.join(ROOT, "profiles", f"traffic_{prec}_{workload}.json")
     if not os.path.exists(path):
         return None
     rec = json.load(open(path))
-    src = os.path.join(ROOT, "paper_1501_07800_amd", "csrc", kernel_source)
-    if rec.get("code_sha256") != code_digest(src):
+    if rec.get("code_sha256") != code_digest(*TRAFFIC_SOURCES):
         return None
     return rec.get("traffic_bytes")
 
@@ -121,12 +129,11 @@ def traffic_from_counters(fetch_csv, write_csv, copy_fetch_csv, copy_write_csv, 
     kw, nw = _pmc_mean_kib(write_csv, "WRITE_SIZE", kname)
     fetch = kf * 1024.0 * f_scale
     write = kw * 1024.0 * w_scale
-    src = os.path.join(ROOT, "paper_1501_07800_amd", "csrc", "qt_numeric.hip")
     rec = {"kernel": kname, "workload": workload, "prec": prec,
            "fetch_kib_per_dispatch": kf, "write_kib_per_dispatch": kw, "dispatches": [nf, nw],
            "copy_fetch_kib": cf, "copy_write_kib": cw, "fetch_scale": f_scale, "write_scale": w_scale,
            "fetch_bytes": fetch, "write_bytes": write, "traffic_bytes": fetch + write,
-           "code_sha256": code_digest(src)}
+           "code_sha256": code_digest(*TRAFFIC_SOURCES)}
     out = os.path.join(ROOT, "profiles", f"traffic_{prec}_{workload}.json")
     json.dump(rec, open(out, "w"), indent=1)
     print(json.dumps(rec), flush=True)
@@ -551,7 +558,7 @@ def main():
 
     peak = PEAK[args.prec] if args.prec != "bf16x3" else PEAK["f32"]
     roof = roofline_bound(flops, alg_bytes, main_r["numeric_ms"], peak)
-    roof.update({"traffic": measured_traffic("qt_numeric.hip", args.workload, args.prec),
+    roof.update({"traffic": measured_traffic(args.workload, args.prec),
                  "kernel": "k_numeric (block GEMM per C block)",
                  "probe_tflops": probe,
                  "frac_of_probe": main_r["numeric_tflops"] / (probe if args.prec != "bf16x3" else probe / 3.0)})

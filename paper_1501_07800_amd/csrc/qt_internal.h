@@ -130,7 +130,6 @@ struct qt_matrix {
     hipStream_t stream = nullptr;
 
     qt::DBuf<uint64_t> bkey;  // Morton key of each block, ascending
-    qt::DBuf<int32_t> bI, bJ; // block coordinates in Morton order
     qt::DBuf<double> v64;     // values (fp64), Morton order, when vtype == QT_F64
     qt::DBuf<float> v32;      // values (fp32), when vtype == QT_F32 or prepared
 
@@ -263,8 +262,10 @@ struct SymbolicOut {
 struct MulOp {
     int ta = 0, tb = 0, upper = 0;
 };
+// launch_order: also build the launch order of C's blocks that suits the
+// product, for a numeric kernel launched from out.na (a batch plan does not)
 void symbolic(qt_matrix* A, qt_matrix* B, qt_prec prec, hipStream_t s, SymbolicOut& out,
-              bool allow_profile = true, const MulOp& op = MulOp{});
+              bool allow_profile = true, const MulOp& op = MulOp{}, bool launch_order = true);
 qt_matrix* multiply(qt_matrix* A, qt_matrix* B, qt_prec prec, hipStream_t s, const MulOp& op = MulOp{});
 qt_matrix* build(int64_t n_rows, int64_t n_cols, int32_t b, int32_t leaf, int64_t nblocks, const int32_t* I,
                  const int32_t* J, const double* values, qt_mem where, hipStream_t s);

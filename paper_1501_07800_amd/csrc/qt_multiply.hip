@@ -612,6 +612,84 @@ __global__ void k_order_fill(const int32_t* __restrict__ table, int64_t n, const
 // leaf positions up to which the launch order is built (a 16 MiB table)
 constexpr int64_t ORDER_MAX_POSITIONS = int64_t(1) << 22;
 
+// Where C blocks average fewer than two block products (an unstructured
+// pattern such as random65536), neighbouring C blocks in Morton order share
+// no operand, and nearly every block product fetches its A and B blocks from
+// beyond L2. Taking the C blocks grouped by the inner index k of their first
+// product instead puts C(i,j) = A(i,k) B(k,j) for all i and j of one k into
+// consecutive launch slots: the run an XCD receives reads block column k of
+// A and block row k of B, both small enough to stay in its L2, and the
+// blocks of each are fetched about once (random65536 fp64: 2.4 GB fetched
+// instead of 11.8 GB). A counting sort over k without global atomics: each
+// workgroup counts its KORDER_WG C blocks per k in LDS, an exclusive scan of
+// the counts taken k-major over (k, workgroup) gives each workgroup its first
+// slot for every k, and a second pass places the blocks. Inside one
+// workgroup and one k the slots are claimed by LDS atomics, so that order
+// varies from call to call; each C block is still computed by one wave with
+// its products in ascending k, so no result depends on it.
+constexpr int KORDER_THREADS = 256, KORDER_ITEMS = 16;
+constexpr int64_t KORDER_WG = KORDER_THREADS * KORDER_ITEMS;   // C blocks per workgroup
+constexpr int64_t KORDER_MAX_K = 16384;                        // LDS table of 64 KiB
+constexpr int64_t KORDER_MAX_CELLS = int64_t(1) << 24;         // (k, workgroup) counts
+
+__device__ __forceinline__ int32_t first_k(const uint64_t* __restrict__ akey, const int32_t* __restrict__ prodA,
+                                           const int32_t* __restrict__ seg, int64_t s, bool ta, int32_t kdim) {
+    const uint64_t key = akey[prodA[seg[s]]];
+    const int64_t k = ta ? (int64_t)morton_row(key) : (int64_t)morton_col(key);   // column of op(A)
+    return (int32_t)(k < 0 ? 0 : (k >= kdim ? kdim - 1 : k));
+}
+
+// k of the workgroup's C blocks (-1 past the end), loaded before any use
+__device__ __forceinline__ void korder_keys(const uint64_t* __restrict__ akey, const int32_t* __restrict__ prodA,
+                                            const int32_t* __restrict__ seg, int32_t nseg, bool ta, int32_t kdim,
+                                            int32_t (&kk)[KORDER_ITEMS]) {
+    const int64_t base = (int64_t)blockIdx.x * KORDER_WG + threadIdx.x;
+#pragma unroll
+    for (int j = 0; j < KORDER_ITEMS; ++j) {
+        const int64_t s = base + j * KORDER_THREADS;
+        kk[j] = s < nseg ? first_k(akey, prodA, seg, s, ta, kdim) : -1;
+    }
+}
+
+// cnt[k * nwg + w]: C blocks of workgroup w whose first product has inner index k
+__global__ __launch_bounds__(KORDER_THREADS) void k_korder_counts(const uint64_t* __restrict__ akey,
+                                                                  const int32_t* __restrict__ prodA,
+                                                                  const int32_t* __restrict__ seg, int32_t nseg,
+                                                                  bool ta, int32_t kdim, int32_t nwg,
+                                                                  int32_t* __restrict__ cnt) {
+    extern __shared__ int32_t tab[];
+    int32_t kk[KORDER_ITEMS];
+    korder_keys(akey, prodA, seg, nseg, ta, kdim, kk);
+    for (int32_t k = threadIdx.x; k < kdim; k += KORDER_THREADS) tab[k] = 0;
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < KORDER_ITEMS; ++j)
+        if (kk[j] >= 0) atomicAdd(&tab[kk[j]], 1);
+    __syncthreads();
+    for (int32_t k = threadIdx.x; k < kdim; k += KORDER_THREADS) cnt[(int64_t)k * nwg + blockIdx.x] = tab[k];
+}
+
+// off: the exclusive scan of cnt; order[slot] = C block
+__global__ __launch_bounds__(KORDER_THREADS) void k_korder_place(const uint64_t* __restrict__ akey,
+                                                                 const int32_t* __restrict__ prodA,
+                                                                 const int32_t* __restrict__ seg, int32_t nseg,
+                                                                 bool ta, int32_t kdim, int32_t nwg,
+                                                                 const int32_t* __restrict__ off,
+                                                                 int32_t* __restrict__ order) {
+    extern __shared__ int32_t tab[];
+    int32_t kk[KORDER_ITEMS];
+    korder_keys(akey, prodA, seg, nseg, ta, kdim, kk);
+    for (int32_t k = threadIdx.x; k < kdim; k += KORDER_THREADS) tab[k] = off[(int64_t)k * nwg + blockIdx.x];
+    __syncthreads();
+    const int64_t base = (int64_t)blockIdx.x * KORDER_WG + threadIdx.x;
+#pragma unroll
+    for (int j = 0; j < KORDER_ITEMS; ++j)
+        if (kk[j] >= 0) {
+            const int32_t o = atomicAdd(&tab[kk[j]], 1);
+            if (o >= 0 && o < nseg) order[o] = (int32_t)(base + j * KORDER_THREADS);
+        }
+}
+
 // ----------------------------------------------------------- host side
 
 // Reading C's counts back. Instead of a device-to-host copy followed by a
@@ -801,7 +879,7 @@ static qt_matrix* empty_result(const qt_matrix* A, const qt_matrix* B, int L, qt
 // array, plus the product lists the numeric phase reads (kept in
 // out.scratch). Synchronizes once. out.na.nseg == 0 means C has no blocks.
 void symbolic(qt_matrix* A, qt_matrix* B, qt_prec prec, hipStream_t s, SymbolicOut& out, bool allow_profile,
-              const MulOp& op) {
+              const MulOp& op, bool launch_order) {
     if (prec != QT_F64 && prec != QT_F32 && prec != QT_BF16X3) fail(QT_ERR_ARG, "unknown precision");
     if (A->b != B->b || A->leaf != B->leaf) fail(QT_ERR_SHAPE, "operands differ in block or leaf size");
     const int64_t a_cols = op.ta ? A->n_rows : A->n_cols;   // op(A) = A or A^T
@@ -886,7 +964,13 @@ void symbolic(qt_matrix* A, qt_matrix* B, qt_prec prec, hipStream_t s, SymbolicO
     const int64_t c_rows_all = op.ta ? A->n_cols : A->n_rows, c_cols_all = op.tb ? B->n_rows : B->n_cols;
     const int64_t lrows = (c_rows_all + A->leaf - 1) / A->leaf, lcols = (c_cols_all + A->leaf - 1) / A->leaf;
     const int64_t lpos = lrows * lcols;
-    const bool make_order = prec == QT_BF16X3 && A->b == 64 && lpos <= ORDER_MAX_POSITIONS;
+    const bool make_order = launch_order && prec == QT_BF16X3 && A->b == 64 && lpos <= ORDER_MAX_POSITIONS;
+    // the order by inner index is built once C's block count is known, if
+    // the products are then fewer than twice the C blocks (cap bounds those)
+    const int64_t kdim = ((op.ta ? A->n_rows : A->n_cols) + A->b - 1) / A->b;
+    const int64_t kwg_cap = (cap + KORDER_WG - 1) / KORDER_WG;   // workgroups of the counting sort
+    const bool may_korder =
+        launch_order && P < 2 * cap && kdim >= 1 && kdim <= KORDER_MAX_K && kdim * kwg_cap <= KORDER_MAX_CELLS;
     ArenaPlan keep, tmp;   // keep: C's tree; tmp: scratch freed after the call
     std::vector<size_t> o_child(L), o_key(L + 1);
     for (int l = 0; l < L; ++l) o_child[l] = keep.take(4 * ncap[l] * sizeof(int32_t));
@@ -924,8 +1008,14 @@ void symbolic(qt_matrix* A, qt_matrix* B, qt_prec prec, hipStream_t s, SymbolicO
         o_ocnt = tmp.take(lpos * sizeof(int32_t));
         o_ooff = tmp.take((lpos + 1) * sizeof(int32_t));
         o_oscan = tmp.take((scan_tmp_elems(lpos) + 1) * sizeof(int32_t));
-        o_order = tmp.take(cap * sizeof(int32_t));
     }
+    size_t o_kcnt = 0, o_knext = 0, o_kscan = 0;
+    if (may_korder) {
+        o_kcnt = tmp.take(kdim * kwg_cap * sizeof(int32_t));
+        o_knext = tmp.take((kdim * kwg_cap + 1) * sizeof(int32_t));
+        o_kscan = tmp.take((scan_tmp_elems(kdim * kwg_cap) + 1) * sizeof(int32_t));
+    }
+    if (make_order || may_korder) o_order = tmp.take(cap * sizeof(int32_t));   // one order is used at most
     const size_t o_count = tmp.take((2 * L + 4) * sizeof(int32_t));
 
     out.C.reset(new_result(A, B, L, prec, s, op));
@@ -1039,12 +1129,11 @@ void symbolic(qt_matrix* A, qt_matrix* B, qt_prec prec, hipStream_t s, SymbolicO
     QT_LEVEL_LAUNCH(k_leaf_count, ncap[L], leaf_wgs, ss, ls);
     if (!ls.use_agg) exclusive_scan(ls.cnt, ls.off, ncap[L], scan_tmp, ss);
     QT_LEVEL_LAUNCH(k_leaf_fill, ncap[L], leaf_wgs, ss, ls);
-    int32_t* order = nullptr;
+    int32_t* order = (make_order || may_korder) ? (int32_t*)at(W, o_order) : nullptr;
     if (make_order) {
         int32_t* tab = (int32_t*)at(W, o_otab);
         int32_t* ocnt = (int32_t*)at(W, o_ocnt);
         int32_t* ooff = (int32_t*)at(W, o_ooff);
-        order = (int32_t*)at(W, o_order);
         const unsigned gp = (unsigned)((lpos + 255) / 256);
         k_order_clear<<<gp, 256, 0, ss>>>(tab, lpos);
         QT_LAUNCH("k_order_clear");
@@ -1062,15 +1151,6 @@ void symbolic(qt_matrix* A, qt_matrix* B, qt_prec prec, hipStream_t s, SymbolicO
     // the one synchronization: node and block counts of C
     std::vector<int32_t> hc(2 * L + 4);
     read_back_counts(dcount, (int)hc.size(), ss, hc.data());
-    {
-        // work the caller queues on s from here on (the numeric kernel first)
-        // follows the traversal
-        hipEvent_t done = nullptr;
-        QT_HIP(hipEventCreateWithFlags(&done, hipEventDisableTiming));
-        QT_HIP(hipEventRecord(done, ss));
-        QT_HIP(hipStreamWaitEvent(s, done, 0));
-        QT_HIP(hipEventDestroy(done));
-    }
     for (int l = 0; l <= L; ++l) {
         if (hc[l] < 0 || hc[l] > ncap[l]) fail(QT_ERR_DEVICE, "symbolic phase: C node count out of range");
         const int64_t expect = (l < L) ? pairs[l + 1] : P;
@@ -1081,6 +1161,33 @@ void symbolic(qt_matrix* A, qt_matrix* B, qt_prec prec, hipStream_t s, SymbolicO
     C->products = hc[2 * L + 2];
     const int32_t nnzC = hc[L + 1];
     if (nnzC < 0 || nnzC > cap || (nnzC == 0 && !op.upper)) fail(QT_ERR_DEVICE, "symbolic phase: C block count out of range");
+
+    const bool leafrow = make_order && C->products >= 2 * (int64_t)nnzC;
+    const bool korder = may_korder && nnzC > 0 && C->products < 2 * (int64_t)nnzC;
+    if (korder) {
+        int32_t* kcnt = (int32_t*)at(W, o_kcnt);
+        int32_t* knext = (int32_t*)at(W, o_knext);
+        const uint64_t* akey = A->bkey.p;
+        const int64_t nwg = (nnzC + KORDER_WG - 1) / KORDER_WG;   // <= kwg_cap, as nnzC <= cap
+        const size_t lds = (size_t)kdim * sizeof(int32_t);
+        k_korder_counts<<<(unsigned)nwg, KORDER_THREADS, lds, ss>>>(akey, ls.prodA, ls.cbseg, nnzC, op.ta,
+                                                                     (int32_t)kdim, (int32_t)nwg, kcnt);
+        QT_LAUNCH("k_korder_counts");
+        exclusive_scan(kcnt, knext, kdim * nwg, (int32_t*)at(W, o_kscan), ss);
+        k_korder_place<<<(unsigned)nwg, KORDER_THREADS, lds, ss>>>(akey, ls.prodA, ls.cbseg, nnzC, op.ta,
+                                                                    (int32_t)kdim, (int32_t)nwg, knext, order);
+        QT_LAUNCH("k_korder_place");
+        if (prof) QT_HIP(hipEventRecord(ev.e1, ss));   // the symbolic phase ends here then
+    }
+    {
+        // work the caller queues on s from here on (the numeric kernel first)
+        // follows the traversal
+        hipEvent_t done = nullptr;
+        QT_HIP(hipEventCreateWithFlags(&done, hipEventDisableTiming));
+        QT_HIP(hipEventRecord(done, ss));
+        QT_HIP(hipStreamWaitEvent(s, done, 0));
+        QT_HIP(hipEventDestroy(done));
+    }
 
     // C's tree: views into its arena
     for (int l = 0; l < L; ++l) {
@@ -1106,7 +1213,7 @@ void symbolic(qt_matrix* A, qt_matrix* B, qt_prec prec, hipStream_t s, SymbolicO
     na.prodA = ls.prodA;
     na.prodB = ls.prodB;
     na.seg = ls.cbseg;
-    na.order = (order && C->products >= 2 * (int64_t)nnzC) ? order : nullptr;
+    na.order = (leafrow || korder) ? order : nullptr;
     na.nseg = nnzC;
     na.C = (prec == QT_F32) ? (void*)C->v32.p : (void*)C->v64.p;
     out.na = na;

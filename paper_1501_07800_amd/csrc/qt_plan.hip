@@ -72,7 +72,7 @@ qt_plan* plan_create(int32_t count, const qt_matrix* const* A, const qt_matrix* 
     std::vector<int64_t> prods(count, 0);
     for (int32_t i = 0; i < count; ++i) {
         SymbolicOut sym;
-        symbolic(const_cast<qt_matrix*>(A[i]), const_cast<qt_matrix*>(B[i]), prec, s, sym, false);
+        symbolic(const_cast<qt_matrix*>(A[i]), const_cast<qt_matrix*>(B[i]), prec, s, sym, false, MulOp{}, false);
         na[i] = sym.na;
         prods[i] = sym.C->products;
         plan->results[i] = std::move(sym.C);

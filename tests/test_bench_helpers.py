@@ -36,19 +36,23 @@ def test_code_digest_ignores_comments_only(tmp_path):
     c.write_text("int f(int x) { return x + 2; }\n")
     assert bench.code_digest(str(a)) == bench.code_digest(str(b))
     assert bench.code_digest(str(a)) != bench.code_digest(str(c))
+    # several sources: each one's code counts, and where one ends
+    assert bench.code_digest(str(a), str(c)) != bench.code_digest(str(a), str(a))
+    assert bench.code_digest(str(a), str(c)) == bench.code_digest(str(b), str(c))
 
 
 def test_measured_traffic_keyed_to_code():
     # a workload with no counter record has no traffic; a committed record is
-    # used only while the numeric source's code is the one it was taken with
-    assert bench.measured_traffic("qt_numeric.hip", "no-such-workload", "f64") is None
+    # used only while the numeric kernels and the launch order are the code
+    # it was taken with
+    assert bench.measured_traffic("no-such-workload", "f64") is None
+    assert [os.path.basename(p) for p in bench.TRAFFIC_SOURCES] == ["qt_numeric.hip", "qt_multiply.hip"]
     rec = os.path.join(ROOT, "profiles", "traffic_f64_decay32768.json")
     if os.path.exists(rec):
         import json
         d = json.load(open(rec))
-        src = os.path.join(ROOT, "paper_1501_07800_amd", "csrc", "qt_numeric.hip")
-        expect = d["traffic_bytes"] if d.get("code_sha256") == bench.code_digest(src) else None
-        assert bench.measured_traffic("qt_numeric.hip", "decay32768", "f64") == expect
+        expect = d["traffic_bytes"] if d.get("code_sha256") == bench.code_digest(*bench.TRAFFIC_SOURCES) else None
+        assert bench.measured_traffic("decay32768", "f64") == expect
 
 
 def test_more_than_one_gpu_is_refused():

@@ -316,3 +316,36 @@ def test_launch_order_shapes(qt, prec, b):
             assert e_cw <= TOL64 and e_f <= TOL64, (e_cw, e_f)
         else:
             assert e_cw <= 3 * 2.0 ** -16 + (3 * b + 4) * 2.0 ** -24, e_cw
+
+
+@pytest.mark.parametrize("prec,b", [("f64", 32), ("f64", 16), ("f64", 64), ("f32", 32), ("bf16x3", 64)])
+def test_inner_index_order_shapes(qt, prec, b):
+    """Products with fewer than two block products per C block (the C blocks
+    are then launched grouped by the inner index of their first product):
+    rectangular, ragged and transposed shapes against the oracle."""
+    from tests._util import transpose
+    rng = np.random.default_rng(900 + b)
+    m, k, n = (29, 47, 23) if b == 64 else (53, 71, 43)
+    for ta, tb, lb in ((False, False, 2), (True, False, 4), (False, True, 1), (True, True, 2)):
+        A = random_pattern(rng, k if ta else m, m if ta else k, 0.07, b)
+        B = random_pattern(rng, n if tb else k, k if tb else n, 0.07, b)
+        opA = transpose(A) if ta else A
+        opB = transpose(B) if tb else B
+        _say("inner-index order", prec, "b", b, "trans", ta, tb, "leaf", lb * b)
+        ref, ost = oracle.multiply(opA, opB, lb * b)
+        absref, _ = oracle.multiply(opA, opB, lb * b, use_abs=True)
+        hC = qt.multiply_ex(qt.from_blockmatrix(A, lb * b), qt.from_blockmatrix(B, lb * b), trans_a=ta,
+                            trans_b=tb, prec=prec)
+        st = hC.stats()
+        assert st["products"] == ost.block_products
+        assert 0 < st["products"] < 2 * ref.nnz   # where the inner-index order is used
+        I, J, V = hC.to_blocks("f64")
+        C = wl.BlockMatrix(m * b, n * b, b, I, J, V)
+        same, e_max, e_f, e_cw = compare(ref, C, absref)
+        assert same
+        if prec == "f64":
+            assert e_cw <= TOL64 and e_f <= TOL64, (e_cw, e_f)
+        elif prec == "f32":
+            assert e_cw <= (k * b + 2) * 2.0 ** -24, e_cw
+        else:
+            assert e_cw <= 3 * 2.0 ** -16 + (3 * b + 4) * 2.0 ** -24, e_cw
