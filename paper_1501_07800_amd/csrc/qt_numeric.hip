@@ -296,7 +296,6 @@ __global__ __launch_bounds__(64, (MinWaves<T, BS>::value)) void k_numeric(const 
     const int64_t q = tile / G::WPB;
     if (q >= nseg) return;
     const int64_t s = order ? order[q] : q;
-    if ((uint64_t)s >= (uint64_t)nseg) return;   // not a C block: nothing to compute
     wave_block<T, BS>(A, B, prodA, prodB, seg[s], seg[s + 1], C + (size_t)s * (BS * BS), (int)(tile % G::WPB));
 }
 
@@ -314,7 +313,6 @@ __global__ __launch_bounds__(64) void k_numeric_bf16x3(const uint16_t* __restric
     const int64_t q = tile / WPB;
     if (q >= nseg) return;
     const int64_t s = order ? order[q] : q;
-    if ((uint64_t)s >= (uint64_t)nseg) return;   // not a C block: nothing to compute
     wave_block_bf16x3<BS>(Ahi, Alo, Bhi_t, Blo_t, prodA, prodB, seg[s], seg[s + 1], C + (size_t)s * (BS * BS),
                           (int)(tile % WPB));
 }
@@ -342,7 +340,6 @@ __global__ __launch_bounds__(256, 4) void k_numeric_f64_b64(const double* __rest
     const int64_t q = xcd_logical<8>(blockIdx.x);
     if (q >= nseg) return;   // uniform over the workgroup
     const int64_t s = order ? order[q] : q;
-    if ((uint64_t)s >= (uint64_t)nseg) return;   // not a C block: nothing to compute
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
     const int r16 = lane & 15, g = lane >> 4;
@@ -446,7 +443,6 @@ __global__ __launch_bounds__(256) void k_numeric_f32_b64(const float* __restrict
     const int64_t q = xcd_logical<8>(blockIdx.x);
     if (q >= nseg) return;   // uniform over the workgroup
     const int64_t s = order ? order[q] : q;
-    if ((uint64_t)s >= (uint64_t)nseg) return;   // not a C block: nothing to compute
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
     const int r16 = lane & 15, g = lane >> 4;
@@ -575,7 +571,6 @@ __global__ __launch_bounds__(256, 2) void k_numeric_bf16x3_b64(const uint16_t* _
     const int64_t q = xcd_logical<8>(blockIdx.x);
     if (q >= nseg) return;   // uniform over the workgroup
     const int64_t s = order ? order[q] : q;
-    if ((uint64_t)s >= (uint64_t)nseg) return;   // not a C block: nothing to compute
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
     const int r16 = lane & 15, g = lane >> 4;
