@@ -497,11 +497,14 @@ __device__ void leaf_fill_node(const LeafStep& st, int32_t c, int lane, int64_t 
         for (int t = 0; t < nb; ++t) {
             const uint64_t rat = lane_value(ra, t);
             const uint64_t cbt = lane_value(cb, t);
+            uint32_t m = on ? (mask_row(rat, i, lb) & mask_row(cbt, j, lb)) : 0u;
+            // most leaf pairs of an unstructured product add no block product
+            // to any block of this C leaf: skip their block positions
+            if (__ballot(m != 0) == 0) continue;
             const uint64_t amot = lane_value(amo, t);
             const uint64_t bmot = lane_value(bmo, t);
             const int32_t abt = (int32_t)lane_value((uint32_t)ab, t);
             const int32_t bbt = (int32_t)lane_value((uint32_t)bb, t);
-            uint32_t m = on ? (mask_row(rat, i, lb) & mask_row(cbt, j, lb)) : 0u;
             while (m) {
                 const int k = __ffs(m) - 1;
                 m &= m - 1;
