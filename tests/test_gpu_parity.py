@@ -349,3 +349,29 @@ def test_inner_index_order_shapes(qt, prec, b):
             assert e_cw <= (k * b + 2) * 2.0 ** -24, e_cw
         else:
             assert e_cw <= 3 * 2.0 ** -16 + (3 * b + 4) * 2.0 ** -24, e_cw
+
+
+def test_inner_index_order_repeatable(qt):
+    """Inside one inner index the launch slots are claimed by atomics and vary
+    from call to call; every C block is still computed by one wave in
+    ascending k, so repeated multiplies give bitwise equal results."""
+    rng = np.random.default_rng(913)
+    A = random_pattern(rng, 80, 96, 0.05, 32)
+    B = random_pattern(rng, 96, 72, 0.05, 32)
+    ref, ost = oracle.multiply(A, B, 128)
+    assert ost.block_products < 2 * ref.nnz
+    hA, hB = qt.from_blockmatrix(A, 128), qt.from_blockmatrix(B, 128)
+    for prec in ("f64", "f32", "bf16x3"):
+        first = None
+        for rep in range(3):
+            _say("inner-index order repeat", prec, rep)
+            hC = qt.multiply(hA, hB, prec)
+            out = hC.to_blocks("f64")
+            hC.free()
+            if first is None:
+                first = out
+                pos = np.sort(out[0].astype(np.int64) * B.nb_cols + out[1])
+                assert np.array_equal(pos, np.sort(ref.I.astype(np.int64) * B.nb_cols + ref.J))
+            else:
+                for x, y in zip(first, out):
+                    assert np.array_equal(x, y), prec
