@@ -351,6 +351,26 @@ def test_inner_index_order_shapes(qt, prec, b):
             assert e_cw <= 3 * 2.0 ** -16 + (3 * b + 4) * 2.0 ** -24, e_cw
 
 
+@pytest.mark.parametrize("kdim", [16384, 16385])
+def test_inner_index_order_widest(qt, kdim):
+    """The inner-index order counts C blocks per k in an LDS table of up to
+    16384 entries (64 KiB): an inner dimension of exactly that many blocks
+    uses the full table, one more keeps Morton order. Both against the
+    oracle."""
+    rng = np.random.default_rng(77)
+    A = random_pattern(rng, 40, kdim, 0.004, 16)
+    B = random_pattern(rng, kdim, 36, 0.004, 16)
+    _say("inner-index order, inner dimension", kdim)
+    ref, ost = oracle.multiply(A, B, 64)
+    absref, _ = oracle.multiply(A, B, 64, use_abs=True)
+    assert 0 < ost.block_products < 2 * ref.nnz
+    C, st, _ = gpu_multiply(qt, A, B, 64, "f64")
+    assert st["products"] == ost.block_products
+    same, e_max, e_f, e_cw = compare(ref, C, absref)
+    assert same
+    assert e_cw <= TOL64 and e_f <= TOL64, (e_cw, e_f)
+
+
 def test_inner_index_order_repeatable(qt):
     """Inside one inner index the launch slots are claimed by atomics and vary
     from call to call; every C block is still computed by one wave in
