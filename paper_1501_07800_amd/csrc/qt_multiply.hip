@@ -36,6 +36,9 @@
 // C blocks there are before C's values are allocated. A level's per-node
 // arrays and its grids are sized by a bound on its C nodes: the smaller of its
 // pair count and the number of node positions C's shape has at that level.
+// A launch order of C's blocks may also be built: leaf-row strips with the
+// traversal, or, once the C block count is known, a grouping by inner index
+// (see "launch order" below).
 // The whole phase runs on a stream of the library, beside the caller's (see
 // side_stream below).
 #include "qt_internal.h"
