@@ -192,6 +192,18 @@ qt_status qt_stats(const qt_matrix* C, int64_t* pairs, int32_t max_levels, int32
                    int64_t* products);
 
 /*
+ * Nodes of the quadtree per level (Sec. 3.1): nodes[l] is the number of
+ * non-NIL nodes at level l (0 = root .. n_levels-1 = leaf level). A zero
+ * submatrix is NIL at every level, so a multiply result keeps exactly the
+ * nodes with at least one stored block below them (a leaf pair with no block
+ * product, and a node over only such leaves, are NIL). At most max_levels
+ * entries are written; *n_levels (may be NULL) receives the depth + 1.
+ * Errors: ARG (NULL matrix, negative max_levels, NULL nodes with
+ * max_levels > 0).
+ */
+qt_status qt_levels(const qt_matrix* M, int64_t* nodes, int32_t max_levels, int32_t* n_levels);
+
+/*
  * Prepare the operand forms a multiply at `prec` reads (fp32 copy, bf16
  * hi/lo split) so that a later timed multiply does not build them. Optional:
  * qt_multiply builds them on first use. Thread-safe. Errors: OOM, DEVICE.

@@ -64,6 +64,8 @@ def _load():
     lib.qt_get_blocks.argtypes = [vp, i64, vp, vp, vp, vp, ctypes.c_int, ctypes.c_int, vp]
     lib.qt_stats.restype = ctypes.c_int
     lib.qt_stats.argtypes = [vp, i64p, i32, i32p, i64p]
+    lib.qt_levels.restype = ctypes.c_int
+    lib.qt_levels.argtypes = [vp, i64p, i32, i32p]
     lib.qt_prepare.restype = ctypes.c_int
     lib.qt_prepare.argtypes = [vp, ctypes.c_int, vp]
     lib.qt_free.restype = None
@@ -101,7 +103,7 @@ def _load():
 
 lib = _load()
 
-EXPORTS = ("qt_build", "qt_multiply", "qt_multiply_ex", "qt_add", "qt_truncate", "qt_sysq", "qt_info", "qt_to_blocks", "qt_get_blocks", "qt_stats", "qt_prepare", "qt_free",
+EXPORTS = ("qt_build", "qt_multiply", "qt_multiply_ex", "qt_add", "qt_truncate", "qt_sysq", "qt_info", "qt_to_blocks", "qt_get_blocks", "qt_stats", "qt_levels", "qt_prepare", "qt_free",
            "qt_plan_create", "qt_plan_execute", "qt_plan_tune", "qt_plan_set_schedule", "qt_plan_result", "qt_plan_info",
            "qt_plan_destroy", "qt_tune_leaf", "qt_profile", "qt_profile_read", "qt_probe_mfma", "qt_last_error", "qt_version")
 PLAN_SCHEDULES = ("flat", "persistent-1", "persistent-4", "persistent-16")
@@ -165,6 +167,13 @@ class Matrix:
         nl, prods = ctypes.c_int32(), ctypes.c_int64()
         _check(lib.qt_stats(self._h, pairs, 64, ctypes.byref(nl), ctypes.byref(prods)))
         return {"pairs": np.array(pairs[:nl.value], np.int64), "products": prods.value}
+
+    def levels(self) -> np.ndarray:
+        """Non-NIL quadtree nodes per level, root first (qt_levels)."""
+        nodes = (ctypes.c_int64 * 64)()
+        nl = ctypes.c_int32()
+        _check(lib.qt_levels(self._h, nodes, 64, ctypes.byref(nl)))
+        return np.array(nodes[:nl.value], np.int64)
 
     def to_blocks(self, dtype: str = "f64", stream=None):
         """Copy out as (I, J, V) numpy arrays sorted by (I, J)."""

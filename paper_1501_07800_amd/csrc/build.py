@@ -21,7 +21,7 @@ SOURCES = ["qt_api.hip", "qt_build.hip", "qt_multiply.hip", "qt_numeric.hip", "q
            "qt_scan.hip", "qt_sort.hip"]
 
 FLAGS = [
-    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall", "-Wshadow",
+    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall", "-Wshadow", "-Werror",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wno-unused-command-line-argument",
 ]

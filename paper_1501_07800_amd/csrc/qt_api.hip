@@ -243,6 +243,17 @@ qt_status qt_stats(const qt_matrix* C, int64_t* pairs, int32_t max_levels, int32
     return QT_OK;
 }
 
+qt_status qt_levels(const qt_matrix* M, int64_t* nodes, int32_t max_levels, int32_t* n_levels) {
+    if (!M || max_levels < 0 || (max_levels > 0 && !nodes)) {
+        set_last_error("bad argument");
+        return QT_ERR_ARG;
+    }
+    const int32_t nl = M->L + 1;
+    if (n_levels) *n_levels = nl;
+    for (int32_t l = 0; l < nl && l < max_levels; ++l) nodes[l] = (l < M->L) ? M->levels[l].n : M->leaves.n;
+    return QT_OK;
+}
+
 qt_status qt_prepare(const qt_matrix* M, qt_prec prec, void* stream) {
     if (!M) {
         set_last_error("NULL matrix");

@@ -355,6 +355,7 @@ static int ilog2(int64_t x) {
 // ------------------------------------------------------------ histograms
 
 void build_histograms(qt_matrix* M, hipStream_t s) {
+    std::lock_guard<std::mutex> lk(M->mu);
     if (M->hist.ready) return;
     Histograms h;
     h.rowcnt.resize(M->L + 1);
@@ -397,6 +398,27 @@ void build_histograms(qt_matrix* M, hipStream_t s) {
 
 // ----------------------------------------------------- operand forms
 
+// A derived form was just queued on s: record its event there.
+static void form_mark(hipEvent_t& ev, hipStream_t s) {
+    if (!ev) QT_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+    QT_HIP(hipEventRecord(ev, s));
+}
+
+// Work queued on s from here on must see the form: wait for its event unless
+// it has completed already (then the event is dropped, so later calls skip
+// even the query). Called with M->mu held.
+static void form_ready(hipEvent_t& ev, hipStream_t s) {
+    if (!ev) return;
+    const hipError_t q = hipEventQuery(ev);
+    if (q == hipSuccess) {
+        (void)hipEventDestroy(ev);
+        ev = nullptr;
+        return;
+    }
+    if (q != hipErrorNotReady) hip_check(q, "hipEventQuery");
+    QT_HIP(hipStreamWaitEvent(s, ev, 0));
+}
+
 const double* operand_f64(qt_matrix* M, hipStream_t s) {
     if (M->vtype == QT_F64) return M->v64.p;
     std::lock_guard<std::mutex> lk(M->mu);
@@ -405,7 +427,9 @@ const double* operand_f64(qt_matrix* M, hipStream_t s) {
         M->v64_cache.alloc(n, s);
         k_f32_to_f64<<<grid_for(n), 256, 0, s>>>(M->v32.p, n, M->v64_cache.p);
         QT_LAUNCH("k_f32_to_f64");
+        form_mark(M->ev_v64, s);
     }
+    form_ready(M->ev_v64, s);
     return M->v64_cache.p;
 }
 
@@ -416,7 +440,9 @@ const float* operand_f32(qt_matrix* M, hipStream_t s) {
         M->v32.alloc(n, s);
         k_f64_to_f32<<<grid_for(n), 256, 0, s>>>(M->v64.p, n, M->v32.p);
         QT_LAUNCH("k_f64_to_f32");
+        form_mark(M->ev_v32, s);
     }
+    form_ready(M->ev_v32, s);
     return M->v32.p;
 }
 
@@ -440,7 +466,9 @@ const double* operand_f64_t(qt_matrix* M, hipStream_t s) {
         M->v64_t.alloc(n, s);
         k_transpose_blocks<double><<<grid_for(n), 256, 0, s>>>(v, M->nblocks, M->b, M->v64_t.p);
         QT_LAUNCH("k_transpose_blocks");
+        form_mark(M->ev_v64_t, s);
     }
+    form_ready(M->ev_v64_t, s);
     return M->v64_t.p;
 }
 
@@ -452,25 +480,30 @@ const float* operand_f32_t(qt_matrix* M, hipStream_t s) {
         M->v32_t.alloc(n, s);
         k_transpose_blocks<float><<<grid_for(n), 256, 0, s>>>(v, M->nblocks, M->b, M->v32_t.p);
         QT_LAUNCH("k_transpose_blocks");
+        form_mark(M->ev_v32_t, s);
     }
+    form_ready(M->ev_v32_t, s);
     return M->v32_t.p;
 }
 
 void operand_bf16(qt_matrix* M, hipStream_t s) {
     std::lock_guard<std::mutex> lk(M->mu);
-    if (M->bf_hi.p || M->nblocks == 0) return;
-    const int64_t n = M->nblocks * (int64_t)M->b * M->b;
-    M->bf_hi.alloc(n, s);
-    M->bf_lo.alloc(n, s);
-    M->bf_hi_t.alloc(n, s);
-    M->bf_lo_t.alloc(n, s);
-    if (M->vtype == QT_F64)
-        k_bf16_split<double><<<grid_for(n), 256, 0, s>>>(M->v64.p, M->nblocks, M->b, M->bf_hi.p, M->bf_lo.p,
-                                                         M->bf_hi_t.p, M->bf_lo_t.p);
-    else
-        k_bf16_split<float><<<grid_for(n), 256, 0, s>>>(M->v32.p, M->nblocks, M->b, M->bf_hi.p, M->bf_lo.p,
-                                                        M->bf_hi_t.p, M->bf_lo_t.p);
-    QT_LAUNCH("k_bf16_split");
+    if (!M->bf_hi.p && M->nblocks > 0) {
+        const int64_t n = M->nblocks * (int64_t)M->b * M->b;
+        M->bf_hi.alloc(n, s);
+        M->bf_lo.alloc(n, s);
+        M->bf_hi_t.alloc(n, s);
+        M->bf_lo_t.alloc(n, s);
+        if (M->vtype == QT_F64)
+            k_bf16_split<double><<<grid_for(n), 256, 0, s>>>(M->v64.p, M->nblocks, M->b, M->bf_hi.p, M->bf_lo.p,
+                                                             M->bf_hi_t.p, M->bf_lo_t.p);
+        else
+            k_bf16_split<float><<<grid_for(n), 256, 0, s>>>(M->v32.p, M->nblocks, M->b, M->bf_hi.p, M->bf_lo.p,
+                                                            M->bf_hi_t.p, M->bf_lo_t.p);
+        QT_LAUNCH("k_bf16_split");
+        form_mark(M->ev_bf16, s);
+    }
+    form_ready(M->ev_bf16, s);
 }
 
 // ----------------------------------------------------------------- build

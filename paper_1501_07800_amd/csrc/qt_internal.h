@@ -139,7 +139,10 @@ struct qt_matrix {
                                          // a built matrix unless it is very large); the DBufs
                                          // below then view into it
 
-    // derived operand forms (built on demand, guarded by mu)
+    // derived operand forms (built on demand, guarded by mu). Each is queued
+    // on the stream of the call that first needs it; the matching event is
+    // recorded there, and every later user on any stream waits for it (see
+    // form_ready) before reading the form.
     std::mutex mu;
     qt::DBuf<uint16_t> bf_hi, bf_lo;     // bf16 split, row-major per block
     qt::DBuf<uint16_t> bf_hi_t, bf_lo_t; // same, each block transposed
@@ -147,12 +150,22 @@ struct qt_matrix {
     std::unique_ptr<qt_matrix> sym_full; // full symmetric matrix from this upper triangle
     qt::DBuf<double> v64_t;              // fp64 values, every block transposed
     qt::DBuf<float> v32_t;               // fp32 values, every block transposed
-    qt::Histograms hist;
+    hipEvent_t ev_v32 = nullptr, ev_v64 = nullptr, ev_bf16 = nullptr, ev_v64_t = nullptr, ev_v32_t = nullptr,
+               ev_sym = nullptr;
+    qt::Histograms hist;                 // built once, under mu (build_histograms)
 
     // counters of the multiply that produced this matrix
     std::vector<int64_t> pairs;
     int64_t products = 0;
     bool plan_owned = false;  // a batch plan's result: released with the plan
+
+    qt_matrix() = default;
+    qt_matrix(const qt_matrix&) = delete;
+    qt_matrix& operator=(const qt_matrix&) = delete;
+    ~qt_matrix() {
+        for (hipEvent_t e : {ev_v32, ev_v64, ev_bf16, ev_v64_t, ev_v32_t, ev_sym})
+            if (e) (void)hipEventDestroy(e);
+    }
 };
 
 namespace qt {

@@ -52,7 +52,7 @@
 
 namespace qt {
 
-constexpr int kPublishMax = 64;   // counts read back per multiply: 2 * depth + 4
+constexpr int kPublishMax = 128;  // counts read back per multiply: 3 * (depth + 1) + 1
 
 // ------------------------------------------------------------- helpers
 
@@ -119,7 +119,8 @@ struct TreeStep {
     int32_t* nfb;
     int32_t* ncseg;
     uint64_t* nckey;
-    int32_t* cchild;          // C's child table at this level (4 per node)
+    int32_t* cchild;          // C's child table at this level (4 per node), before NIL normalisation
+    int32_t* nparent;         // parent (C node at this level) of every C node of the next level
     int32_t* ncount_next;
     int32_t np_next;          // bound on pairs at the next level (exact unless `upper`)
     int32_t nc_next;          // bound on C nodes at the next level
@@ -211,6 +212,7 @@ __device__ void tree_fill_node(const TreeStep& st, int32_t c, int lane, int64_t 
         if (my_c >= 0 && my_c < st.nc_next) {
             st.nckey[my_c] = st.ckey[c] * 4 + (uint64_t)lane;
             st.ncseg[my_c] = my_run;
+            st.nparent[my_c] = c;
         }
     }
     const int32_t s0 = st.cseg[c], len = st.cseg[c + 1] - s0;
@@ -342,6 +344,11 @@ __global__ __launch_bounds__(64 * W) void k_tree_fill(TreeStep st) {
         if (c == 0 && lane == 0) tree_level_totals(st, st.off[st.ncap]);
         if (c < st.ncap) tree_fill_node(st, c, lane, st.off[c]);
     }
+}
+
+__global__ void k_fill_flags(int32_t* __restrict__ f, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) f[i] = 0;
 }
 
 // Level-0 frontier: the pair of roots, one C node.
@@ -563,6 +570,93 @@ __global__ __launch_bounds__(64 * W) void k_leaf_fill(LeafStep st) {
     }
 }
 
+// ---------------------------------------------- NIL normalisation of C
+//
+// The traversal creates a C node for every quadrant that receives a pair, and
+// a C leaf for every leaf pair group, before it knows whether any block
+// product lands there: a leaf whose pairs all miss (no k with A(i,k) and
+// B(k,j) both present) holds no block, and so does a node above only such
+// leaves. Zero submatrices are NIL at every level of the quadtree (Sec. 3.1),
+// so C's tree keeps exactly the nodes with a stored block below them:
+//   mark:    every leaf that holds a block flags itself and its ancestors
+//            (parents were recorded by the traversal; a walk stops at the
+//            first ancestor already flagged);
+//   scan:    one exclusive scan over the flags of all levels, concatenated,
+//            gives every kept node its index among the kept nodes of its level;
+//   compact: kept nodes are copied into C's tree, child tables remapped
+//            (a child that is not kept becomes NIL), and the kept counts of
+//            every level are written for the read-back.
+// C's blocks, their order and the product lists do not change: an empty leaf
+// owns none of them.
+constexpr int NIL_MAX_LEVELS = 32;
+
+struct NilTree {
+    int L;
+    int64_t foff[NIL_MAX_LEVELS + 2];        // flags of level l at foff[l] .. foff[l+1]-1
+    const int32_t* ncount;                   // traversal's C node counts, levels 0 .. L
+    const int32_t* uparent[NIL_MAX_LEVELS + 1];   // levels 1 .. L
+    const int32_t* uchild[NIL_MAX_LEVELS];   // levels 0 .. L-1 (4 per node)
+    const uint64_t* ukey[NIL_MAX_LEVELS + 1];
+    const int32_t* ubase;                    // leaves
+    const uint64_t* umo;
+    const uint64_t* urm;
+    const uint64_t* ucm;
+    int32_t* flags;                          // foff[L+1] entries, cleared before the traversal
+    const int32_t* ex;                       // exclusive scan of flags (foff[L+1] + 1 entries)
+    int32_t* child[NIL_MAX_LEVELS];          // the kept tree
+    uint64_t* key[NIL_MAX_LEVELS + 1];
+    int32_t* base;
+    uint64_t* mo;
+    uint64_t* rm;
+    uint64_t* cm;
+    int32_t* kept;                           // kept nodes per level, levels 0 .. L
+};
+
+__global__ void k_nil_mark(NilTree t) {
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int L = t.L;
+    if (c >= t.ncount[L] || t.umo[c] == 0) return;
+    t.flags[t.foff[L] + c] = 1;
+    int32_t p = (int32_t)c;
+    for (int l = L; l > 0; --l) {
+        p = t.uparent[l][p];
+        int32_t* f = t.flags + t.foff[l - 1] + p;
+        if (*f) break;   // that ancestor and its own ancestors are flagged already
+        *f = 1;
+    }
+}
+
+__device__ __forceinline__ int32_t nil_rank(const NilTree& t, int l, int64_t c) {
+    return t.ex[t.foff[l] + c] - t.ex[t.foff[l]];
+}
+
+__global__ void k_nil_compact(NilTree t) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int L = t.L;
+    if (i == 0)
+        for (int l = 0; l <= L; ++l) t.kept[l] = t.ex[t.foff[l + 1]] - t.ex[t.foff[l]];
+    if (i >= t.foff[L + 1] || !t.flags[i]) return;
+    int l = 0;
+    while (i >= t.foff[l + 1]) ++l;
+    const int64_t c = i - t.foff[l];
+    const int32_t n = nil_rank(t, l, c);
+    t.key[l][n] = t.ukey[l][c];
+    if (l < L) {
+        const int4 u = *reinterpret_cast<const int4*>(t.uchild[l] + 4 * c);
+        const int32_t uc[4] = {u.x, u.y, u.z, u.w};
+        int32_t out[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            out[q] = (uc[q] >= 0 && t.flags[t.foff[l + 1] + uc[q]]) ? nil_rank(t, l + 1, uc[q]) : -1;
+        *reinterpret_cast<int4*>(t.child[l] + 4 * (int64_t)n) = make_int4(out[0], out[1], out[2], out[3]);
+    } else {
+        t.base[n] = t.ubase[c];
+        t.mo[n] = t.umo[c];
+        t.rm[n] = t.urm[c];
+        t.cm[n] = t.ucm[c];
+    }
+}
+
 // ------------------------------------------------ launch order of C's blocks
 //
 // The numeric kernels give each XCD runs of consecutive launch slots. With
@@ -663,16 +757,16 @@ __global__ __launch_bounds__(KORDER_THREADS) void k_korder_counts(const uint64_t
                                                                   const int32_t* __restrict__ seg, int32_t nseg,
                                                                   bool ta, int32_t kdim, int32_t nwg,
                                                                   int32_t* __restrict__ cnt) {
-    extern __shared__ int32_t tab[];
+    extern __shared__ int32_t ktab[];
     int32_t kk[KORDER_ITEMS];
     korder_keys(akey, prodA, seg, nseg, ta, kdim, kk);
-    for (int32_t k = threadIdx.x; k < kdim; k += KORDER_THREADS) tab[k] = 0;
+    for (int32_t k = threadIdx.x; k < kdim; k += KORDER_THREADS) ktab[k] = 0;
     __syncthreads();
 #pragma unroll
     for (int j = 0; j < KORDER_ITEMS; ++j)
-        if (kk[j] >= 0) atomicAdd(&tab[kk[j]], 1);
+        if (kk[j] >= 0) atomicAdd(&ktab[kk[j]], 1);
     __syncthreads();
-    for (int32_t k = threadIdx.x; k < kdim; k += KORDER_THREADS) cnt[(int64_t)k * nwg + blockIdx.x] = tab[k];
+    for (int32_t k = threadIdx.x; k < kdim; k += KORDER_THREADS) cnt[(int64_t)k * nwg + blockIdx.x] = ktab[k];
 }
 
 // off: the exclusive scan of cnt; order[slot] = C block
@@ -682,16 +776,16 @@ __global__ __launch_bounds__(KORDER_THREADS) void k_korder_place(const uint64_t*
                                                                  bool ta, int32_t kdim, int32_t nwg,
                                                                  const int32_t* __restrict__ off,
                                                                  int32_t* __restrict__ order) {
-    extern __shared__ int32_t tab[];
+    extern __shared__ int32_t ktab[];
     int32_t kk[KORDER_ITEMS];
     korder_keys(akey, prodA, seg, nseg, ta, kdim, kk);
-    for (int32_t k = threadIdx.x; k < kdim; k += KORDER_THREADS) tab[k] = off[(int64_t)k * nwg + blockIdx.x];
+    for (int32_t k = threadIdx.x; k < kdim; k += KORDER_THREADS) ktab[k] = off[(int64_t)k * nwg + blockIdx.x];
     __syncthreads();
     const int64_t base = (int64_t)blockIdx.x * KORDER_WG + threadIdx.x;
 #pragma unroll
     for (int j = 0; j < KORDER_ITEMS; ++j)
         if (kk[j] >= 0) {
-            const int32_t o = atomicAdd(&tab[kk[j]], 1);
+            const int32_t o = atomicAdd(&ktab[kk[j]], 1);
             if (o >= 0 && o < nseg) order[o] = (int32_t)(base + j * KORDER_THREADS);
         }
 }
@@ -710,11 +804,10 @@ struct alignas(64) HostSlot {
 };
 
 __global__ void k_publish(const int32_t* __restrict__ counts, int n, HostSlot* slot, uint32_t seq) {
-    const int t = threadIdx.x;
-    if (t < n) slot->counts[t] = counts[t];
+    for (int t = threadIdx.x; t < n; t += blockDim.x) slot->counts[t] = counts[t];
     __threadfence_system();
     __syncthreads();
-    if (t == 0) __hip_atomic_store(&slot->flag, seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+    if (threadIdx.x == 0) __hip_atomic_store(&slot->flag, seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
 static std::mutex g_slot_mu;
@@ -986,6 +1079,22 @@ void symbolic(qt_matrix* A, qt_matrix* B, qt_prec prec, hipStream_t s, SymbolicO
     const size_t o_lrm = keep.take(ncap[L] * sizeof(uint64_t));
     const size_t o_lcm = keep.take(ncap[L] * sizeof(uint64_t));
     const size_t o_bkey = keep.take(cap * sizeof(uint64_t));
+    // the tree as the traversal forms it, before NIL normalisation (scratch)
+    std::vector<size_t> u_child(L), u_key(L + 1), u_parent(L + 1);
+    for (int l = 0; l < L; ++l) u_child[l] = tmp.take(4 * ncap[l] * sizeof(int32_t));
+    for (int l = 0; l <= L; ++l) u_key[l] = tmp.take(ncap[l] * sizeof(uint64_t));
+    for (int l = 1; l <= L; ++l) u_parent[l] = tmp.take(ncap[l] * sizeof(int32_t));
+    const size_t u_lbase = tmp.take(ncap[L] * sizeof(int32_t));
+    const size_t u_lmo = tmp.take(ncap[L] * sizeof(uint64_t));
+    const size_t u_lrm = tmp.take(ncap[L] * sizeof(uint64_t));
+    const size_t u_lcm = tmp.take(ncap[L] * sizeof(uint64_t));
+    if (L + 1 > NIL_MAX_LEVELS) fail(QT_ERR_UNSUPPORTED, "quadtree too deep");
+    std::vector<int64_t> foff(L + 2, 0);
+    for (int l = 0; l <= L; ++l) foff[l + 1] = foff[l] + ncap[l];
+    if (foff[L + 1] > kMaxI32) fail(QT_ERR_UNSUPPORTED, "too many C nodes");
+    const size_t o_nflags = tmp.take(foff[L + 1] * sizeof(int32_t));
+    const size_t o_nex = tmp.take((foff[L + 1] + 1) * sizeof(int32_t));
+    const size_t o_nscan = tmp.take((scan_tmp_elems(foff[L + 1]) + 1) * sizeof(int32_t));
     std::vector<size_t> o_fa(L + 1), o_fb(L + 1), o_cseg(L + 1), o_cnt(L + 1), o_off(L + 1), o_tot(L + 1),
         o_wagg(L + 1);
     std::vector<int64_t> gsum_at(L + 1);
@@ -1022,7 +1131,7 @@ void symbolic(qt_matrix* A, qt_matrix* B, qt_prec prec, hipStream_t s, SymbolicO
         o_kscan = tmp.take((scan_tmp_elems(kdim * kwg_cap) + 1) * sizeof(int32_t));
     }
     if (make_order || may_korder) o_order = tmp.take(cap * sizeof(int32_t));   // one order is used at most
-    const size_t o_count = tmp.take((2 * L + 4) * sizeof(int32_t));
+    const size_t o_count = tmp.take((3 * L + 4) * sizeof(int32_t));
 
     out.C.reset(new_result(A, B, L, prec, s, op));
     qt_matrix* C = out.C.get();
@@ -1037,7 +1146,10 @@ void symbolic(qt_matrix* A, qt_matrix* B, qt_prec prec, hipStream_t s, SymbolicO
     char* K = C->arena.p;
     char* W = out.scratch.p;
     auto at = [](char* base, size_t off) { return (void*)(base + off); };
-    int32_t* dcount = (int32_t*)at(W, o_count);   // [0..L] C nodes per level, [L+1] C blocks, then checks
+    // [0..L] C nodes per level as traversed, [L+1] C blocks, [L+2..2L+2] checks,
+    // [2L+3..3L+3] C nodes per level after NIL normalisation
+    int32_t* dcount = (int32_t*)at(W, o_count);
+    int32_t* nflags = (int32_t*)at(W, o_nflags);
 
     const bool prof = out.prof = allow_profile && profiling_on();
     PhaseEvents& ev = out.ev;
@@ -1055,7 +1167,7 @@ void symbolic(qt_matrix* A, qt_matrix* B, qt_prec prec, hipStream_t s, SymbolicO
         st.fa = (const int32_t*)at(W, o_fa[l]);
         st.fb = (const int32_t*)at(W, o_fb[l]);
         st.cseg = (const int32_t*)at(W, o_cseg[l]);
-        st.ckey = (const uint64_t*)at(K, o_key[l]);
+        st.ckey = (const uint64_t*)at(W, u_key[l]);
         st.ncount = dcount + l;
         st.Ach = (l < liftA) ? lift : A->levels[l - liftA].child.p;
         st.Bch = (l < liftB) ? lift : B->levels[l - liftB].child.p;
@@ -1068,8 +1180,9 @@ void symbolic(qt_matrix* A, qt_matrix* B, qt_prec prec, hipStream_t s, SymbolicO
         st.nfa = (int32_t*)at(W, o_fa[l + 1]);
         st.nfb = (int32_t*)at(W, o_fb[l + 1]);
         st.ncseg = (int32_t*)at(W, o_cseg[l + 1]);
-        st.nckey = (uint64_t*)at(K, o_key[l + 1]);
-        st.cchild = (int32_t*)at(K, o_child[l]);
+        st.nckey = (uint64_t*)at(W, u_key[l + 1]);
+        st.cchild = (int32_t*)at(W, u_child[l]);
+        st.nparent = (int32_t*)at(W, u_parent[l + 1]);
         st.ncount_next = dcount + l + 1;
         st.np_next = (int32_t)pairs[l + 1];
         st.nc_next = (int32_t)ncap[l + 1];
@@ -1080,8 +1193,10 @@ void symbolic(qt_matrix* A, qt_matrix* B, qt_prec prec, hipStream_t s, SymbolicO
         return st;
     };
     RootInit root{(int32_t*)at(W, o_fa[0]), (int32_t*)at(W, o_fb[0]), (int32_t*)at(W, o_cseg[0]),
-                  (uint64_t*)at(K, o_key[0]), dcount, (int64_t*)at(W, o_gsum), gsum_total};
+                  (uint64_t*)at(W, u_key[0]), dcount, (int64_t*)at(W, o_gsum), gsum_total};
 
+    k_fill_flags<<<(unsigned)((foff[L + 1] + 255) / 256), 256, 0, ss>>>(nflags, foff[L + 1]);
+    QT_LAUNCH("k_fill_flags");
     k_root_init<<<1, 64, 0, ss>>>(root);
     QT_LAUNCH("k_root_init");
     int64_t* scan_tmp = (int64_t*)at(W, o_scan);
@@ -1100,7 +1215,7 @@ void symbolic(qt_matrix* A, qt_matrix* B, qt_prec prec, hipStream_t s, SymbolicO
     ls.fa = (const int32_t*)at(W, o_fa[L]);
     ls.fb = (const int32_t*)at(W, o_fb[L]);
     ls.cseg = (const int32_t*)at(W, o_cseg[L]);
-    ls.ckey = (const uint64_t*)at(K, o_key[L]);
+    ls.ckey = (const uint64_t*)at(W, u_key[L]);
     ls.ncount = dcount + L;
     ls.ncap = (int32_t)ncap[L];
     ls.lb_log = lb_log;
@@ -1126,10 +1241,10 @@ void symbolic(qt_matrix* A, qt_matrix* B, qt_prec prec, hipStream_t s, SymbolicO
     ls.cbkey = (uint64_t*)at(K, o_bkey);
     ls.cbseg = (int32_t*)at(W, o_cbseg);
     ls.cap = (int32_t)cap;
-    ls.lbase = (int32_t*)at(K, o_lbase);
-    ls.lmo = (uint64_t*)at(K, o_lmo);
-    ls.lrm = (uint64_t*)at(K, o_lrm);
-    ls.lcm = (uint64_t*)at(K, o_lcm);
+    ls.lbase = (int32_t*)at(W, u_lbase);
+    ls.lmo = (uint64_t*)at(W, u_lmo);
+    ls.lrm = (uint64_t*)at(W, u_lrm);
+    ls.lcm = (uint64_t*)at(W, u_lcm);
     ls.nblocks_out = dcount + L + 1;
     ls.check = dcount + 2 * L + 2;
     QT_LEVEL_LAUNCH(k_leaf_count, ncap[L], leaf_wgs, ss, ls);
@@ -1137,28 +1252,62 @@ void symbolic(qt_matrix* A, qt_matrix* B, qt_prec prec, hipStream_t s, SymbolicO
     QT_LEVEL_LAUNCH(k_leaf_fill, ncap[L], leaf_wgs, ss, ls);
     int32_t* order = (make_order || may_korder) ? (int32_t*)at(W, o_order) : nullptr;
     if (make_order) {
-        int32_t* tab = (int32_t*)at(W, o_otab);
+        int32_t* otab = (int32_t*)at(W, o_otab);
         int32_t* ocnt = (int32_t*)at(W, o_ocnt);
         int32_t* ooff = (int32_t*)at(W, o_ooff);
         const unsigned gp = (unsigned)((lpos + 255) / 256);
-        k_order_clear<<<gp, 256, 0, ss>>>(tab, lpos);
+        k_order_clear<<<gp, 256, 0, ss>>>(otab, lpos);
         QT_LAUNCH("k_order_clear");
         k_order_place<<<(unsigned)((ncap[L] + 255) / 256), 256, 0, ss>>>(ls.ckey, ls.ncount, ls.ncap, lrows, lcols,
-                                                                          tab);
+                                                                          otab);
         QT_LAUNCH("k_order_place");
-        k_order_counts<<<gp, 256, 0, ss>>>(tab, lpos, ls.lmo, ocnt);
+        k_order_counts<<<gp, 256, 0, ss>>>(otab, lpos, ls.lmo, ocnt);
         QT_LAUNCH("k_order_counts");
         exclusive_scan(ocnt, ooff, lpos, (int32_t*)at(W, o_oscan), ss);
-        k_order_fill<<<gp, 256, 0, ss>>>(tab, lpos, ls.lbase, ocnt, ooff, ls.cap, order);
+        k_order_fill<<<gp, 256, 0, ss>>>(otab, lpos, ls.lbase, ocnt, ooff, ls.cap, order);
         QT_LAUNCH("k_order_fill");
+    }
+    {
+        // NIL normalisation: C keeps only the nodes with a block below them
+        NilTree nt{};
+        nt.L = L;
+        for (int l = 0; l <= L + 1; ++l) nt.foff[l] = foff[l];
+        nt.ncount = dcount;
+        for (int l = 1; l <= L; ++l) nt.uparent[l] = (const int32_t*)at(W, u_parent[l]);
+        for (int l = 0; l < L; ++l) {
+            nt.uchild[l] = (const int32_t*)at(W, u_child[l]);
+            nt.child[l] = (int32_t*)at(K, o_child[l]);
+        }
+        for (int l = 0; l <= L; ++l) {
+            nt.ukey[l] = (const uint64_t*)at(W, u_key[l]);
+            nt.key[l] = (uint64_t*)at(K, o_key[l]);
+        }
+        nt.ubase = ls.lbase;
+        nt.umo = ls.lmo;
+        nt.urm = ls.lrm;
+        nt.ucm = ls.lcm;
+        nt.flags = nflags;
+        nt.ex = (const int32_t*)at(W, o_nex);
+        nt.base = (int32_t*)at(K, o_lbase);
+        nt.mo = (uint64_t*)at(K, o_lmo);
+        nt.rm = (uint64_t*)at(K, o_lrm);
+        nt.cm = (uint64_t*)at(K, o_lcm);
+        nt.kept = dcount + 2 * L + 3;
+        k_nil_mark<<<(unsigned)((ncap[L] + 255) / 256), 256, 0, ss>>>(nt);
+        QT_LAUNCH("k_nil_mark");
+        exclusive_scan(nflags, (int32_t*)at(W, o_nex), foff[L + 1], (int32_t*)at(W, o_nscan), ss);
+        k_nil_compact<<<(unsigned)((foff[L + 1] + 255) / 256), 256, 0, ss>>>(nt);
+        QT_LAUNCH("k_nil_compact");
     }
     if (prof) QT_HIP(hipEventRecord(ev.e1, ss));
 
     // the one synchronization: node and block counts of C
-    std::vector<int32_t> hc(2 * L + 4);
+    std::vector<int32_t> hc(3 * L + 4);
     read_back_counts(dcount, (int)hc.size(), ss, hc.data());
     for (int l = 0; l <= L; ++l) {
         if (hc[l] < 0 || hc[l] > ncap[l]) fail(QT_ERR_DEVICE, "symbolic phase: C node count out of range");
+        if (hc[2 * L + 3 + l] < 0 || hc[2 * L + 3 + l] > hc[l])
+            fail(QT_ERR_DEVICE, "symbolic phase: kept C node count out of range");
         const int64_t expect = (l < L) ? pairs[l + 1] : P;
         const bool bad = op.upper ? (hc[L + 2 + l] < 0 || hc[L + 2 + l] > expect) : (hc[L + 2 + l] != expect);
         if (bad) fail(QT_ERR_DEVICE, "symbolic phase: pair count mismatch");
@@ -1195,19 +1344,21 @@ void symbolic(qt_matrix* A, qt_matrix* B, qt_prec prec, hipStream_t s, SymbolicO
         QT_HIP(hipEventDestroy(done));
     }
 
-    // C's tree: views into its arena
+    // C's tree (NIL-normalised): views into its arena
+    const int32_t* kept = hc.data() + 2 * L + 3;
     for (int l = 0; l < L; ++l) {
-        C->levels[l].n = hc[l];
-        C->levels[l].child.view(at(K, o_child[l]), 4 * (size_t)hc[l]);
-        C->levels[l].key.view(at(K, o_key[l]), hc[l]);
+        C->levels[l].n = kept[l];
+        C->levels[l].child.view(at(K, o_child[l]), 4 * (size_t)kept[l]);
+        C->levels[l].key.view(at(K, o_key[l]), kept[l]);
     }
     LeafLevel& CL = C->leaves;
-    CL.n = hc[L];
-    CL.key.view(at(K, o_key[L]), hc[L]);
-    CL.base.view(at(K, o_lbase), hc[L]);
-    CL.mask_mo.view(at(K, o_lmo), hc[L]);
-    CL.mask_rm.view(at(K, o_lrm), hc[L]);
-    CL.mask_cm.view(at(K, o_lcm), hc[L]);
+    CL.n = kept[L];
+    CL.key.view(at(K, o_key[L]), kept[L]);
+    CL.base.view(at(K, o_lbase), kept[L]);
+    CL.mask_mo.view(at(K, o_lmo), kept[L]);
+    CL.mask_rm.view(at(K, o_lrm), kept[L]);
+    CL.mask_cm.view(at(K, o_lcm), kept[L]);
+    if ((nnzC > 0) != (kept[L] > 0)) fail(QT_ERR_DEVICE, "symbolic phase: C leaves and blocks disagree");
     C->bkey.view(at(K, o_bkey), nnzC);
     C->nblocks = nnzC;
 

@@ -362,9 +362,9 @@ __global__ __launch_bounds__(256, 4) void k_numeric_f64_b64(const double* __rest
         const double* a_ = A + (size_t)prodA[TT] * (BS * BS);                                          \
         const double* b_ = B + (size_t)prodB[TT] * (BS * BS);                                          \
         _Pragma("unroll") for (int r = 0; r < 4; ++r) {                                                \
-            const int q = tid + 256 * r;                                                               \
-            pa[r] = *reinterpret_cast<const v2d_t*>(a_ + (q >> 4) * BS + (HH) * KH + (q & 15) * 2);    \
-            pb[r] = *reinterpret_cast<const v2d_t*>(b_ + ((HH) * KH + (q >> 5)) * BS + (q & 31) * 2);  \
+            const int pc = tid + 256 * r;                                                              \
+            pa[r] = *reinterpret_cast<const v2d_t*>(a_ + (pc >> 4) * BS + (HH) * KH + (pc & 15) * 2);  \
+            pb[r] = *reinterpret_cast<const v2d_t*>(b_ + ((HH) * KH + (pc >> 5)) * BS + (pc & 31) * 2); \
         }                                                                                              \
     } while (0)
     QT_F64L_FETCH(t0, 0);   // a segment holds at least one product
@@ -374,9 +374,9 @@ __global__ __launch_bounds__(256, 4) void k_numeric_f64_b64(const double* __rest
             __syncthreads();   // every wave is done reading the previous half
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const int q = tid + 256 * r;
-                *reinterpret_cast<v2d_t*>(la + (q >> 4) * F64L_AROW + (q & 15) * 2) = pa[r];
-                *reinterpret_cast<v2d_t*>(lb + (q >> 5) * F64L_BROW + (q & 31) * 2) = pb[r];
+                const int pc = tid + 256 * r;
+                *reinterpret_cast<v2d_t*>(la + (pc >> 4) * F64L_AROW + (pc & 15) * 2) = pa[r];
+                *reinterpret_cast<v2d_t*>(lb + (pc >> 5) * F64L_BROW + (pc & 31) * 2) = pb[r];
             }
             __syncthreads();
             if (h == 0)
@@ -463,9 +463,9 @@ __global__ __launch_bounds__(256) void k_numeric_f32_b64(const float* __restrict
         const float* a_ = A + (size_t)prodA[TT] * (BS * BS);                                          \
         const float* b_ = B + (size_t)prodB[TT] * (BS * BS);                                          \
         _Pragma("unroll") for (int r = 0; r < 2; ++r) {                                               \
-            const int q = tid + 256 * r;                                                              \
-            pa[r] = *reinterpret_cast<const v4f*>(a_ + (q >> 3) * BS + (HH) * KH + (q & 7) * 4);      \
-            pb[r] = *reinterpret_cast<const v4f*>(b_ + ((HH) * KH + (q >> 4)) * BS + (q & 15) * 4);   \
+            const int pc = tid + 256 * r;                                                             \
+            pa[r] = *reinterpret_cast<const v4f*>(a_ + (pc >> 3) * BS + (HH) * KH + (pc & 7) * 4);    \
+            pb[r] = *reinterpret_cast<const v4f*>(b_ + ((HH) * KH + (pc >> 4)) * BS + (pc & 15) * 4); \
         }                                                                                             \
     } while (0)
     QT_F32L_FETCH(t0, 0);   // a segment holds at least one product
@@ -475,9 +475,9 @@ __global__ __launch_bounds__(256) void k_numeric_f32_b64(const float* __restrict
             __syncthreads();   // every wave is done reading the previous half
 #pragma unroll
             for (int r = 0; r < 2; ++r) {
-                const int q = tid + 256 * r;
-                *reinterpret_cast<v4f*>(la + (q >> 3) * F32L_AROW + (q & 7) * 4) = pa[r];
-                *reinterpret_cast<v4f*>(lb + (q >> 4) * F32L_BROW + (q & 15) * 4) = pb[r];
+                const int pc = tid + 256 * r;
+                *reinterpret_cast<v4f*>(la + (pc >> 3) * F32L_AROW + (pc & 7) * 4) = pa[r];
+                *reinterpret_cast<v4f*>(lb + (pc >> 4) * F32L_BROW + (pc & 15) * 4) = pb[r];
             }
             __syncthreads();
             if (h == 0)

@@ -45,12 +45,15 @@ def check_f64(qt, A, B, leaf, same=False, check_counts=True):
     _say("f64", A.n_rows, A.n_cols, B.n_cols, "b", A.b, "leaf", leaf, "nnz", A.nnz, B.nnz)
     ref, ost = oracle.multiply(A, B, leaf)
     absAB, _ = oracle.multiply(A, B, leaf, use_abs=True)
-    C, st, _ = gpu_multiply(qt, A, B, leaf, "f64", same)
+    C, st, hC = gpu_multiply(qt, A, B, leaf, "f64", same)
     same_pat, e_max, e_f, e_cw = compare(ref, C, absAB)
     assert same_pat, (ref.nnz, C.nnz)
     assert e_cw <= TOL64, e_cw
     assert e_f <= TOL64, e_f
     assert st["products"] == ost.block_products
+    # C's quadtree: the non-NIL nodes of every level, as Algorithm 1 forms them
+    # with zero submatrices NIL at every level (Sec. 3.1)
+    assert hC.levels().tolist() == ost.c_nodes.tolist()
     if check_counts:
         assert st["pairs"].tolist() == ost.mul_tasks.tolist()
     return ref, C
@@ -113,6 +116,73 @@ def test_banded1024_f64(qt):
     A = wl.config("banded1024")
     ref, C = check_f64(qt, A, A, 256, same=True)
     assert C.nnz == 374
+
+
+def test_banded1024_c_tree_matches_golden(qt):
+    """C's non-NIL nodes per level equal the hand-derived counts of the
+    banded workload: 4 of its 14 leaf pair groups yield no block product and
+    are NIL (golden file, derived by hand from the band structure)."""
+    import json
+    import os
+    g = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "banded1024_counts.json")))
+    A = wl.config("banded1024")
+    hA = qt.from_blockmatrix(A, 256)
+    hC = qt.multiply(hA, hA)
+    assert hC.levels().tolist() == g["c_nodes_per_level"]
+    assert hC.stats()["pairs"].tolist() == g["mul_tasks_per_level"]
+    assert hC.nblocks == g["nnz_C"]
+
+
+@pytest.mark.parametrize("case", ["banded", "decay", "random"])
+def test_chained_pair_counts_match_oracle(qt, case):
+    """D = C*A with the multiply result C as an operand: the traversal of D
+    walks C's tree, so its pairs per level (the multiply tasks of Algorithm 1
+    at each level) equal the oracle's only if C's tree holds no empty node."""
+    if case == "banded":
+        A, leaf = wl.config("banded1024"), 256
+    elif case == "decay":
+        A, leaf = wl.decay3d(1024, 25.0, 16, 32, seed=17), 128
+    else:
+        A, leaf = wl.random_blocks(256, 256, 600, 32, seed=18), 128
+    _say("chained pair counts", case, A.n_rows, A.nnz, leaf)
+    ref_C, st_C = oracle.multiply(A, A, leaf)
+    ref_D, st_D = oracle.multiply(ref_C, A, leaf)
+    hA = qt.from_blockmatrix(A, leaf)
+    hC = qt.multiply(hA, hA)
+    assert hC.levels().tolist() == st_C.c_nodes.tolist()
+    hD = qt.multiply(hC, hA)
+    st = hD.stats()
+    assert st["pairs"].tolist() == st_D.mul_tasks.tolist()
+    assert st["products"] == st_D.block_products
+    assert hD.levels().tolist() == st_D.c_nodes.tolist()
+    I, J = hD.pattern()
+    assert np.array_equal(I, ref_D.I) and np.array_equal(J, ref_D.J)
+
+
+def test_exact_cancellation_keeps_block(qt):
+    """A C block whose block products cancel exactly stays present with value
+    zero: sparsity is detected from the structure only, never from values.
+    C(0,0) = X Y + X (-Y) with small integer entries, so both the oracle's and
+    the GPU's sums are exact zeros; C(0,1) = X Y' is an ordinary block."""
+    b = 32
+    rng = np.random.default_rng(19)
+    X = rng.integers(-3, 4, (b, b)).astype(np.float64)
+    Y = rng.integers(-3, 4, (b, b)).astype(np.float64)
+    Y2 = rng.integers(-3, 4, (b, b)).astype(np.float64)
+    n = 4 * b
+    A = wl.BlockMatrix(n, n, b, np.array([0, 0], np.int32), np.array([0, 1], np.int32), np.stack([X, X]))
+    B = wl.BlockMatrix(n, n, b, np.array([0, 0, 1], np.int32), np.array([0, 1, 0], np.int32),
+                       np.stack([Y, Y2, -Y]))
+    ref, st = oracle.multiply(A, B, 2 * b)
+    assert ref.nnz == 2 and np.all(ref.V[0] == 0.0)
+    for prec in ("f64", "f32", "bf16x3"):
+        hA, hB = qt.from_blockmatrix(A, 2 * b), qt.from_blockmatrix(B, 2 * b)
+        hC = qt.multiply(hA, hB, prec)
+        I, J, V = hC.to_blocks("f64")
+        assert I.tolist() == [0, 0] and J.tolist() == [0, 1], prec
+        assert np.all(V[0] == 0.0), prec
+        assert np.array_equal(V[1], X @ Y2), prec      # integers below 2^24: exact in every path
+        assert hC.levels().tolist() == st.c_nodes.tolist()
 
 
 @pytest.mark.parametrize("b", [16, 32, 64])

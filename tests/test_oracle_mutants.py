@@ -31,6 +31,8 @@ MUTANTS = {
     "empty leaf product kept": ("if (!any) { tree_free(X, lb, 1); return NULL; }\n    return X;",
                                 "return X;"),
     "local block sum restarts per t": ("s += a * x;", "s = a * x;"),
+    "abs mode drops B's absolute value": ("if (use_abs) { a = fabs(a); x = fabs(x); }",
+                                          "if (use_abs) { a = fabs(a); }"),
 }
 
 
@@ -54,6 +56,8 @@ def _run_pins(lib):
         bound = np.abs(Ad) @ np.abs(Bd)
         ok &= bool(np.all(np.abs(to_dense(C) - ref) <= 1e-13 * bound))
         ok &= np.array_equal(positions(C), oracle.pattern_by_definition(A, B))
+        Cabs, _ = oracle.multiply(A, B, lb * b, use_abs=True, lib=lib)
+        ok &= bool(np.all(np.abs(to_dense(Cabs) - bound) <= 1e-13 * bound))
     g = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "banded1024_counts.json")))
     A = wl.config("banded1024")
     C, st = oracle.multiply(A, A, 256, lib=lib)

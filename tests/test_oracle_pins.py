@@ -56,6 +56,30 @@ def test_dense_nonsymmetric_operands_catch_transposes():
         _dense_check(A, B, lb * 3)
 
 
+@pytest.mark.parametrize("b", [1, 4, 32])
+@pytest.mark.parametrize("lb", [1, 2, 8])
+def test_abs_mode_is_abs_product(b, lb):
+    """The |A||B| mode, the denominator of every componentwise parity bound,
+    equals numpy's product of the entrywise absolute values (a library routine
+    on the dense forms). All terms are non-negative, so the oracle's sum and
+    numpy's differ only by rounding: within (k+1) u of the value. Operands with
+    mixed signs make a dropped fabs on either side (or a signed sum) fail."""
+    rng = np.random.default_rng(300 + 10 * b + lb)
+    nbr, nbk, nbc = (11, 9, 7) if b < 32 else (4, 5, 3)
+    for fill in (0.1, 0.5, 1.0):
+        A = random_pattern(rng, nbr, nbk, fill, b)
+        B = random_pattern(rng, nbk, nbc, fill, b)
+        C, _ = oracle.multiply(A, B, lb * b, use_abs=True)
+        ref = np.abs(to_dense(A)) @ np.abs(to_dense(B))
+        Cd = to_dense(C)
+        k = nbk * b
+        assert np.all(np.abs(Cd - ref) <= (k + 1) * 2.0 ** -53 * ref)
+        assert np.array_equal(positions(C), oracle.pattern_by_definition(A, B))
+        # every present block of |A||B| is non-negative, and positive wherever
+        # some product term is nonzero (no cancellation is possible)
+        assert (C.V >= 0).all()
+
+
 def test_boolean_product_pattern_larger():
     """Pattern(C) is the boolean product of the block patterns (bit-exact)."""
     rng = np.random.default_rng(11)
