@@ -60,6 +60,34 @@ typedef enum {
 typedef enum { QT_MEM_HOST = 0, QT_MEM_DEVICE = 1 } qt_mem;
 
 /*
+ * Device allocator of the library (the paper's chunks hold their data in
+ * memory the runtime manages, Sec. 2; here the caller may manage it).
+ *
+ * Every device buffer the library creates -- a handle's values, tree and
+ * derived operand forms, a multiply's scratch, a plan's work list -- is then
+ * obtained with alloc(bytes, stream, ctx) and returned with
+ * free_(p, stream, ctx):
+ *   alloc:  returns at least `bytes` of device memory on the current device,
+ *           aligned to 256 bytes, that work queued on `stream` from now on may
+ *           use; NULL when it cannot (the library call then fails with
+ *           QT_ERR_OOM and releases whatever it had obtained).
+ *   free_:  gives p back. All use of p by the library is queued on `stream`
+ *           before this point, or on other streams that `stream` already
+ *           waits for; the allocator may hand p to later work on `stream`,
+ *           and to other streams once they have waited for this point.
+ * Both callbacks may be called from any thread that calls the library, and
+ * from several at once. Buffers made before a change are still returned to
+ * the allocator that made them, so ctx must stay valid while any of them
+ * lives. alloc == free_ == NULL restores the default: HIP's stream-ordered
+ * pool (hipMallocAsync / hipFreeAsync on the device's default pool). A few
+ * bytes per device that the library keeps until the process ends (a lift
+ * table, pinned read-back slots) never go through the allocator.
+ * Errors: ARG (exactly one of alloc, free_ is NULL).
+ */
+qt_status qt_set_allocator(void* (*alloc)(size_t bytes, void* stream, void* ctx),
+                           void (*free_)(void* p, void* stream, void* ctx), void* ctx);
+
+/*
  * Build a matrix from a list of nonzero blocks (Sec. 3.1 and 4.1).
  *
  * n_rows, n_cols: scalar dimensions; both multiples of block_size.
@@ -108,9 +136,10 @@ qt_status qt_multiply(const qt_matrix* A, const qt_matrix* B, qt_prec prec,
  *   QT_OP_TRANS_A  use A^T;   QT_OP_TRANS_B  use B^T;
  *   QT_OP_UPPER    C(I, J) only for I <= J (C must be square); the traversal
  *                  drops every quadrant strictly below the diagonal.
- * The transposed operands are read through a block-transposed copy of their
- * values, built on first use and kept with the handle. Otherwise as
- * qt_multiply. Errors: ARG (unknown flag), SHAPE, OOM, DEVICE, UNSUPPORTED.
+ * A transposed operand is read from its stored blocks as they are: the
+ * product lists mark its blocks, and the numeric kernel loads each marked
+ * block transposed; no copy of any operand is made. Otherwise as qt_multiply.
+ * Errors: ARG (unknown flag), SHAPE, OOM, DEVICE, UNSUPPORTED.
  */
 #define QT_OP_TRANS_A 1
 #define QT_OP_TRANS_B 2
@@ -141,11 +170,13 @@ qt_status qt_truncate(const qt_matrix* M, double eps, void* stream, qt_matrix** 
 /*
  * Symmetric matrix square (Sec. 3.3): A holds the upper block triangle
  * (blocks with I <= J; diagonal blocks stored whole) of a symmetric S; C
- * holds the upper block triangle of S*S. S is formed once from A (the strictly
- * upper blocks mirrored and transposed) and kept with A; the product skips
- * every C quadrant below the diagonal, about half the block products of S*S.
- * Errors: ARG (a block below the diagonal), SHAPE (not square), OOM, DEVICE,
- * UNSUPPORTED (A holds fp32 values).
+ * holds the upper block triangle of S*S. The quadtree of S is formed once
+ * from A's block pattern and kept with A: structure only (keys, tree, and
+ * for each block of S the block of A that holds it, the mirrored ones marked
+ * as transposed), about 12 bytes per block and no values. The product reads
+ * A's values through it and skips every C quadrant below the diagonal, about
+ * half the block products of S*S. A may hold fp64 or fp32 values.
+ * Errors: ARG (a block below the diagonal), SHAPE (not square), OOM, DEVICE.
  */
 qt_status qt_sysq(const qt_matrix* A, qt_prec prec, void* stream, qt_matrix** C);
 

@@ -98,14 +98,122 @@ def _load():
     lib.qt_probe_mfma.argtypes = [ctypes.c_int, ctypes.c_void_p, ctypes.POINTER(ctypes.c_double)]
     lib.qt_version.restype = ctypes.c_char_p
     lib.qt_version.argtypes = []
+    lib.qt_set_allocator.restype = ctypes.c_int
+    lib.qt_set_allocator.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
     return lib
 
 
 lib = _load()
 
+# Device allocator callbacks (qt_set_allocator): alloc(bytes, stream, ctx) -> ptr, free_(ptr, stream, ctx).
+ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
+FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p)
+_installed = None     # the callbacks installed now
+_kept = []            # every callback pair ever installed: buffers made under one are returned through it
+
+
+def set_allocator(alloc, free_):
+    """qt_set_allocator with Python callables alloc(nbytes, stream) -> int and
+    free_(ptr, stream); (None, None) restores HIP's stream-ordered pool."""
+    global _installed
+    if alloc is None and free_ is None:
+        _check(lib.qt_set_allocator(None, None, None))
+        _installed = None
+        return
+    a = ALLOC_FN(lambda n, st, ctx: alloc(n, st))
+    f = FREE_FN(lambda p, st, ctx: free_(p, st))
+    _kept.append((a, f, alloc, free_))
+    _check(lib.qt_set_allocator(ctypes.cast(a, ctypes.c_void_p), ctypes.cast(f, ctypes.c_void_p), None))
+    _installed = (a, f, alloc, free_)
+
+
+class TorchAllocator:
+    """Device memory from torch's caching allocator.
+
+    A buffer is a uint8 tensor allocated with ``stream`` current, so torch
+    ties it to that stream. At free time the tensor is marked as used on the
+    freeing stream (``record_stream``): torch then hands the memory out again
+    only after the work queued there so far has finished, which is the
+    ordering qt_set_allocator asks for.
+    """
+
+    def __init__(self):
+        import threading
+        import torch
+        self._torch = torch
+        self._live = {}
+        self._streams = {}
+        self._lock = threading.Lock()
+
+    def _stream(self, ptr):
+        torch = self._torch
+        if not ptr:
+            return torch.cuda.default_stream()
+        with self._lock:
+            st = self._streams.get(ptr)
+            if st is None:
+                st = torch.cuda.ExternalStream(ptr)
+                self._streams[ptr] = st
+        return st
+
+    def alloc(self, nbytes, stream):
+        torch = self._torch
+        try:
+            st = self._stream(stream)
+            with torch.cuda.stream(st):
+                t = torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=torch.cuda.current_device())
+        except Exception:
+            return None
+        p = t.data_ptr()
+        with self._lock:
+            self._live[p] = (t, stream or 0)
+        return p
+
+    def free(self, p, stream):
+        with self._lock:
+            entry = self._live.pop(p, None)
+        if entry is None:
+            return
+        t, made_on = entry
+        if (stream or 0) != made_on:
+            t.record_stream(self._stream(stream))
+        del t
+
+    def outstanding(self) -> int:
+        with self._lock:
+            return len(self._live)
+
+
+def use_torch_allocator() -> TorchAllocator:
+    """Route the library's device memory through torch's caching allocator."""
+    ta = TorchAllocator()
+    set_allocator(ta.alloc, ta.free)
+    return ta
+
+
+def use_hip_pool():
+    """Back to HIP's stream-ordered pool (the library's own default)."""
+    set_allocator(None, None)
+
+
+def _default_allocator():
+    """On a GPU, torch's caching allocator serves the library's device memory
+    (QT_ALLOCATOR=hip keeps HIP's stream-ordered pool instead)."""
+    if os.environ.get("QT_ALLOCATOR", "torch") != "torch":
+        return None
+    try:
+        import torch
+    except ImportError:
+        return None
+    if not torch.cuda.is_available():
+        return None
+    return use_torch_allocator()
+
+
 EXPORTS = ("qt_build", "qt_multiply", "qt_multiply_ex", "qt_add", "qt_truncate", "qt_sysq", "qt_info", "qt_to_blocks", "qt_get_blocks", "qt_stats", "qt_levels", "qt_prepare", "qt_free",
            "qt_plan_create", "qt_plan_execute", "qt_plan_tune", "qt_plan_set_schedule", "qt_plan_result", "qt_plan_info",
-           "qt_plan_destroy", "qt_tune_leaf", "qt_profile", "qt_profile_read", "qt_probe_mfma", "qt_last_error", "qt_version")
+           "qt_plan_destroy", "qt_tune_leaf", "qt_profile", "qt_profile_read", "qt_probe_mfma", "qt_last_error", "qt_version",
+           "qt_set_allocator")
 PLAN_SCHEDULES = ("flat", "persistent-1", "persistent-4", "persistent-16")
 
 
@@ -378,3 +486,7 @@ def probe_mfma(prec: str = "f64", stream=None) -> float:
 
 def version() -> str:
     return lib.qt_version().decode()
+
+
+# installed last: it calls into the library through the helpers above
+ALLOCATOR = _default_allocator()

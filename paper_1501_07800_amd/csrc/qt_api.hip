@@ -87,7 +87,29 @@ using namespace qt;
         return QT_ERR_DEVICE;                                \
     }
 
+namespace qt {
+static std::mutex g_alloc_mu;
+static std::vector<std::unique_ptr<Allocator>> g_alloc_records;   // kept until the process ends
+}  // namespace qt
+
 extern "C" {
+
+qt_status qt_set_allocator(void* (*alloc)(size_t, void*, void*), void (*free_)(void*, void*, void*), void* ctx) {
+    if ((alloc == nullptr) != (free_ == nullptr)) {
+        set_last_error("alloc and free_ must both be set or both be NULL");
+        return QT_ERR_ARG;
+    }
+    QT_GUARD_BEGIN
+    if (!alloc) {
+        set_allocator(nullptr);
+        return QT_OK;
+    }
+    std::lock_guard<std::mutex> lk(g_alloc_mu);
+    g_alloc_records.push_back(std::unique_ptr<Allocator>(new Allocator{alloc, free_, ctx}));
+    set_allocator(g_alloc_records.back().get());
+    return QT_OK;
+    QT_GUARD_END
+}
 
 qt_status qt_build(int64_t n_rows, int64_t n_cols, int32_t block_size, int32_t leaf_size, int64_t nblocks,
                    const int32_t* I, const int32_t* J, const double* values, qt_mem where, void* stream,

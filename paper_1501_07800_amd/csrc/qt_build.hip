@@ -10,6 +10,7 @@
 #include "qt_morton.h"
 
 #include <algorithm>
+#include <atomic>
 #include <set>
 
 namespace qt {
@@ -31,9 +32,26 @@ static void ensure_pool() {
     g_pool_ready.insert(dev);
 }
 
-void* dev_alloc(size_t bytes, hipStream_t s) {
-    ensure_pool();
+static std::atomic<const Allocator*> g_allocator{nullptr};
+
+const Allocator* current_allocator() { return g_allocator.load(std::memory_order_acquire); }
+
+void set_allocator(const Allocator* a) { g_allocator.store(a, std::memory_order_release); }
+
+void* dev_alloc(size_t bytes, hipStream_t s, const Allocator** who) {
+    const Allocator* a = current_allocator();
+    *who = a;
     void* p = nullptr;
+    if (a) {
+        p = a->alloc(bytes, (void*)s, a->ctx);
+        if (!p) fail(QT_ERR_OOM, "the installed allocator returned no memory");
+        if (reinterpret_cast<uintptr_t>(p) & 255) {
+            a->free_(p, (void*)s, a->ctx);
+            fail(QT_ERR_DEVICE, "the installed allocator returned memory not aligned to 256 bytes");
+        }
+        return p;
+    }
+    ensure_pool();
     hipError_t e = hipMallocAsync(&p, bytes, s);
     if (e != hipSuccess) {
         (void)hipGetLastError();
@@ -42,8 +60,12 @@ void* dev_alloc(size_t bytes, hipStream_t s) {
     return p;
 }
 
-void dev_free(void* p, hipStream_t s) {
-    if (p) (void)hipFreeAsync(p, s);
+void dev_free(void* p, hipStream_t s, const Allocator* who) {
+    if (!p) return;
+    if (who)
+        who->free_(p, (void*)s, who->ctx);
+    else
+        (void)hipFreeAsync(p, s);
 }
 
 // --------------------------------------------------------------- kernels
@@ -446,62 +468,23 @@ const float* operand_f32(qt_matrix* M, hipStream_t s) {
     return M->v32.p;
 }
 
-// dst block t = src block t transposed
-template <class T>
-__global__ void k_transpose_blocks(const T* __restrict__ src, int64_t nblk, int b, T* __restrict__ dst) {
-    const int64_t bb = (int64_t)b * b;
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= nblk * bb) return;
-    const int64_t t = i / bb;
-    const int e = (int)(i - t * bb);
-    const int r = e / b, c = e - r * b;
-    dst[t * bb + (int64_t)c * b + r] = src[i];
-}
-
-const double* operand_f64_t(qt_matrix* M, hipStream_t s) {
-    const double* v = operand_f64(M, s);
-    std::lock_guard<std::mutex> lk(M->mu);
-    if (!M->v64_t.p && M->nblocks > 0) {
-        const int64_t n = M->nblocks * (int64_t)M->b * M->b;
-        M->v64_t.alloc(n, s);
-        k_transpose_blocks<double><<<grid_for(n), 256, 0, s>>>(v, M->nblocks, M->b, M->v64_t.p);
-        QT_LAUNCH("k_transpose_blocks");
-        form_mark(M->ev_v64_t, s);
-    }
-    form_ready(M->ev_v64_t, s);
-    return M->v64_t.p;
-}
-
-const float* operand_f32_t(qt_matrix* M, hipStream_t s) {
-    const float* v = operand_f32(M, s);
-    std::lock_guard<std::mutex> lk(M->mu);
-    if (!M->v32_t.p && M->nblocks > 0) {
-        const int64_t n = M->nblocks * (int64_t)M->b * M->b;
-        M->v32_t.alloc(n, s);
-        k_transpose_blocks<float><<<grid_for(n), 256, 0, s>>>(v, M->nblocks, M->b, M->v32_t.p);
-        QT_LAUNCH("k_transpose_blocks");
-        form_mark(M->ev_v32_t, s);
-    }
-    form_ready(M->ev_v32_t, s);
-    return M->v32_t.p;
-}
-
 void operand_bf16(qt_matrix* M, hipStream_t s) {
     std::lock_guard<std::mutex> lk(M->mu);
     if (!M->bf_hi.p && M->nblocks > 0) {
+        // all four parts are obtained before any is attached to the handle,
+        // so a failed allocation leaves no partial form behind
         const int64_t n = M->nblocks * (int64_t)M->b * M->b;
-        M->bf_hi.alloc(n, s);
-        M->bf_lo.alloc(n, s);
-        M->bf_hi_t.alloc(n, s);
-        M->bf_lo_t.alloc(n, s);
+        DBuf<uint16_t> hi(n, s), lo(n, s), hi_t(n, s), lo_t(n, s);
         if (M->vtype == QT_F64)
-            k_bf16_split<double><<<grid_for(n), 256, 0, s>>>(M->v64.p, M->nblocks, M->b, M->bf_hi.p, M->bf_lo.p,
-                                                             M->bf_hi_t.p, M->bf_lo_t.p);
+            k_bf16_split<double><<<grid_for(n), 256, 0, s>>>(M->v64.p, M->nblocks, M->b, hi.p, lo.p, hi_t.p, lo_t.p);
         else
-            k_bf16_split<float><<<grid_for(n), 256, 0, s>>>(M->v32.p, M->nblocks, M->b, M->bf_hi.p, M->bf_lo.p,
-                                                            M->bf_hi_t.p, M->bf_lo_t.p);
+            k_bf16_split<float><<<grid_for(n), 256, 0, s>>>(M->v32.p, M->nblocks, M->b, hi.p, lo.p, hi_t.p, lo_t.p);
         QT_LAUNCH("k_bf16_split");
         form_mark(M->ev_bf16, s);
+        M->bf_hi = std::move(hi);
+        M->bf_lo = std::move(lo);
+        M->bf_hi_t = std::move(hi_t);
+        M->bf_lo_t = std::move(lo_t);
     }
     form_ready(M->ev_bf16, s);
 }
@@ -509,6 +492,29 @@ void operand_bf16(qt_matrix* M, hipStream_t s) {
 // ----------------------------------------------------------------- build
 
 void build_tree_levels(qt_matrix* M, hipStream_t s);
+
+// Block keys in Morton order and the quadtree levels of M (shape fields set,
+// nblocks > 0) from a device block list; perm[t] receives the list position
+// of the block at sorted position t. Rejects out-of-range and repeated (I, J).
+static void build_structure(qt_matrix* M, const int32_t* pI, const int32_t* pJ, int64_t nblocks, int64_t nbr,
+                            int64_t nbc, DBuf<int32_t>& perm, hipStream_t s) {
+    int64_t npow2 = 1;
+    while (npow2 < nblocks) npow2 <<= 1;
+    DBuf<uint64_t> keys(npow2, s);
+    perm.alloc(npow2, s);
+    DBuf<int32_t> derr(1, s);
+    QT_HIP(hipMemsetAsync(derr.p, 0, sizeof(int32_t), s));
+    k_build_keys<<<grid_for(nblocks), 256, 0, s>>>(pI, pJ, nblocks, nbr, nbc, keys.p, perm.p, derr.p);
+    QT_LAUNCH("k_build_keys");
+    bitonic_sort(keys.p, perm.p, nblocks, s);
+    k_build_dups<<<grid_for(nblocks), 256, 0, s>>>(keys.p, nblocks, derr.p);
+    QT_LAUNCH("k_build_dups");
+    const int32_t err = read_scalar(derr.p, s);
+    if (err & 1) fail(QT_ERR_ARG, "block index out of range");
+    if (err & 2) fail(QT_ERR_DUPLICATE, "the same (I, J) block is listed twice");
+    M->bkey = std::move(keys);   // first nblocks entries are the sorted keys
+    build_tree_levels(M, s);
+}
 
 qt_matrix* build(int64_t n_rows, int64_t n_cols, int32_t b, int32_t leaf, int64_t nblocks, const int32_t* I,
                  const int32_t* J, const double* values, qt_mem where, hipStream_t s) {
@@ -569,26 +575,11 @@ qt_matrix* build(int64_t n_rows, int64_t n_cols, int32_t b, int32_t leaf, int64_
         pV = dV.p;
     }
 
-    int64_t npow2 = 1;
-    while (npow2 < nblocks) npow2 <<= 1;
-    DBuf<uint64_t> keys(npow2, s);
-    DBuf<int32_t> perm(npow2, s);
-    DBuf<int32_t> derr(1, s);
-    QT_HIP(hipMemsetAsync(derr.p, 0, sizeof(int32_t), s));
-    k_build_keys<<<grid_for(nblocks), 256, 0, s>>>(pI, pJ, nblocks, nbr, nbc, keys.p, perm.p, derr.p);
-    QT_LAUNCH("k_build_keys");
-    bitonic_sort(keys.p, perm.p, nblocks, s);
-    k_build_dups<<<grid_for(nblocks), 256, 0, s>>>(keys.p, nblocks, derr.p);
-    QT_LAUNCH("k_build_dups");
-    const int32_t err = read_scalar(derr.p, s);
-    if (err & 1) fail(QT_ERR_ARG, "block index out of range");
-    if (err & 2) fail(QT_ERR_DUPLICATE, "the same (I, J) block is listed twice");
-
+    DBuf<int32_t> perm;
+    build_structure(M.get(), pI, pJ, nblocks, nbr, nbc, perm, s);
     M->v64.alloc((size_t)nblocks * bb, s);
     k_gather_blocks<double><<<block_grid(nblocks), 256, 0, s>>>(pV, perm.p, nblocks, bb, M->v64.p);
     QT_LAUNCH("k_gather_blocks");
-    M->bkey = std::move(keys);   // first nblocks entries are the sorted keys
-    build_tree_levels(M.get(), s);
     build_histograms(M.get(), s);
     QT_HIP(hipStreamSynchronize(s));
     return M.release();
@@ -725,9 +716,10 @@ void to_blocks(const qt_matrix* M, int32_t* I, int32_t* J, void* values, qt_prec
     }
 }
 
-// Blocks of the full symmetric matrix from an upper block triangle: block t
-// (I <= J) goes to slot t, and its mirror (J, I) = block^T to slot
-// nblocks + rank among the strictly upper blocks.
+// The full symmetric matrix S from its upper block triangle A, as structure
+// only: block (I, J), I <= J, of A is block (I, J) of S, and for I < J also
+// block (J, I) of S, read transposed. S holds no values; its block map points
+// every block of S at the block of A that holds it (top bit: transposed).
 __global__ void k_mirror_flags(const uint64_t* __restrict__ bkey, int64_t n, int32_t* __restrict__ upper,
                                int32_t* __restrict__ err) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -737,30 +729,28 @@ __global__ void k_mirror_flags(const uint64_t* __restrict__ bkey, int64_t n, int
     if (i > j) atomicOr(err, 1);
 }
 
-__global__ void k_mirror_fill(const uint64_t* __restrict__ bkey, const double* __restrict__ v, int64_t n, int b,
-                              const int32_t* __restrict__ upper, const int32_t* __restrict__ rank,
-                              int32_t* __restrict__ I, int32_t* __restrict__ J, double* __restrict__ V) {
-    const int64_t bb = (int64_t)b * b;
-    for (int64_t t = blockIdx.x; t < n; t += gridDim.x) {
-        const int32_t i = (int32_t)morton_row(bkey[t]), j = (int32_t)morton_col(bkey[t]);
-        const double* src = v + t * bb;
-        if (threadIdx.x == 0) {
-            I[t] = i;
-            J[t] = j;
-        }
-        for (int e = threadIdx.x; e < bb; e += blockDim.x) V[t * bb + e] = src[e];
-        if (upper[t]) {
-            const int64_t m = n + rank[t];
-            if (threadIdx.x == 0) {
-                I[m] = j;
-                J[m] = i;
-            }
-            for (int e = threadIdx.x; e < bb; e += blockDim.x) {
-                const int r = e / b, c = e - r * b;
-                V[m * bb + (int64_t)c * b + r] = src[e];
-            }
-        }
+// entries t < n: A's blocks; entry n + rank[t]: the mirror of strictly upper block t
+__global__ void k_mirror_list(const uint64_t* __restrict__ bkey, int64_t n, const int32_t* __restrict__ upper,
+                              const int32_t* __restrict__ rank, int32_t* __restrict__ I, int32_t* __restrict__ J,
+                              int32_t* __restrict__ src) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n) return;
+    const int32_t i = (int32_t)morton_row(bkey[t]), j = (int32_t)morton_col(bkey[t]);
+    I[t] = i;
+    J[t] = j;
+    src[t] = (int32_t)t;
+    if (upper[t]) {
+        const int64_t m = n + rank[t];
+        I[m] = j;
+        J[m] = i;
+        src[m] = (int32_t)((uint32_t)t | PROD_TRANS);
     }
+}
+
+__global__ void k_gather_i32(const int32_t* __restrict__ src, const int32_t* __restrict__ perm, int64_t n,
+                             int32_t* __restrict__ dst) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n) dst[t] = src[perm[t]];
 }
 
 qt_matrix* symmetric_full(qt_matrix* A, hipStream_t s) {
@@ -768,28 +758,45 @@ qt_matrix* symmetric_full(qt_matrix* A, hipStream_t s) {
     if (A->sym_full) return A->sym_full.get();
     if (A->n_rows != A->n_cols) fail(QT_ERR_SHAPE, "a symmetric matrix must be square");
     const int64_t n = A->nblocks;
-    const int bb = A->b * A->b;
-    if (n == 0) {
-        A->sym_full.reset(build(A->n_rows, A->n_cols, A->b, A->leaf, 0, nullptr, nullptr, nullptr, QT_MEM_DEVICE, s));
-        return A->sym_full.get();
+    std::unique_ptr<qt_matrix> S(new qt_matrix);
+    S->n_rows = A->n_rows;
+    S->n_cols = A->n_cols;
+    S->b = A->b;
+    S->leaf = A->leaf;
+    S->lb = A->lb;
+    S->lb_log = A->lb_log;
+    S->L = A->L;
+    S->vtype = A->vtype;
+    S->stream = s;
+    S->device = A->device;
+    S->levels.resize(S->L);
+    S->vsrc = A;
+    if (n > 0) {
+        DBuf<int32_t> up(n, s), rank(n + 1, s), tmp(scan_tmp_elems(n) + 1, s), err(1, s);
+        QT_HIP(hipMemsetAsync(err.p, 0, sizeof(int32_t), s));
+        k_mirror_flags<<<grid_for(n), 256, 0, s>>>(A->bkey.p, n, up.p, err.p);
+        QT_LAUNCH("k_mirror_flags");
+        exclusive_scan(up.p, rank.p, n, tmp.p, s);
+        int32_t h[2] = {0, 0};
+        QT_HIP(hipMemcpyAsync(&h[0], rank.p + n, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        QT_HIP(hipMemcpyAsync(&h[1], err.p, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        QT_HIP(hipStreamSynchronize(s));
+        if (h[1]) fail(QT_ERR_ARG, "upper-triangular storage holds a block below the diagonal");
+        const int64_t total = n + h[0];
+        if (total > (int64_t(1) << 31) - 2) fail(QT_ERR_UNSUPPORTED, "too many blocks");
+        DBuf<int32_t> I(total, s), J(total, s), src(total, s);
+        k_mirror_list<<<grid_for(n), 256, 0, s>>>(A->bkey.p, n, up.p, rank.p, I.p, J.p, src.p);
+        QT_LAUNCH("k_mirror_list");
+        S->nblocks = total;
+        DBuf<int32_t> perm;
+        build_structure(S.get(), I.p, J.p, total, A->n_rows / A->b, A->n_cols / A->b, perm, s);
+        S->bmap.alloc(total, s);
+        k_gather_i32<<<grid_for(total), 256, 0, s>>>(src.p, perm.p, total, S->bmap.p);
+        QT_LAUNCH("k_gather_i32");
     }
-    if (A->vtype != QT_F64) fail(QT_ERR_UNSUPPORTED, "symmetric square of an fp32 matrix");
-    DBuf<int32_t> up(n, s), rank(n + 1, s), tmp(scan_tmp_elems(n) + 1, s), err(1, s);
-    QT_HIP(hipMemsetAsync(err.p, 0, sizeof(int32_t), s));
-    k_mirror_flags<<<grid_for(n), 256, 0, s>>>(A->bkey.p, n, up.p, err.p);
-    QT_LAUNCH("k_mirror_flags");
-    exclusive_scan(up.p, rank.p, n, tmp.p, s);
-    int32_t h[2] = {0, 0};
-    QT_HIP(hipMemcpyAsync(&h[0], rank.p + n, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-    QT_HIP(hipMemcpyAsync(&h[1], err.p, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    build_histograms(S.get(), s);
     QT_HIP(hipStreamSynchronize(s));
-    if (h[1]) fail(QT_ERR_ARG, "upper-triangular storage holds a block below the diagonal");
-    const int64_t total = n + h[0];
-    DBuf<int32_t> I(total, s), J(total, s);
-    DBuf<double> V((size_t)total * bb, s);
-    k_mirror_fill<<<block_grid(n), 256, 0, s>>>(A->bkey.p, A->v64.p, n, A->b, up.p, rank.p, I.p, J.p, V.p);
-    QT_LAUNCH("k_mirror_fill");
-    A->sym_full.reset(build(A->n_rows, A->n_cols, A->b, A->leaf, total, I.p, J.p, V.p, QT_MEM_DEVICE, s));
+    A->sym_full = std::move(S);
     return A->sym_full.get();
 }
 

@@ -37,26 +37,42 @@ void set_last_error(const std::string& m);
 
 // ------------------------------------------------------- device buffers
 
-// Stream-ordered device allocation (hipMallocAsync from the device's default
-// pool, whose release threshold is raised so freed memory is reused).
-void* dev_alloc(size_t bytes, hipStream_t s);
-void dev_free(void* p, hipStream_t s);
+// A caller-installed device allocator (qt_set_allocator). Records are never
+// freed, so a buffer can always be returned to the allocator that made it.
+struct Allocator {
+    void* (*alloc)(size_t bytes, void* stream, void* ctx);
+    void (*free_)(void* p, void* stream, void* ctx);
+    void* ctx;
+};
+// The allocator new buffers come from (nullptr: HIP's stream-ordered pool).
+const Allocator* current_allocator();
+void set_allocator(const Allocator* a);   // nullptr: back to HIP's pool
 
-// Owning device buffer; released stream-ordered on the stream it was made on.
-// A DBuf may also be a non-owning view into memory owned elsewhere (an arena).
+// Stream-ordered device allocation: from the installed allocator, else
+// hipMallocAsync from the device's default pool (whose release threshold is
+// raised so freed memory is reused). *who receives the allocator used.
+// Throws QT_ERR_OOM when the allocation fails.
+void* dev_alloc(size_t bytes, hipStream_t s, const Allocator** who);
+void dev_free(void* p, hipStream_t s, const Allocator* who);
+
+// Owning device buffer; released stream-ordered on the stream it was made on
+// (or on the stream assigned to `s` later), through the allocator that made
+// it. A DBuf may also be a non-owning view into memory owned elsewhere (an
+// arena).
 template <class T>
 struct DBuf {
     T* p = nullptr;
     size_t n = 0;
     hipStream_t s = nullptr;
     bool own = true;
+    const Allocator* al = nullptr;
     DBuf() = default;
     DBuf(size_t count, hipStream_t st) { alloc(count, st); }
     void alloc(size_t count, hipStream_t st) {
         release();
         s = st;
         n = count;
-        p = count ? static_cast<T*>(dev_alloc(count * sizeof(T), st)) : nullptr;
+        p = count ? static_cast<T*>(dev_alloc(count * sizeof(T), st, &al)) : nullptr;
     }
     void view(void* ptr, size_t count) {
         release();
@@ -65,26 +81,36 @@ struct DBuf {
         own = false;
     }
     void release() {
-        if (p && own) dev_free(p, s);
+        if (p && own) dev_free(p, s, al);
         p = nullptr;
         n = 0;
         own = true;
+        al = nullptr;
     }
     ~DBuf() { release(); }
     DBuf(const DBuf&) = delete;
     DBuf& operator=(const DBuf&) = delete;
-    DBuf(DBuf&& o) noexcept : p(o.p), n(o.n), s(o.s), own(o.own) { o.p = nullptr; o.n = 0; o.own = true; }
+    DBuf(DBuf&& o) noexcept : p(o.p), n(o.n), s(o.s), own(o.own), al(o.al) {
+        o.p = nullptr; o.n = 0; o.own = true; o.al = nullptr;
+    }
     DBuf& operator=(DBuf&& o) noexcept {
         if (this != &o) {
             release();
-            p = o.p; n = o.n; s = o.s; own = o.own;
-            o.p = nullptr; o.n = 0; o.own = true;
+            p = o.p; n = o.n; s = o.s; own = o.own; al = o.al;
+            o.p = nullptr; o.n = 0; o.own = true; o.al = nullptr;
         }
         return *this;
     }
 };
 
 // ------------------------------------------------------------ the handle
+
+// An entry of a product list is a block index into the operand's values; its
+// top bit marks a block read transposed (every block of an operand used as
+// X^T, or a mirrored block of a symmetric matrix stored as its upper
+// triangle). Block counts stay below 2^31 - 1, so the index fits below it.
+constexpr int32_t PROD_INDEX = 0x7fffffff;
+constexpr uint32_t PROD_TRANS = 0x80000000u;
 
 // One quadtree level above the leaves: n nodes, child[4*i + q] is the index
 // of child q = 2*m + n of node i in the next level, or -1 for NIL.
@@ -147,11 +173,8 @@ struct qt_matrix {
     qt::DBuf<uint16_t> bf_hi, bf_lo;     // bf16 split, row-major per block
     qt::DBuf<uint16_t> bf_hi_t, bf_lo_t; // same, each block transposed
     qt::DBuf<double> v64_cache;          // fp64 copy when vtype == QT_F32
-    std::unique_ptr<qt_matrix> sym_full; // full symmetric matrix from this upper triangle
-    qt::DBuf<double> v64_t;              // fp64 values, every block transposed
-    qt::DBuf<float> v32_t;               // fp32 values, every block transposed
-    hipEvent_t ev_v32 = nullptr, ev_v64 = nullptr, ev_bf16 = nullptr, ev_v64_t = nullptr, ev_v32_t = nullptr,
-               ev_sym = nullptr;
+    std::unique_ptr<qt_matrix> sym_full; // structure of the full symmetric matrix from this upper triangle
+    hipEvent_t ev_v32 = nullptr, ev_v64 = nullptr, ev_bf16 = nullptr;
     qt::Histograms hist;                 // built once, under mu (build_histograms)
 
     // counters of the multiply that produced this matrix
@@ -159,11 +182,17 @@ struct qt_matrix {
     int64_t products = 0;
     bool plan_owned = false;  // a batch plan's result: released with the plan
 
+    // A structure-only matrix (the full symmetric form of an upper block
+    // triangle) holds no values: its block t is block bmap[t] & PROD_INDEX of
+    // vsrc, read transposed when the top bit of bmap[t] is set.
+    qt_matrix* vsrc = nullptr;
+    qt::DBuf<int32_t> bmap;
+
     qt_matrix() = default;
     qt_matrix(const qt_matrix&) = delete;
     qt_matrix& operator=(const qt_matrix&) = delete;
     ~qt_matrix() {
-        for (hipEvent_t e : {ev_v32, ev_v64, ev_bf16, ev_v64_t, ev_v32_t, ev_sym})
+        for (hipEvent_t e : {ev_v32, ev_v64, ev_bf16})
             if (e) (void)hipEventDestroy(e);
     }
 };
@@ -198,8 +227,6 @@ void bitonic_sort(uint64_t* keys, int32_t* vals, int64_t n, hipStream_t s);
 void build_histograms(qt_matrix* M, hipStream_t s);   // fills M->hist (synchronizes)
 const double* operand_f64(qt_matrix* M, hipStream_t s);
 const float* operand_f32(qt_matrix* M, hipStream_t s);
-const double* operand_f64_t(qt_matrix* M, hipStream_t s);   // every block transposed
-const float* operand_f32_t(qt_matrix* M, hipStream_t s);
 void operand_bf16(qt_matrix* M, hipStream_t s);
 uint64_t morton2(uint32_t r, uint32_t c);
 
@@ -210,9 +237,12 @@ struct NumericArgs {
     const void* A;            // fp64 or fp32 blocks of A
     const void* B;
     const uint16_t* Ahi; const uint16_t* Alo;    // bf16 split of A (row-major blocks)
+    const uint16_t* Ahi_t; const uint16_t* Alo_t; // bf16 split of A (transposed blocks)
+    const uint16_t* Bhi; const uint16_t* Blo;    // bf16 split of B (row-major blocks)
     const uint16_t* Bhi_t; const uint16_t* Blo_t; // bf16 split of B (transposed blocks)
-    const int32_t* prodA;     // per product: block index into A
+    const int32_t* prodA;     // per product: block index into A (top bit: read transposed, if dyn)
     const int32_t* prodB;     // per product: block index into B
+    int dyn;                  // products may read operand blocks transposed (PROD_TRANS)
     const int32_t* seg;       // nseg + 1 offsets into the product lists
     int32_t nseg;
     const int32_t* order;     // launch slot q computes C block order[q] (a permutation
@@ -284,7 +314,8 @@ qt_matrix* build(int64_t n_rows, int64_t n_cols, int32_t b, int32_t leaf, int64_
                  const int32_t* J, const double* values, qt_mem where, hipStream_t s);
 qt_matrix* add(qt_matrix* A, qt_matrix* B, hipStream_t s);
 qt_matrix* truncate(qt_matrix* M, double eps, hipStream_t s, int64_t* removed, double* removed_norm2);
-// The full symmetric matrix whose upper block triangle is A (cached in A).
+// The structure of the full symmetric matrix whose upper block triangle is A
+// (cached in A; its values are A's, through its block map).
 qt_matrix* symmetric_full(qt_matrix* A, hipStream_t s);
 
 }  // namespace qt

@@ -412,6 +412,8 @@ struct LeafStep {
     int32_t* check;
     int ta, tb;               // op(A) = A^T / op(B) = B^T (masks already swapped by the host)
     int upper;                // keep only blocks on or above the diagonal
+    const int32_t* amap;      // structure-only A: its block t is held by its value source as amap[t]
+    const int32_t* bmap;
 };
 
 // Lane t's value in every lane, for a t that is the same in every lane: a
@@ -524,8 +526,11 @@ __device__ void leaf_fill_node(const LeafStep& st, int32_t c, int lane, int64_t 
                 const uint32_t qb = st.tb ? (uint32_t)morton_key((uint32_t)j, (uint32_t)k)
                                           : (uint32_t)morton_key((uint32_t)k, (uint32_t)j);
                 if (out < st.P) {
-                    st.prodA[out] = abt + __popcll(amot & ((1ull << qa) - 1));
-                    st.prodB[out] = bbt + __popcll(bmot & ((1ull << qb) - 1));
+                    // the block of the value source, with the transposition bit
+                    const int32_t ia = abt + __popcll(amot & ((1ull << qa) - 1));
+                    const int32_t ib = bbt + __popcll(bmot & ((1ull << qb) - 1));
+                    st.prodA[out] = st.amap ? st.amap[ia] : (int32_t)((uint32_t)ia | (st.ta ? PROD_TRANS : 0u));
+                    st.prodB[out] = st.bmap ? st.bmap[ib] : (int32_t)((uint32_t)ib | (st.tb ? PROD_TRANS : 0u));
                 }
                 ++out;
             }
@@ -734,8 +739,12 @@ constexpr int64_t KORDER_MAX_CELLS = int64_t(1) << 24;         // (k, workgroup)
 
 __device__ __forceinline__ int32_t first_k(const uint64_t* __restrict__ akey, const int32_t* __restrict__ prodA,
                                            const int32_t* __restrict__ seg, int64_t s, bool ta, int32_t kdim) {
-    const uint64_t key = akey[prodA[seg[s]]];
-    const int64_t k = ta ? (int64_t)morton_row(key) : (int64_t)morton_col(key);   // column of op(A)
+    // a product whose A block is read transposed (top bit set) has its inner
+    // index in the stored block's row
+    const int32_t pa = prodA[seg[s]];
+    const uint64_t key = akey[pa & PROD_INDEX];
+    const int64_t k = (pa < 0) ? (int64_t)morton_row(key) : (int64_t)morton_col(key);   // column of op(A)
+    (void)ta;
     return (int32_t)(k < 0 ? 0 : (k >= kdim ? kdim - 1 : k));
 }
 
@@ -1037,24 +1046,33 @@ void symbolic(qt_matrix* A, qt_matrix* B, qt_prec prec, hipStream_t s, SymbolicO
         return;
     }
 
-    // operand forms for this precision; a transposed operand reads a copy of
-    // its values with every block transposed (same block order)
+    // operand forms for this precision, from the matrices that hold the values
+    // (a structure-only operand reads its value source's blocks). A block read
+    // transposed is marked in the product lists and transposed as it is
+    // loaded: no transposed copy of any operand is made.
+    qt_matrix* Av = A->vsrc ? A->vsrc : A;
+    qt_matrix* Bv = B->vsrc ? B->vsrc : B;
     NumericArgs na{};
     na.b = A->b;
     na.prec = prec;
+    na.dyn = (op.ta || op.tb || A->vsrc || B->vsrc) ? 1 : 0;
     if (prec == QT_F64) {
-        na.A = op.ta ? operand_f64_t(A, s) : operand_f64(A, s);
-        na.B = op.tb ? operand_f64_t(B, s) : operand_f64(B, s);
+        na.A = operand_f64(Av, s);
+        na.B = operand_f64(Bv, s);
     } else if (prec == QT_F32) {
-        na.A = op.ta ? operand_f32_t(A, s) : operand_f32(A, s);
-        na.B = op.tb ? operand_f32_t(B, s) : operand_f32(B, s);
+        na.A = operand_f32(Av, s);
+        na.B = operand_f32(Bv, s);
     } else {
-        operand_bf16(A, s);
-        operand_bf16(B, s);
-        na.Ahi = op.ta ? A->bf_hi_t.p : A->bf_hi.p;
-        na.Alo = op.ta ? A->bf_lo_t.p : A->bf_lo.p;
-        na.Bhi_t = op.tb ? B->bf_hi.p : B->bf_hi_t.p;
-        na.Blo_t = op.tb ? B->bf_lo.p : B->bf_lo_t.p;
+        operand_bf16(Av, s);
+        operand_bf16(Bv, s);
+        na.Ahi = Av->bf_hi.p;
+        na.Alo = Av->bf_lo.p;
+        na.Ahi_t = Av->bf_hi_t.p;
+        na.Alo_t = Av->bf_lo_t.p;
+        na.Bhi = Bv->bf_hi.p;
+        na.Blo = Bv->bf_lo.p;
+        na.Bhi_t = Bv->bf_hi_t.p;
+        na.Blo_t = Bv->bf_lo_t.p;
     }
 
     // ---- plan the two allocations
@@ -1225,6 +1243,8 @@ void symbolic(qt_matrix* A, qt_matrix* B, qt_prec prec, hipStream_t s, SymbolicO
     ls.ta = op.ta;
     ls.tb = op.tb;
     ls.upper = op.upper;
+    ls.amap = A->vsrc ? A->bmap.p : nullptr;
+    ls.bmap = B->vsrc ? B->bmap.p : nullptr;
     ls.Amo = A->leaves.mask_mo.p;
     ls.Bmo = B->leaves.mask_mo.p;
     ls.Abase = A->leaves.base.p;
@@ -1322,7 +1342,7 @@ void symbolic(qt_matrix* A, qt_matrix* B, qt_prec prec, hipStream_t s, SymbolicO
     if (korder) {
         int32_t* kcnt = (int32_t*)at(W, o_kcnt);
         int32_t* knext = (int32_t*)at(W, o_knext);
-        const uint64_t* akey = A->bkey.p;
+        const uint64_t* akey = Av->bkey.p;   // keys of the blocks the products name
         const int64_t nwg = (nnzC + KORDER_WG - 1) / KORDER_WG;   // <= kwg_cap, as nnzC <= cap
         const size_t lds = (size_t)kdim * sizeof(int32_t);
         k_korder_counts<<<(unsigned)nwg, KORDER_THREADS, lds, ss>>>(akey, ls.prodA, ls.cbseg, nnzC, op.ta,

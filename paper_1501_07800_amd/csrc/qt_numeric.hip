@@ -194,6 +194,127 @@ __device__ __forceinline__ void wave_block(const T* __restrict__ A, const T* __r
     }
 }
 
+// As wave_block, for product lists whose block indices may carry the
+// transposition bit (PROD_TRANS): the block is then read as its transpose,
+// op(A) = A^T or op(B) = B^T for that product, straight from the stored
+// block. A lane's rows interleave like its columns (lane r16 holds rows
+// 2 r16 and 2 r16 + 1 in tiles 0 and 1), so a transposed A block, whose rows
+// of op(A) are stored columns, gives both of a lane's rows in one load of two
+// adjacent entries, as an untransposed B block gives both of its columns.
+// A transposed B block gives a lane VEC consecutive inner indices of one
+// column in one load, as an untransposed A block does for a row. The
+// transposition is uniform over the wave (one product at a time), so the
+// choice is a scalar branch. The inner index order is wave_block's, so every
+// result is bitwise what wave_block gives on transposed copies of the blocks.
+template <class T, int BS>
+__device__ __forceinline__ void wave_block_op(const T* __restrict__ A, const T* __restrict__ B,
+                                              const int32_t* __restrict__ prodA, const int32_t* __restrict__ prodB,
+                                              int32_t t0, int32_t t1, T* __restrict__ c, int sub) {
+    typedef Geo<BS> G;
+    typedef typename Mfma<T>::acc acc_t;
+    constexpr int VEC = 16 / sizeof(T);
+    constexpr int NV = G::KS / VEC;
+    constexpr int RS = G::MT;                      // stride between a lane's rows (and columns)
+    typedef T vec_t __attribute__((ext_vector_type(VEC)));
+    typedef T pair_t __attribute__((ext_vector_type(2)));
+    const int lane = threadIdx.x & 63;
+    const int r16 = lane & 15;
+    const int g = lane >> 4;
+    const int wm = (sub / (BS / G::WT)) * G::WT;
+    const int wn = (sub % (BS / G::WT)) * G::WT;
+
+    acc_t acc[G::MT][G::MT];
+#pragma unroll
+    for (int i = 0; i < G::MT; ++i)
+#pragma unroll
+        for (int j = 0; j < G::MT; ++j) acc[i][j] = acc_t{0, 0, 0, 0};
+
+    int32_t ia = prodA[t0], ib = prodB[t0];
+    for (int32_t t = t0; t < t1; ++t) {
+        const bool ta = ia < 0, tb = ib < 0;
+        const T* a = A + (size_t)(ia & PROD_INDEX) * (BS * BS);
+        const T* b = B + (size_t)(ib & PROD_INDEX) * (BS * BS);
+        if (t + 1 < t1) {
+            ia = prodA[t + 1];
+            ib = prodB[t + 1];
+        }
+#pragma unroll
+        for (int ch = 0; ch < G::NCH; ++ch) {
+            T ar[G::MT][G::KS], br[G::MT][G::KS];
+            if (!ta) {
+#pragma unroll
+                for (int mt = 0; mt < G::MT; ++mt) {
+                    const T* row = a + (wm + RS * r16 + mt) * BS + ch * G::KC + g * VEC;
+#pragma unroll
+                    for (int v = 0; v < NV; ++v) {
+                        const vec_t x = *reinterpret_cast<const vec_t*>(row + v * 4 * VEC);
+#pragma unroll
+                        for (int e = 0; e < VEC; ++e) ar[mt][v * VEC + e] = x[e];
+                    }
+                }
+            } else {
+#pragma unroll
+                for (int ks = 0; ks < G::KS; ++ks) {
+                    const int k = ch * G::KC + (ks / VEC) * 4 * VEC + g * VEC + ks % VEC;
+                    if constexpr (G::MT == 2) {
+                        const pair_t x = *reinterpret_cast<const pair_t*>(a + k * BS + wm + 2 * r16);
+                        ar[0][ks] = x[0];
+                        ar[1][ks] = x[1];
+                    } else {
+                        ar[0][ks] = a[k * BS + wm + r16];
+                    }
+                }
+            }
+            if (!tb) {
+#pragma unroll
+                for (int ks = 0; ks < G::KS; ++ks) {
+                    const int k = ch * G::KC + (ks / VEC) * 4 * VEC + g * VEC + ks % VEC;
+                    if constexpr (G::MT == 2) {
+                        const pair_t x = *reinterpret_cast<const pair_t*>(b + k * BS + wn + 2 * r16);
+                        br[0][ks] = x[0];
+                        br[1][ks] = x[1];
+                    } else {
+                        br[0][ks] = b[k * BS + wn + r16];
+                    }
+                }
+            } else {
+#pragma unroll
+                for (int nt = 0; nt < G::MT; ++nt) {
+                    const T* col = b + (wn + RS * r16 + nt) * BS + ch * G::KC + g * VEC;
+#pragma unroll
+                    for (int v = 0; v < NV; ++v) {
+                        const vec_t x = *reinterpret_cast<const vec_t*>(col + v * 4 * VEC);
+#pragma unroll
+                        for (int e = 0; e < VEC; ++e) br[nt][v * VEC + e] = x[e];
+                    }
+                }
+            }
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int ks = 0; ks < G::KS; ++ks)
+#pragma unroll
+                for (int mt = 0; mt < G::MT; ++mt)
+#pragma unroll
+                    for (int nt = 0; nt < G::MT; ++nt)
+                        acc[mt][nt] = Mfma<T>::step(ar[mt][ks], br[nt][ks], acc[mt][nt]);
+        }
+    }
+    if constexpr (G::MT == 2) {
+#pragma unroll
+        for (int mt = 0; mt < G::MT; ++mt)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const pair_t v = {acc[mt][0][i], acc[mt][1][i]};
+                __builtin_nontemporal_store(
+                    v, reinterpret_cast<pair_t*>(c + (wm + 2 * Mfma<T>::row(g, i) + mt) * BS + wn + 2 * r16));
+            }
+    } else {
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+            __builtin_nontemporal_store(acc[0][0][i], c + (wm + Mfma<T>::row(g, i)) * BS + wn + r16);
+    }
+}
+
 // Split-bf16 path: per block product, F = lo_a*hi_b + hi_a*lo_b + hi_a*hi_b
 // in fp32 MFMA (16 x 16 x 32 bf16: lane 16*g + r supplies A[r][8g .. 8g+7]
 // and B[8g .. 8g+7][r]); F is then added into fp64 accumulators, and C is
@@ -206,13 +327,23 @@ __device__ __forceinline__ v8bf load8(const uint16_t* p) {
     return r;
 }
 
-template <int BS>
+// Split operands of one product: op(A) row-major (A's split, or the split of
+// the transposed block) and op(B)^T row-major (B's transposed split, or B's
+// own split when the product reads B transposed).
+struct SplitOps {
+    const uint16_t* Ahi; const uint16_t* Alo;
+    const uint16_t* Ahi_t; const uint16_t* Alo_t;
+    const uint16_t* Bhi; const uint16_t* Blo;
+    const uint16_t* Bhi_t; const uint16_t* Blo_t;
+};
+
+template <int BS, bool DYN = false>
 __device__ __forceinline__ void wave_block_bf16x3(const uint16_t* __restrict__ Ahi, const uint16_t* __restrict__ Alo,
                                                   const uint16_t* __restrict__ Bhi_t,
                                                   const uint16_t* __restrict__ Blo_t,
                                                   const int32_t* __restrict__ prodA,
                                                   const int32_t* __restrict__ prodB, int32_t t0, int32_t t1,
-                                                  double* __restrict__ c, int sub) {
+                                                  double* __restrict__ c, int sub, const SplitOps* ops = nullptr) {
     static_assert(BS == 32 || BS == 64, "split-bf16 path needs b = 32 or 64");
     constexpr int WT = 32, MT = 2;
     const int lane = threadIdx.x & 63;
@@ -228,8 +359,16 @@ __device__ __forceinline__ void wave_block_bf16x3(const uint16_t* __restrict__ A
         for (int j = 0; j < MT; ++j) acc[i][j] = v4d{0, 0, 0, 0};
 
     for (int32_t t = t0; t < t1; ++t) {
-        const size_t oa = (size_t)prodA[t] * (BS * BS);
-        const size_t ob = (size_t)prodB[t] * (BS * BS);
+        const int32_t ia = prodA[t], ib = prodB[t];
+        const size_t oa = (size_t)(ia & PROD_INDEX) * (BS * BS);
+        const size_t ob = (size_t)(ib & PROD_INDEX) * (BS * BS);
+        if constexpr (DYN) {
+            // a transposed block's row-major op form is the other layout of its split
+            Ahi = ia < 0 ? ops->Ahi_t : ops->Ahi;
+            Alo = ia < 0 ? ops->Alo_t : ops->Alo;
+            Bhi_t = ib < 0 ? ops->Bhi : ops->Bhi_t;
+            Blo_t = ib < 0 ? ops->Blo : ops->Blo_t;
+        }
         v4f f[MT][MT];
 #pragma unroll
         for (int i = 0; i < MT; ++i)
@@ -315,6 +454,40 @@ __global__ __launch_bounds__(64) void k_numeric_bf16x3(const uint16_t* __restric
     const int64_t s = order ? order[q] : q;
     wave_block_bf16x3<BS>(Ahi, Alo, Bhi_t, Blo_t, prodA, prodB, seg[s], seg[s + 1], C + (size_t)s * (BS * BS),
                           (int)(tile % WPB));
+}
+
+// One multiply whose products may read blocks transposed (transposed
+// operands, symmetric operands stored as a triangle): one wave per tile, as
+// k_numeric at b = 16 and 32, at every block size.
+template <class T, int BS>
+__global__ __launch_bounds__(64, (MinWaves<T, BS>::value)) void k_numeric_op(const T* __restrict__ A,
+                                                                           const T* __restrict__ B,
+                                                                           const int32_t* __restrict__ prodA,
+                                                                           const int32_t* __restrict__ prodB,
+                                                                           const int32_t* __restrict__ seg,
+                                                                           int32_t nseg,
+                                                                           const int32_t* __restrict__ order,
+                                                                           T* __restrict__ C) {
+    typedef Geo<BS> G;
+    const int64_t tile = xcd_logical<>(blockIdx.x);
+    const int64_t q = tile / G::WPB;
+    if (q >= nseg) return;
+    const int64_t s = order ? order[q] : q;
+    wave_block_op<T, BS>(A, B, prodA, prodB, seg[s], seg[s + 1], C + (size_t)s * (BS * BS), (int)(tile % G::WPB));
+}
+
+template <int BS>
+__global__ __launch_bounds__(64) void k_numeric_bf16x3_op(SplitOps ops, const int32_t* __restrict__ prodA,
+                                                          const int32_t* __restrict__ prodB,
+                                                          const int32_t* __restrict__ seg, int32_t nseg,
+                                                          const int32_t* __restrict__ order, double* __restrict__ C) {
+    constexpr int WPB = (BS / 32) * (BS / 32);
+    const int64_t tile = xcd_logical<>(blockIdx.x);
+    const int64_t q = tile / WPB;
+    if (q >= nseg) return;
+    const int64_t s = order ? order[q] : q;
+    wave_block_bf16x3<BS, true>(nullptr, nullptr, nullptr, nullptr, prodA, prodB, seg[s], seg[s + 1],
+                                C + (size_t)s * (BS * BS), (int)(tile % WPB), &ops);
 }
 
 // b = 64 fp64 with the operands shared through LDS, as for the split path
@@ -677,8 +850,47 @@ static void launch_bf(const NumericArgs& a, hipStream_t s) {
     QT_LAUNCH("k_numeric_bf16x3");
 }
 
+template <class T, int BS>
+static void launch_op(const NumericArgs& a, hipStream_t s) {
+    typedef Geo<BS> G;
+    const unsigned grid = xcd_grid<>((int64_t)a.nseg * G::WPB);
+    k_numeric_op<T, BS><<<grid, 64, 0, s>>>((const T*)a.A, (const T*)a.B, a.prodA, a.prodB, a.seg, a.nseg, a.order,
+                                            (T*)a.C);
+    QT_LAUNCH("k_numeric_op");
+}
+
+template <int BS>
+static void launch_bf_op(const NumericArgs& a, hipStream_t s) {
+    constexpr int WPB = (BS / 32) * (BS / 32);
+    const SplitOps ops{a.Ahi, a.Alo, a.Ahi_t, a.Alo_t, a.Bhi, a.Blo, a.Bhi_t, a.Blo_t};
+    const unsigned grid = xcd_grid<>((int64_t)a.nseg * WPB);
+    k_numeric_bf16x3_op<BS><<<grid, 64, 0, s>>>(ops, a.prodA, a.prodB, a.seg, a.nseg, a.order, (double*)a.C);
+    QT_LAUNCH("k_numeric_bf16x3_op");
+}
+
 void launch_numeric(const NumericArgs& a, hipStream_t s) {
     if (a.nseg <= 0) return;
+    if (a.dyn) {
+        if (a.prec == QT_F64) {
+            switch (a.b) {
+                case 16: return launch_op<double, 16>(a, s);
+                case 32: return launch_op<double, 32>(a, s);
+                case 64: return launch_op<double, 64>(a, s);
+            }
+        } else if (a.prec == QT_F32) {
+            switch (a.b) {
+                case 16: return launch_op<float, 16>(a, s);
+                case 32: return launch_op<float, 32>(a, s);
+                case 64: return launch_op<float, 64>(a, s);
+            }
+        } else if (a.prec == QT_BF16X3) {
+            switch (a.b) {
+                case 32: return launch_bf_op<32>(a, s);
+                case 64: return launch_bf_op<64>(a, s);
+            }
+        }
+        fail(QT_ERR_UNSUPPORTED, "no numeric kernel for this block size and precision");
+    }
     if (a.prec == QT_F64) {
         switch (a.b) {
             case 16: return launch_t<double, 16>(a, s);

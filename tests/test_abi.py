@@ -81,3 +81,17 @@ def test_plan_and_tuner_argument_checks():
     qt.lib.qt_plan_destroy(None)
     best = ctypes.c_int32()
     assert qt.lib.qt_tune_leaf(None, None, 0, None, 1, ctypes.byref(best), None, None, 0, None) == qt.QT_ERR_ARG
+
+
+def test_set_allocator_argument_checks():
+    """qt_set_allocator needs both callbacks or neither (no GPU needed)."""
+    import paper_1501_07800_amd as qt
+    a = qt.ALLOC_FN(lambda n, s, c: None)
+    f = qt.FREE_FN(lambda p, s, c: None)
+    assert qt.lib.qt_set_allocator(ctypes.cast(a, ctypes.c_void_p), None, None) == qt.QT_ERR_ARG
+    assert qt.lib.qt_set_allocator(None, ctypes.cast(f, ctypes.c_void_p), None) == qt.QT_ERR_ARG
+    prev = qt._installed
+    assert qt.lib.qt_set_allocator(ctypes.cast(a, ctypes.c_void_p), ctypes.cast(f, ctypes.c_void_p), None) == 0
+    assert qt.lib.qt_set_allocator(None, None, None) == 0
+    if prev is not None:          # put back what the binding installed
+        qt.set_allocator(prev[2], prev[3])

@@ -6,7 +6,7 @@ import pytest
 
 import oracle
 import workloads as wl
-from tests._util import (compare, positions, random_pattern, symmetric_from_upper, transpose,
+from tests._util import (compare, identity, positions, random_pattern, symmetric_from_upper, transpose,
                          upper_blocks)
 
 pytestmark = pytest.mark.gpu
@@ -116,6 +116,89 @@ def test_sysq(qt, prec):
     # about half the block products of the full square (Sec. 6.1: the expected speedup of 2)
     ratio = C.stats()["products"] / st.block_products
     assert 0.45 < ratio < 0.65, ratio
+
+
+@pytest.mark.parametrize("ta,tb", [(True, False), (False, True), (True, True)])
+@pytest.mark.parametrize("prec,b", [("f64", 32), ("f64", 16), ("f64", 64), ("f32", 32), ("f32", 64),
+                                    ("bf16x3", 32), ("bf16x3", 64)])
+def test_transposed_read_equals_explicit_transpose_bitwise(qt, prec, b, ta, tb):
+    """op(A) op(B) read straight from the stored blocks (no transposed copy)
+    is bitwise the plain product of operands transposed on the host: the
+    transposed loads feed the MFMAs the same inner indices in the same order."""
+    rng = np.random.default_rng(50 + b)
+    nb = 23 if b < 64 else 11
+    A = random_pattern(rng, nb, nb + 3, 0.12, b)            # op(A) is nb x (nb+3), or its transpose
+    if ta and not tb:
+        B = random_pattern(rng, nb, nb + 1, 0.12, b)
+    elif tb and not ta:
+        B = random_pattern(rng, nb + 2, nb + 3, 0.12, b)
+    else:
+        B = random_pattern(rng, nb + 1, nb, 0.12, b)
+    leaf = 4 * b
+    got = qt.multiply_ex(qt.from_blockmatrix(A, leaf), qt.from_blockmatrix(B, leaf), ta, tb, prec=prec)
+    At = transpose(A) if ta else A
+    Bt = transpose(B) if tb else B
+    ref = qt.multiply(qt.from_blockmatrix(At, leaf), qt.from_blockmatrix(Bt, leaf), prec)
+    I1, J1, V1 = got.to_blocks("f64")
+    I2, J2, V2 = ref.to_blocks("f64")
+    assert np.array_equal(I1, I2) and np.array_equal(J1, J2)
+    assert np.array_equal(V1, V2)
+
+
+@pytest.mark.parametrize("prec,b", [("f64", 16), ("f64", 64), ("f32", 64), ("bf16x3", 64)])
+def test_sysq_block_sizes(qt, prec, b):
+    rng = np.random.default_rng(60 + b)
+    nb = 40 if b < 64 else 18
+    U = _sym_upper(rng, nb, 0.08, b)
+    S = symmetric_from_upper(U)
+    full, st = oracle.multiply(S, S, 2 * b)
+    absfull, _ = oracle.multiply(S, S, 2 * b, use_abs=True)
+    C = qt.sysq(qt.from_blockmatrix(U, 2 * b), prec)
+    kmax = int(np.bincount(S.I, minlength=nb).max())
+    tol = {"f64": 1e-12, "f32": (kmax * b + 2) * 2.0 ** -24,
+           "bf16x3": 3 * 2.0 ** -16 + (3 * b + 4) * 2.0 ** -24}[prec]
+    _check(_blocks(C, U.n_rows, U.n_cols, b), upper_blocks(full), upper_blocks(absfull), tol)
+
+
+def test_sysq_of_fp32_values_and_no_value_copy(qt):
+    """The symmetric operand is structure only: its blocks are read from the
+    triangle's own values (transposed for the mirrored ones), so the first
+    qt_sysq of a handle obtains a few bytes per block, not a copy of the
+    values; and an fp32 triangle (an fp32 multiply's result) works too."""
+    import paper_1501_07800_amd as q
+    rng = np.random.default_rng(61)
+    b = 32
+    U = _sym_upper(rng, 48, 0.08, b)
+    h = qt.from_blockmatrix(U, 4 * b)
+    qt.prepare(h, "f64")
+    seen = []
+    base = q.TorchAllocator()
+
+    def alloc(n, st):
+        seen.append(n)
+        return base.alloc(n, st)
+    q.set_allocator(alloc, base.free)
+    try:
+        C = qt.sysq(h, "f64")
+    finally:
+        if q.ALLOCATOR is not None:
+            q.set_allocator(q.ALLOCATOR.alloc, q.ALLOCATOR.free)
+        else:
+            q.use_hip_pool()
+    value_bytes = U.nnz * b * b * 8
+    c_bytes = C.nblocks * b * b * 8
+    # everything obtained beyond C's values: structure, scratch and product lists
+    assert sum(seen) - c_bytes < 0.25 * value_bytes, (sum(seen), c_bytes, value_bytes)
+    # an fp32 upper triangle: (U32)^2 through the f32 path
+    Id = identity(48, b)
+    h32 = qt.multiply(h, qt.from_blockmatrix(Id, 4 * b), "f32")     # U with fp32 values
+    C32 = qt.sysq(h32, "f32")
+    S = symmetric_from_upper(U)
+    full, _ = oracle.multiply(S, S, 4 * b)
+    absfull, _ = oracle.multiply(S, S, 4 * b, use_abs=True)
+    kmax = int(np.bincount(S.I, minlength=48).max())
+    _check(_blocks(C32, U.n_rows, U.n_cols, b), upper_blocks(full), upper_blocks(absfull),
+           (kmax * b + 4) * 2.0 ** -24)
 
 
 def test_sysq_decay_and_errors(qt):

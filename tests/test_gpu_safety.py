@@ -1,0 +1,206 @@
+"""Failure and concurrency contracts of the C ABI, on the GPU.
+
+- Every entry point that allocates returns QT_ERR_OOM with its output handle
+  NULL when the installed allocator fails, at whichever allocation it fails,
+  and gives back every buffer it obtained during the call.
+- One handle may be an input of several calls at once, from several threads
+  and streams: derived operand forms made on one stream are waited for on
+  another, and a result's count histograms are built once.
+"""
+import ctypes
+import threading
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as wl
+from tests._util import compare, random_pattern
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def qt():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1501_07800_amd as q
+    return q
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+class Injecting:
+    """Allocator over torch's that fails its allocation number fail_at (and
+    every later one) and tracks which of its buffers are still out."""
+
+    def __init__(self, base, fail_at=None):
+        self.base, self.fail_at, self.count = base, fail_at, 0
+        self.out = set()
+
+    def alloc(self, n, stream):
+        k = self.count
+        self.count += 1
+        if self.fail_at is not None and k >= self.fail_at:
+            return None
+        p = self.base.alloc(n, stream)
+        if p:
+            self.out.add(p)
+        return p
+
+    def free(self, p, stream):
+        self.out.discard(p)
+        self.base.free(p, stream)
+
+
+def _restore(qt):
+    if qt.ALLOCATOR is not None:
+        qt.set_allocator(qt.ALLOCATOR.alloc, qt.ALLOCATOR.free)
+    else:
+        qt.use_hip_pool()
+
+
+def _operations(qt, A, B, U):
+    """(name, call) pairs; call(out) runs one entry point through the raw C ABI
+    with output handle `out` and returns its status."""
+    L = qt.lib
+    s = None
+    nI, nJ, nV = (np.ascontiguousarray(A.I), np.ascontiguousarray(A.J), np.ascontiguousarray(A.V))
+    hA = qt.from_blockmatrix(A, 128)
+    hB = qt.from_blockmatrix(B, 128)
+    hU = qt.from_blockmatrix(U, 128)
+    for p in ("f64", "f32", "bf16x3"):
+        qt.prepare(hA, p)
+        qt.prepare(hB, p)
+    qt.sysq(hU).free()              # the symmetric operand form is made and kept with hU
+    plan_in = (ctypes.c_void_p * 2)(hA.handle.value, hA.handle.value)
+    plan_in2 = (ctypes.c_void_p * 2)(hB.handle.value, hA.handle.value)
+    keep = (hA, hB, hU, nI, nJ, nV, plan_in, plan_in2)
+    P = qt.PREC
+    ops = [
+        ("build", lambda o: L.qt_build(A.n_rows, A.n_cols, A.b, 128, A.nnz, nI.ctypes.data, nJ.ctypes.data,
+                                       nV.ctypes.data, qt.MEM_HOST, s, ctypes.byref(o))),
+        ("multiply f64", lambda o: L.qt_multiply(hA.handle, hB.handle, P["f64"], s, ctypes.byref(o))),
+        ("multiply f32", lambda o: L.qt_multiply(hA.handle, hB.handle, P["f32"], s, ctypes.byref(o))),
+        ("multiply bf16x3", lambda o: L.qt_multiply(hA.handle, hB.handle, P["bf16x3"], s, ctypes.byref(o))),
+        ("multiply_ex A^T B^T", lambda o: L.qt_multiply_ex(hA.handle, hB.handle, 3, P["f64"], s, ctypes.byref(o))),
+        ("add", lambda o: L.qt_add(hA.handle, hB.handle, s, ctypes.byref(o))),
+        ("truncate", lambda o: L.qt_truncate(hA.handle, 1.0, s, ctypes.byref(o), None, None)),
+        ("sysq", lambda o: L.qt_sysq(hU.handle, P["f64"], s, ctypes.byref(o))),
+        ("plan_create", lambda o: L.qt_plan_create(2, plan_in, plan_in2, P["f32"], s, ctypes.byref(o))),
+    ]
+    return ops, keep
+
+
+def _release(qt, name, o):
+    if o.value:
+        if name == "plan_create":
+            qt.lib.qt_plan_destroy(o)
+        else:
+            qt.lib.qt_free(o)
+
+
+def test_allocation_failure_returns_oom_and_leaks_nothing(qt):
+    import torch
+    rng = np.random.default_rng(40)
+    A = random_pattern(rng, 24, 24, 0.15, 32)
+    B = random_pattern(rng, 24, 24, 0.15, 32)
+    U = wl.BlockMatrix(A.n_rows, A.n_cols, 32, A.I[A.I <= A.J], A.J[A.I <= A.J],
+                       np.ascontiguousarray(A.V[A.I <= A.J]))
+    ops, keep = _operations(qt, A, B, U)
+    base = qt.TorchAllocator()
+    try:
+        for name, call in ops:
+            counter = Injecting(base)
+            qt.set_allocator(counter.alloc, counter.free)
+            o = ctypes.c_void_p()
+            assert call(o) == qt.QT_OK, (name, qt.lib.qt_last_error())
+            _release(qt, name, o)
+            torch.cuda.synchronize()
+            total = counter.count
+            assert total > 0, name
+            assert not counter.out, (name, "a successful call kept buffers after its result was freed")
+            _say(name, "allocations", total)
+            for k in range(total):
+                inj = Injecting(base, fail_at=k)
+                qt.set_allocator(inj.alloc, inj.free)
+                o = ctypes.c_void_p(12345)
+                rc = call(o)
+                assert rc == qt.QT_ERR_OOM, (name, k, rc, qt.lib.qt_last_error())
+                assert o.value is None, (name, k)
+                assert not inj.out, (name, k, len(inj.out))
+            torch.cuda.synchronize()
+    finally:
+        _restore(qt)
+    del keep
+
+
+def test_two_threads_share_result_handle(qt):
+    """Two threads, each on its own stream, multiply the same result handle C
+    (whose histograms neither has built yet) by A, five times each."""
+    import torch
+    rng = np.random.default_rng(41)
+    A = random_pattern(rng, 48, 48, 0.06, 32)
+    refC, _ = oracle.multiply(A, A, 128)
+    refD, _ = oracle.multiply(refC, A, 128)
+    absA = wl.BlockMatrix(A.n_rows, A.n_cols, 32, A.I, A.J, np.abs(A.V))
+    absC, _ = oracle.multiply(absA, absA, 128)
+    absD, _ = oracle.multiply(absC, absA, 128)
+    hA = qt.from_blockmatrix(A, 128)
+    hC = qt.multiply(hA, hA)
+    torch.cuda.synchronize()
+    got, errors = [], []
+
+    def work():
+        try:
+            st = torch.cuda.Stream()
+            for _ in range(5):
+                hD = qt.multiply(hC, hA, "f64", stream=st)
+                I, J, V = hD.to_blocks(stream=st)
+                got.append(wl.BlockMatrix(A.n_rows, A.n_cols, 32, I, J, V))
+                hD.free()
+        except Exception as e:      # reported below, in the test's thread
+            errors.append(e)
+
+    ts = [threading.Thread(target=work) for _ in range(2)]
+    for t in ts:
+        t.start()
+    for t in ts:
+        t.join()
+    assert not errors, errors
+    assert len(got) == 10
+    for D in got:
+        same, _, _, e_cw = compare(refD, D, absD)
+        assert same and e_cw <= 4e-12
+
+
+@pytest.mark.parametrize("prec", ["f32", "bf16x3"])
+def test_operand_form_made_on_a_busy_stream(qt, prec):
+    """A fresh handle's reduced-precision form is first made on stream s1,
+    which is still busy; a multiply of the same handle on stream s2 must wait
+    for that form, not read it half made."""
+    import torch
+    rng = np.random.default_rng(42)
+    A = random_pattern(rng, 64, 64, 0.08, 32)
+    ref, _ = oracle.multiply(A, A, 128)
+    absAB, _ = oracle.multiply(A, A, 128, use_abs=True)
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    hA = qt.from_blockmatrix(A, 128)
+    torch.cuda.synchronize()
+    x = torch.randn(4096, 4096, device="cuda")
+    with torch.cuda.stream(s1):
+        for _ in range(8):
+            x = x @ x               # keeps s1 busy for a while
+            x /= x.norm()
+    C1 = qt.multiply(hA, hA, prec, stream=s1)   # makes the form on s1, behind the busy work
+    C2 = qt.multiply(hA, hA, prec, stream=s2)   # same handle, other stream, right away
+    I, J, V = C2.to_blocks("f64", stream=s2)
+    torch.cuda.synchronize()
+    got = wl.BlockMatrix(A.n_rows, A.n_cols, 32, I, J, V)
+    same, _, e_f, e_cw = compare(ref, got, absAB)
+    assert same
+    assert e_cw <= 1e-4, e_cw          # far above either path's bound; unconverted values give O(1)
+    del C1
