@@ -200,6 +200,26 @@ qt_status qt_to_blocks(const qt_matrix* M, int32_t* I, int32_t* J, void* values,
                        qt_prec out_type, qt_mem where, void* stream);
 
 /*
+ * qt_to_blocks for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid allocation):
+ * the same copy-out into device arrays I, J, values (values may be NULL),
+ * bitwise the same result, but every buffer it needs beyond the caller's
+ * arrays is a fixed scratch array of the library, 12 MiB per device, held
+ * until the process ends. It calls no allocator (neither HIP's nor one set
+ * with qt_set_allocator) and does not synchronize; the copy is queued on
+ * `stream`. All calls on one device share that scratch and its contents
+ * stay from call to call: calls on one device that overlap in time (on two
+ * streams, or from two threads without ordering) race and give wrong
+ * results; order them on one stream. The matrix must live on the current
+ * device. Errors: ARG (NULL matrix or array, matrix on another device),
+ * UNSUPPORTED (out_type QT_BF16X3, more than QT_NOALLOC_MAX_BLOCKS blocks),
+ * DEVICE.
+ */
+#define QT_NOALLOC_MAX_BLOCKS (1 << 20)
+qt_status qt_to_blocks_noalloc(const qt_matrix* M, int32_t* I, int32_t* J, void* values, qt_prec out_type,
+                               void* stream);
+
+/*
  * Fetch chosen blocks: for t < count, block (I[t], J[t]) is looked up by
  * binary search over the matrix's Morton-ordered block keys and copied to
  * values + t*b*b (as out_type, like qt_to_blocks); found[t] is 1, or 0 with

@@ -60,6 +60,8 @@ def _load():
     lib.qt_info.argtypes = [vp, i64p, i64p, i32p, i32p, i64p, ctypes.POINTER(ctypes.c_int)]
     lib.qt_to_blocks.restype = ctypes.c_int
     lib.qt_to_blocks.argtypes = [vp, vp, vp, vp, ctypes.c_int, ctypes.c_int, vp]
+    lib.qt_to_blocks_noalloc.restype = ctypes.c_int
+    lib.qt_to_blocks_noalloc.argtypes = [vp, vp, vp, vp, ctypes.c_int, vp]
     lib.qt_get_blocks.restype = ctypes.c_int
     lib.qt_get_blocks.argtypes = [vp, i64, vp, vp, vp, vp, ctypes.c_int, ctypes.c_int, vp]
     lib.qt_stats.restype = ctypes.c_int
@@ -210,10 +212,11 @@ def _default_allocator():
     return use_torch_allocator()
 
 
-EXPORTS = ("qt_build", "qt_multiply", "qt_multiply_ex", "qt_add", "qt_truncate", "qt_sysq", "qt_info", "qt_to_blocks", "qt_get_blocks", "qt_stats", "qt_levels", "qt_prepare", "qt_free",
+EXPORTS = ("qt_build", "qt_multiply", "qt_multiply_ex", "qt_add", "qt_truncate", "qt_sysq", "qt_info", "qt_to_blocks", "qt_to_blocks_noalloc", "qt_get_blocks", "qt_stats", "qt_levels", "qt_prepare", "qt_free",
            "qt_plan_create", "qt_plan_execute", "qt_plan_tune", "qt_plan_set_schedule", "qt_plan_result", "qt_plan_info",
            "qt_plan_destroy", "qt_tune_leaf", "qt_profile", "qt_profile_read", "qt_probe_mfma", "qt_last_error", "qt_version",
            "qt_set_allocator")
+NOALLOC_MAX_BLOCKS = 1 << 20   # QT_NOALLOC_MAX_BLOCKS
 PLAN_SCHEDULES = ("flat", "persistent-1", "persistent-4", "persistent-16")
 
 
@@ -318,6 +321,13 @@ class Matrix:
         """Copy out into caller-provided torch device tensors (no host sync)."""
         _check(lib.qt_to_blocks(self._h, I.data_ptr(), J.data_ptr(), V.data_ptr(), PREC[dtype], MEM_DEVICE,
                                 _stream_ptr(stream)))
+
+    def to_blocks_noalloc(self, I, J, V, dtype: str = "f64", stream=None):
+        """qt_to_blocks_noalloc: the same copy-out into caller-provided torch
+        device tensors, using the library's fixed scratch instead of any
+        allocation (V may be None for the pattern only)."""
+        _check(lib.qt_to_blocks_noalloc(self._h, I.data_ptr(), J.data_ptr(), None if V is None else V.data_ptr(),
+                                        PREC[dtype], _stream_ptr(stream)))
 
 
 def build(n_rows: int, n_cols: int, b: int, leaf: int, I, J, V, stream=None) -> Matrix:

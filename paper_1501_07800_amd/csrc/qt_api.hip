@@ -11,6 +11,7 @@ static thread_local std::string t_last_error;
 void set_last_error(const std::string& m) { t_last_error = m; }
 
 void to_blocks(const qt_matrix*, int32_t*, int32_t*, void*, qt_prec, qt_mem, hipStream_t);
+void to_blocks_noalloc(const qt_matrix*, int32_t*, int32_t*, void*, qt_prec, hipStream_t);
 void get_blocks(const qt_matrix*, int64_t, const int32_t*, const int32_t*, void*, int32_t*, qt_prec, qt_mem,
                 hipStream_t);
 qt_plan* plan_create(int32_t, const qt_matrix* const*, const qt_matrix* const*, qt_prec, hipStream_t);
@@ -237,6 +238,18 @@ qt_status qt_to_blocks(const qt_matrix* M, int32_t* I, int32_t* J, void* values,
     }
     QT_GUARD_BEGIN
     to_blocks(M, I, J, values, out_type, where, (hipStream_t)stream);
+    return QT_OK;
+    QT_GUARD_END
+}
+
+qt_status qt_to_blocks_noalloc(const qt_matrix* M, int32_t* I, int32_t* J, void* values, qt_prec out_type,
+                               void* stream) {
+    if (!M) {
+        set_last_error("NULL matrix");
+        return QT_ERR_ARG;
+    }
+    QT_GUARD_BEGIN
+    to_blocks_noalloc(M, I, J, values, out_type, (hipStream_t)stream);
     return QT_OK;
     QT_GUARD_END
 }

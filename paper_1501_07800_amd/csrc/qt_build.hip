@@ -664,6 +664,38 @@ void build_tree_levels(qt_matrix* M, hipStream_t s) {
 
 // ------------------------------------------------------------ copy out
 
+// Copy-out into device arrays I, J, values (values may be NULL): row-major
+// sort keys and the permutation go to rk / perm, which hold npow2 entries
+// each (npow2 = the next power of two >= M->nblocks, as the sort needs).
+static void rowmajor_copy(const qt_matrix* M, uint64_t* rk, int32_t* perm, int32_t* I, int32_t* J, void* values,
+                          qt_prec out_type, hipStream_t s) {
+    const int64_t n = M->nblocks;
+    const int bb = M->b * M->b;
+    const int64_t nbc = M->n_cols / M->b;
+    k_rowmajor_keys<<<grid_for(n), 256, 0, s>>>(M->bkey.p, n, nbc, rk, perm);
+    QT_LAUNCH("k_rowmajor_keys");
+    bitonic_sort(rk, perm, n, s);
+    k_coords<<<grid_for(n), 256, 0, s>>>(M->bkey.p, perm, n, I, J);
+    QT_LAUNCH("k_coords");
+    if (!values) return;   // pattern only
+    const unsigned g = block_grid(n);
+    if (M->vtype == QT_F64 && out_type == QT_F64)
+        k_gather_convert<double, double><<<g, 256, 0, s>>>(M->v64.p, perm, n, bb, (double*)values);
+    else if (M->vtype == QT_F64)
+        k_gather_convert<double, float><<<g, 256, 0, s>>>(M->v64.p, perm, n, bb, (float*)values);
+    else if (out_type == QT_F64)
+        k_gather_convert<float, double><<<g, 256, 0, s>>>(M->v32.p, perm, n, bb, (double*)values);
+    else
+        k_gather_convert<float, float><<<g, 256, 0, s>>>(M->v32.p, perm, n, bb, (float*)values);
+    QT_LAUNCH("k_gather_convert");
+}
+
+static int64_t pow2_at_least(int64_t n) {
+    int64_t p = 1;
+    while (p < n) p <<= 1;
+    return p;
+}
+
 void to_blocks(const qt_matrix* M, int32_t* I, int32_t* J, void* values, qt_prec out_type, qt_mem where,
                hipStream_t s) {
     if (out_type != QT_F64 && out_type != QT_F32) fail(QT_ERR_UNSUPPORTED, "output type must be F64 or F32");
@@ -672,14 +704,9 @@ void to_blocks(const qt_matrix* M, int32_t* I, int32_t* J, void* values, qt_prec
     if (n == 0) return;
     if (!I || !J) fail(QT_ERR_ARG, "NULL output array");
     const int bb = M->b * M->b;
-    const int64_t nbc = M->n_cols / M->b;
-    int64_t npow2 = 1;
-    while (npow2 < n) npow2 <<= 1;
+    const int64_t npow2 = pow2_at_least(n);
     DBuf<uint64_t> rk(npow2, s);
     DBuf<int32_t> perm(npow2, s);
-    k_rowmajor_keys<<<grid_for(n), 256, 0, s>>>(M->bkey.p, n, nbc, rk.p, perm.p);
-    QT_LAUNCH("k_rowmajor_keys");
-    bitonic_sort(rk.p, perm.p, n, s);
     const size_t vbytes = values ? (size_t)n * bb * (out_type == QT_F64 ? sizeof(double) : sizeof(float)) : 0;
     DBuf<int32_t> tI, tJ;
     DBuf<char> tV;
@@ -694,26 +721,64 @@ void to_blocks(const qt_matrix* M, int32_t* I, int32_t* J, void* values, qt_prec
         oJ = tJ.p;
         oV = values ? (void*)tV.p : nullptr;
     }
-    k_coords<<<grid_for(n), 256, 0, s>>>(M->bkey.p, perm.p, n, oI, oJ);
-    QT_LAUNCH("k_coords");
-    const unsigned g = block_grid(n);
-    if (!values) {
-        // pattern only
-    } else if (M->vtype == QT_F64 && out_type == QT_F64)
-        k_gather_convert<double, double><<<g, 256, 0, s>>>(M->v64.p, perm.p, n, bb, (double*)oV);
-    else if (M->vtype == QT_F64)
-        k_gather_convert<double, float><<<g, 256, 0, s>>>(M->v64.p, perm.p, n, bb, (float*)oV);
-    else if (out_type == QT_F64)
-        k_gather_convert<float, double><<<g, 256, 0, s>>>(M->v32.p, perm.p, n, bb, (double*)oV);
-    else
-        k_gather_convert<float, float><<<g, 256, 0, s>>>(M->v32.p, perm.p, n, bb, (float*)oV);
-    if (values) QT_LAUNCH("k_gather_convert");
+    rowmajor_copy(M, rk.p, perm.p, oI, oJ, oV, out_type, s);
     if (where == QT_MEM_HOST) {
         QT_HIP(hipMemcpyAsync(I, oI, n * sizeof(int32_t), hipMemcpyDeviceToHost, s));
         QT_HIP(hipMemcpyAsync(J, oJ, n * sizeof(int32_t), hipMemcpyDeviceToHost, s));
         if (values) QT_HIP(hipMemcpyAsync(values, oV, vbytes, hipMemcpyDeviceToHost, s));
         QT_HIP(hipStreamSynchronize(s));
     }
+}
+
+// -------------------------------------------- copy-out without allocation
+
+// Scratch of the allocation-free copy-out: the row-major sort keys (8 bytes
+// per entry) followed by the permutation (4 bytes per entry) of up to
+// QT_NOALLOC_MAX_BLOCKS blocks, 12 MiB, one copy per device for the life of
+// the process. Host code never passes `scratch` itself (on the host it names
+// a stand-in, not device memory): it takes the array's device address once
+// per device with hipGetSymbolAddress and uses that address only.
+constexpr int64_t kNoAllocEntries = QT_NOALLOC_MAX_BLOCKS;
+static __device__ __align__(256) uint64_t scratch[kNoAllocEntries + kNoAllocEntries / 2];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void* g_scratch_addr[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device (taken on the first call
+// made with that device current).
+static void* scratch_address(int dev) {
+    if (dev < 0 || dev >= kMaxDevices) fail(QT_ERR_UNSUPPORTED, "device ordinal beyond the library's table");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_addr[dev]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            (void)hipGetLastError();
+            fail(QT_ERR_DEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+        }
+        g_scratch_addr[dev] = p;
+    }
+    return g_scratch_addr[dev];
+}
+
+void to_blocks_noalloc(const qt_matrix* M, int32_t* I, int32_t* J, void* values, qt_prec out_type, hipStream_t s) {
+    if (out_type != QT_F64 && out_type != QT_F32) fail(QT_ERR_UNSUPPORTED, "output type must be F64 or F32");
+    const int64_t n = M->nblocks;
+    if (n > QT_NOALLOC_MAX_BLOCKS)
+        fail(QT_ERR_UNSUPPORTED, "matrix has " + std::to_string(n) + " blocks; the allocation-free copy-out takes at most " +
+                                     std::to_string((long long)QT_NOALLOC_MAX_BLOCKS));
+    int dev = 0;
+    QT_HIP(hipGetDevice(&dev));
+    if (dev != M->device) fail(QT_ERR_ARG, "the matrix lives on another device than the current one");
+    uint64_t* rk = static_cast<uint64_t*>(scratch_address(dev));
+    if (n == 0) return;
+    if (!I || !J) fail(QT_ERR_ARG, "NULL output array");
+    int32_t* perm = reinterpret_cast<int32_t*>(rk + kNoAllocEntries);
+    // rk and perm are written in full (entries < n by the key kernel, the
+    // rest up to the power of two by the sort's padding) before any read, so
+    // nothing left by an earlier call is seen and nothing needs clearing.
+    rowmajor_copy(M, rk, perm, I, J, values, out_type, s);
 }
 
 // The full symmetric matrix S from its upper block triangle A, as structure
