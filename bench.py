@@ -28,6 +28,38 @@ METRIC = "block-product TFLOP/s and MFMA-peak fraction, split vs FP64 path at st
 PEAK = {"f64": 78.6, "f32": 157.3, "bf16x3": 2516.6}   # dense MFMA TFLOP/s, MI355X
 HBM_PEAK_GBS = 8000.0                                   # HBM3E, MI355X
 
+# Error bounds each path must meet against the fp64 oracle, normwise (e_F =
+# ||C - C_ref||_F / ||C_ref||_F) and by the largest entry error over max |C_ref|:
+# fp64 is held to 1e-12; fp32 and the split-bf16 path to their a-priori bounds
+# per block product (inputs rounded to fp32, products summed in fp32: about
+# (k b + 2) 2^-24 for fp32 with k products per C block; 3 2^-16 + (b + 2) 2^-24
+# for split bf16) with room for the longest product lists of the workloads.
+TOLERANCE = {"f64": {"e_F": 1e-12, "e_max_rel": 1e-12},
+             "f32": {"e_F": 1e-5, "e_max_rel": 1e-4},
+             "bf16x3": {"e_F": 1e-4, "e_max_rel": 1e-3}}
+
+
+def check_path(entry: dict, prec: str) -> list:
+    """Failed checks of one path's result (pattern, then the error bounds)."""
+    if entry.get("pattern_matches_oracle") is False:
+        return [f"{prec}: C block pattern differs from the oracle"]
+    bad = []
+    for key, lim in TOLERANCE[prec].items():
+        if key in entry and not entry[key] <= lim:
+            bad.append(f"{prec}: {key} = {entry[key]:.3g} above {lim:g}")
+    return bad
+
+
+def cpu_model() -> str:
+    """The host CPU's model name (first 'model name' line of /proc/cpuinfo)."""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
@@ -68,7 +100,28 @@ def measured_traffic(workload: str, prec: str):
 
 
 COPY_BYTES = 1 << 31   # plain device copy used to calibrate the traffic counters
-CPU_SAMPLE_FLOPS = 1.0e11   # block-product work the CPU oracle is given at most (10-20 s)
+CPU_SAMPLE_FLOPS = 1.0e11   # block-product work the CPU oracle is given at most (a few s per run)
+CPU_SAMPLE_FLOPS_1T = 8.0e9  # the same for the one-thread runs
+
+
+def row_sample(wl, A, P, max_flops, name):
+    """The C block rows 0 .. R-1 of C = A*A as the oracle's sample: A's first
+    R block rows (times A), R the smallest that holds max_flops of block
+    products, or all of A when the whole product is within max_flops.
+    Returns (A's rows, their block products, R or None, description)."""
+    import numpy as np
+    b = A.b
+    if 2.0 * b ** 3 * P <= max_flops:
+        return A, P, None, f"the full {name} workload, C = A*A"
+    rowcnt = np.bincount(A.I, minlength=A.nb_rows).astype(np.float64)
+    p_row = np.bincount(A.I, weights=rowcnt[A.J], minlength=A.nb_rows)
+    R = int(np.searchsorted(np.cumsum(p_row), max_flops / (2.0 * b ** 3))) + 1
+    R = min(R, A.nb_rows)
+    keep = A.I < R
+    Ao = wl.BlockMatrix(A.n_rows, A.n_cols, b, A.I[keep], A.J[keep], A.V[keep])
+    P_o = int(p_row[:R].sum())
+    return Ao, P_o, R, (f"C block rows 0..{R - 1} of {A.nb_rows} of {name} (A's first {R} block rows "
+                        f"times A: {P_o} of {P} block products)")
 
 
 def calibrate_copy():
@@ -378,6 +431,8 @@ def main():
     ap.add_argument("--prec", default="f64", choices=["f64", "f32", "bf16x3"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-paths", action="store_true", help="time only --prec")
+    ap.add_argument("--no-hbm-config", action="store_true",
+                    help="leave out the random65536 fp64/fp32 entry of the default run")
     ap.add_argument("--ops", action="store_true",
                     help="time the other operations (transposes, symmetric square, add, truncate) on --workload")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -501,28 +556,33 @@ def main():
     if not args.no_cpu_baseline:
         import oracle
         # the whole workload when the oracle finishes it in seconds, else the
-        # C block rows 0 .. R-1 (A's first R block rows times A), with R the
-        # smallest that holds CPU_SAMPLE_FLOPS of block products
-        Ao, P_o, what = A, P, f"the full {args.workload} workload, C = A*A, one run"
-        if flops > CPU_SAMPLE_FLOPS:
-            rowcnt = np.bincount(A.I, minlength=A.nb_rows).astype(np.float64)
-            p_row = np.bincount(A.I, weights=rowcnt[A.J], minlength=A.nb_rows)
-            R = int(np.searchsorted(np.cumsum(p_row), CPU_SAMPLE_FLOPS / (2.0 * b ** 3))) + 1
-            R = min(R, A.nb_rows)
-            keep = A.I < R
-            Ao = wl.BlockMatrix(A.n_rows, A.n_cols, b, A.I[keep], A.J[keep], A.V[keep])
-            P_o = int(p_row[:R].sum())
-            sample_rows = R
-            what = (f"C block rows 0..{R - 1} of {A.nb_rows} of {args.workload} (A's first {R} block rows "
-                    f"times A: {P_o} of {P} block products), one run")
-        log(f"bench: CPU oracle (fp64, OpenMP) on {what}")
-        t0 = time.perf_counter()
-        ref, st = oracle.multiply(Ao, A, leaf)
-        t1 = time.perf_counter()
-        assert st.block_products == P_o
-        cpu = {"value": 2.0 * b ** 3 * P_o / (t1 - t0) / 1e12, "unit": "TFLOP/s", "cores": oracle.threads(),
-               "kind": "oracle", "seconds": t1 - t0, "sample": what}
-        log(f"bench: oracle {t1 - t0:.1f} s on {cpu['cores']} threads")
+        # C block rows 0 .. R-1 (A's first R block rows times A)
+        Ao, P_o, sample_rows, what = row_sample(wl, A, P, CPU_SAMPLE_FLOPS, args.workload)
+        log(f"bench: CPU oracle (fp64, OpenMP) on {what}, 3 runs")
+        secs = []
+        for _ in range(3):
+            t0 = time.perf_counter()
+            ref, st = oracle.multiply(Ao, A, leaf)
+            secs.append(time.perf_counter() - t0)
+            assert st.block_products == P_o
+        med = float(np.median(secs))
+        cpu = {"value": 2.0 * b ** 3 * P_o / med / 1e12, "unit": "TFLOP/s", "cores": oracle.threads(),
+               "kind": "oracle", "seconds": med, "runs_s": secs, "statistic": "median of 3 runs",
+               "sample": what, "cpu_model": cpu_model(), "host_cpus": os.cpu_count()}
+        log(f"bench: oracle {med:.2f} s (median of 3) on {cpu['cores']} threads")
+        # one thread, on a smaller row sample (the same rows from the top)
+        A1, P_1, _, what1 = row_sample(wl, A, P, CPU_SAMPLE_FLOPS_1T, args.workload)
+        secs1 = []
+        for _ in range(3):
+            t0 = time.perf_counter()
+            _, st1 = oracle.multiply(A1, A, leaf, threads=1)
+            secs1.append(time.perf_counter() - t0)
+            assert st1.block_products == P_1
+        oracle.multiply(A1, A1, leaf, threads=cpu["cores"])   # back to the full thread count
+        med1 = float(np.median(secs1))
+        cpu["one_thread"] = {"value": 2.0 * b ** 3 * P_1 / med1 / 1e12, "unit": "TFLOP/s", "cores": 1,
+                             "seconds": med1, "runs_s": secs1, "statistic": "median of 3 runs", "sample": what1}
+        log(f"bench: oracle on one thread: {med1:.2f} s (median of 3) for {P_1} block products")
 
     paths = {}
     for prec, r in results.items():
@@ -556,6 +616,26 @@ def main():
             entry["mfma_utilisation"] = 3 * r["numeric_tflops"] / PEAK["bf16x3"]
         paths[prec] = entry
 
+    failed = [msg for prec, e in paths.items() for msg in check_path(e, prec)]
+
+    # the HBM-bound configuration (uniformly random blocks, 1 % fill) beside
+    # the headline: fp64 and fp32, each against the HBM roofline
+    hbm = None
+    if not args.no_paths and not args.no_hbm_config and args.workload != "random65536":
+        hbm = hbm_config_entry(qt, torch, wl, "random65536", args.steps, args.warmup)
+        failed += [msg for prec, e in hbm["paths"].items() for msg in check_path(e, prec)]
+
+    # the batched block GEMM's practical peak, shaped like the paper's Table 2
+    # (64000 uniform b x b products, one operand pair reused)
+    practical = None
+    if not args.no_paths:
+        practical = {"count": 64000, "what": "64000 products C_i = A B of b x b blocks through the numeric "
+                                              "kernels, A and B the same for all (TFLOP/s)"}
+        for prec in ("f64", "f32", "bf16x3"):
+            practical[prec] = {str(bs): qt.probe_batched(prec, bs, 64000) for bs in (16, 32, 64)
+                               if not (prec == "bf16x3" and bs == 16)}
+        log(f"bench: practical peak (TFLOP/s): {practical}")
+
     peak = PEAK[args.prec] if args.prec != "bf16x3" else PEAK["f32"]
     roof = roofline_bound(flops, alg_bytes, main_r["numeric_ms"], peak)
     roof.update({"traffic": measured_traffic(args.workload, args.prec),
@@ -584,8 +664,72 @@ def main():
             "ms": pcie_ms, "tflops": flops / (pcie_ms * 1e-3) / 1e12,
             "what": "qt_build from host block lists + qt_multiply + qt_to_blocks to host (PCIe both ways)"},
         "paths": paths,
+        "hbm_config": hbm,
+        "practical_peak": practical,
+        "checks": {"tolerance": TOLERANCE, "failed": failed,
+                   "what": "C block pattern equal to the oracle's; errors against the fp64 oracle within "
+                           "the tolerance of each path"},
     }
+    if failed:
+        # a result that fails its check is no measurement: no value, non-zero exit
+        out["value"] = None
+        print(json.dumps(out), flush=True)
+        log("bench: CHECK FAILED: " + "; ".join(failed))
+        sys.exit(1)
     print(json.dumps(out), flush=True)
+
+
+def hbm_config_entry(qt, torch, wl, name, steps, warmup, samples=64):
+    """Timed fp64 and fp32 multiplies of workload `name` (C = A*A), each with
+    its numeric kernel against the HBM roofline (A read once, C written once),
+    its C pattern checked against the boolean product of A's block pattern and
+    `samples` C blocks against the definition C(I,J) = sum_K A(I,K) A(K,J)."""
+    import numpy as np
+    import oracle
+    cfg = wl.CONFIGS[name]
+    log(f"bench: generating {name}")
+    A = wl.config(name)
+    b, leaf = A.b, cfg["leaf"]
+    hA = qt.from_blockmatrix(A, leaf)
+    ref_pos = oracle.pattern_by_definition(A, A)
+    rng = np.random.default_rng(11)
+    pick = np.sort(rng.choice(len(ref_pos), size=min(samples, len(ref_pos)), replace=False))
+    sI = (ref_pos[pick] // A.nb_cols).astype(np.int32)
+    sJ = (ref_pos[pick] % A.nb_cols).astype(np.int32)
+    index = oracle.make_index(A, A)
+    sref = np.stack([oracle.block_by_definition(A, A, i, j, index) for i, j in zip(sI, sJ)])
+    paths = {}
+    for prec in ("f64", "f32"):
+        qt.prepare(hA, prec)
+        log(f"bench: {name} {prec}: {warmup} warmup + {steps} timed steps")
+        dt, prof, C = timed_steps(qt, torch, hA, prec, steps, warmup)
+        P = C.stats()["products"]
+        flops = 2.0 * b ** 3 * P
+        num_ms = prof["numeric_ms"] / max(prof["calls"], 1)
+        esz = 4 if prec == "f32" else 8
+        alg = (A.nnz + C.nblocks) * b * b * esz
+        I, J = C.pattern()
+        pos = I.astype(np.int64) * A.nb_cols + J
+        entry = {"tflops": flops * steps / dt / 1e12, "ms_per_step": dt / steps * 1e3, "numeric_ms": num_ms,
+                 "numeric_tflops": flops / (num_ms * 1e-3) / 1e12, "block_products": P, "nnz_C": C.nblocks,
+                 "roofline": roofline_bound(flops, alg, num_ms, PEAK[prec]),
+                 "pattern_matches_oracle": bool(np.array_equal(pos, ref_pos))}
+        if entry["pattern_matches_oracle"]:
+            V, F = C.get_blocks(sI, sJ, "f64")
+            d = V - sref
+            entry["e_max"] = float(np.abs(d).max())
+            entry["e_max_rel"] = float(np.abs(d).max() / np.abs(sref).max())
+            entry["e_F"] = float(np.linalg.norm(d) / np.linalg.norm(sref))
+            entry["error_sample"] = f"{len(sI)} C blocks drawn uniformly, against the definition"
+        C.free()
+        log(f"bench: {name} {prec}: {entry['tflops']:.2f} TFLOP/s end to end, numeric {num_ms:.3f} ms = "
+            f"{entry['roofline']['achieved']:.0f} {entry['roofline']['unit']} ({entry['roofline']['frac']:.2f} "
+            f"of the {entry['roofline']['bound']} roof)")
+        paths[prec] = entry
+    paths["f32"]["speedup_vs_f64"] = paths["f32"]["tflops"] / paths["f64"]["tflops"]
+    hA.free()
+    return {"workload": name, "n": A.n_rows, "b": b, "leaf": leaf, "nnz_A": A.nnz, "op": "C = A*A",
+            "paths": paths}
 
 
 if __name__ == "__main__":

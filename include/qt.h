@@ -341,6 +341,17 @@ qt_status qt_profile_read(double* symbolic_ms, double* numeric_ms, int64_t* call
  * Synchronizes `stream`. Errors: ARG (NULL output, unknown precision), DEVICE. */
 qt_status qt_probe_mfma(qt_prec prec, void* stream, double* tflops);
 
+/* Practical peak of the batched block GEMM (Sec. 6.1, Table 2, which times
+ * 64000 products C_i = A B of b x b blocks, A and B the same for all): runs
+ * `count` such products through the multiply's own numeric kernels (one C
+ * block per product, the operands one block of A and one of B read by every
+ * product), ten launches after one warm-up, and returns 2 b^3 count / time
+ * in TFLOP/s in *tflops. count is at most 2^24; the C blocks (count b^2
+ * values) are allocated for the call. Synchronizes `stream`.
+ * Errors: ARG (NULL output, count out of range, unknown precision), SHAPE (b
+ * not 16, 32 or 64), UNSUPPORTED (BF16X3 at b = 16), OOM, DEVICE. */
+qt_status qt_probe_batched(qt_prec prec, int32_t block_size, int64_t count, void* stream, double* tflops);
+
 /* Text of the last error on this thread ("" if none). */
 const char* qt_last_error(void);
 

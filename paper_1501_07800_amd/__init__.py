@@ -96,6 +96,8 @@ def _load():
                                  i32, i32p]
     lib.qt_last_error.restype = ctypes.c_char_p
     lib.qt_last_error.argtypes = []
+    lib.qt_probe_batched.restype = ctypes.c_int
+    lib.qt_probe_batched.argtypes = [ctypes.c_int, i32, i64, ctypes.c_void_p, ctypes.POINTER(ctypes.c_double)]
     lib.qt_probe_mfma.restype = ctypes.c_int
     lib.qt_probe_mfma.argtypes = [ctypes.c_int, ctypes.c_void_p, ctypes.POINTER(ctypes.c_double)]
     lib.qt_version.restype = ctypes.c_char_p
@@ -214,7 +216,7 @@ def _default_allocator():
 
 EXPORTS = ("qt_build", "qt_multiply", "qt_multiply_ex", "qt_add", "qt_truncate", "qt_sysq", "qt_info", "qt_to_blocks", "qt_to_blocks_noalloc", "qt_get_blocks", "qt_stats", "qt_levels", "qt_prepare", "qt_free",
            "qt_plan_create", "qt_plan_execute", "qt_plan_tune", "qt_plan_set_schedule", "qt_plan_result", "qt_plan_info",
-           "qt_plan_destroy", "qt_tune_leaf", "qt_profile", "qt_profile_read", "qt_probe_mfma", "qt_last_error", "qt_version",
+           "qt_plan_destroy", "qt_tune_leaf", "qt_profile", "qt_profile_read", "qt_probe_mfma", "qt_probe_batched", "qt_last_error", "qt_version",
            "qt_set_allocator")
 NOALLOC_MAX_BLOCKS = 1 << 20   # QT_NOALLOC_MAX_BLOCKS
 PLAN_SCHEDULES = ("flat", "persistent-1", "persistent-4", "persistent-16")
@@ -491,6 +493,14 @@ def probe_mfma(prec: str = "f64", stream=None) -> float:
     """qt_probe_mfma: TFLOP/s of a register-only loop of the path's MFMA instruction."""
     out = ctypes.c_double()
     _check(lib.qt_probe_mfma(PREC[prec], _stream_ptr(stream), ctypes.byref(out)))
+    return out.value
+
+
+def probe_batched(prec: str = "f64", b: int = 32, count: int = 64000, stream=None) -> float:
+    """qt_probe_batched: TFLOP/s of `count` b x b block products C_i = A B
+    (one operand pair for all) through the numeric kernels."""
+    out = ctypes.c_double()
+    _check(lib.qt_probe_batched(PREC[prec], b, count, _stream_ptr(stream), ctypes.byref(out)))
     return out.value
 
 

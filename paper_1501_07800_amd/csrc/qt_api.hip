@@ -343,6 +343,18 @@ qt_status qt_profile_read(double* symbolic_ms, double* numeric_ms, int64_t* call
     QT_GUARD_END
 }
 
+qt_status qt_probe_batched(qt_prec prec, int32_t block_size, int64_t count, void* stream, double* tflops) {
+    if (!tflops) {
+        set_last_error("NULL output");
+        return QT_ERR_ARG;
+    }
+    *tflops = 0;
+    QT_GUARD_BEGIN
+    *tflops = probe_batched(prec, block_size, count, (hipStream_t)stream);
+    return QT_OK;
+    QT_GUARD_END
+}
+
 qt_status qt_probe_mfma(qt_prec prec, void* stream, double* tflops) {
     if (!tflops) {
         set_last_error("NULL output");

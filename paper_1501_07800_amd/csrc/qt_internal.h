@@ -251,6 +251,7 @@ struct NumericArgs {
 };
 void launch_numeric(const NumericArgs& a, hipStream_t s);
 double probe_mfma(qt_prec prec, hipStream_t s);   // TFLOP/s of a register-only MFMA loop
+double probe_batched(qt_prec prec, int b, int64_t count, hipStream_t s);   // TFLOP/s of count block products
 
 // One problem of a batch, as the batch kernels read it (device memory).
 struct BatchProblem {

@@ -4,6 +4,12 @@
 // fill every SIMD several times over. No memory traffic inside the loop, so
 // the rate it reaches is the ceiling the block GEMMs can approach, to be read
 // beside the published peak.
+//
+// Also the batched-GEMM benchmark of the paper's practical peak figures
+// (Sec. 6.1, Table 2): `count` independent block products C_i = A B, one
+// pair of b x b operands reused by all, each C_i its own block, run through
+// the multiply's own numeric kernels (one C block per product, as in a
+// multiply whose C blocks each have one block product).
 #include "qt_internal.h"
 
 namespace qt {
@@ -81,6 +87,95 @@ static double probe_kind(hipStream_t s) {
     (void)hipEventDestroy(e1);
     const double flops = ProbeOp<KIND>::flops * PROBE_CHAINS * (double)iters * wgs * 4.0;
     return flops / (best * 1e-3) / 1e12;
+}
+
+__global__ void k_probe_fill(double* v, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) v[i] = 0.5 + 1e-3 * (double)(i % 97);
+}
+__global__ void k_probe_fill32(float* v, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) v[i] = 0.5f + 1e-3f * (float)(i % 97);
+}
+__global__ void k_probe_fill16(uint16_t* v, int64_t n, uint16_t x) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) v[i] = x;
+}
+__global__ void k_probe_iota(int32_t* seg, int32_t* zeros, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i <= n) seg[i] = (int32_t)i;
+    if (i < n) zeros[i] = 0;
+}
+
+double probe_batched(qt_prec prec, int b, int64_t count, hipStream_t s) {
+    if (prec != QT_F64 && prec != QT_F32 && prec != QT_BF16X3) fail(QT_ERR_ARG, "unknown precision");
+    if (b != 16 && b != 32 && b != 64) fail(QT_ERR_SHAPE, "block size must be 16, 32 or 64");
+    if (prec == QT_BF16X3 && b == 16) fail(QT_ERR_UNSUPPORTED, "split-bf16 path needs b = 32 or 64");
+    if (count < 1 || count > (int64_t(1) << 24)) fail(QT_ERR_ARG, "count must be in 1 .. 2^24");
+    const int64_t bb = (int64_t)b * b;
+    const unsigned T = 256;
+    auto grid = [&](int64_t n) { return (unsigned)((n + T - 1) / T); };
+    DBuf<int32_t> seg(count + 1, s), zero(count, s);
+    k_probe_iota<<<grid(count + 1), T, 0, s>>>(seg.p, zero.p, count);
+    QT_LAUNCH("k_probe_iota");
+    NumericArgs na{};
+    na.b = b;
+    na.prec = prec;
+    na.prodA = zero.p;   // every product reads operand block 0 of A and of B
+    na.prodB = zero.p;
+    na.seg = seg.p;
+    na.nseg = (int32_t)count;
+    DBuf<double> a64, b64, c64;
+    DBuf<float> a32, b32, c32;
+    DBuf<uint16_t> split;
+    if (prec == QT_F32) {
+        a32.alloc(bb, s);
+        b32.alloc(bb, s);
+        c32.alloc(count * bb, s);
+        k_probe_fill32<<<grid(bb), T, 0, s>>>(a32.p, bb);
+        k_probe_fill32<<<grid(bb), T, 0, s>>>(b32.p, bb);
+        QT_LAUNCH("k_probe_fill32");
+        na.A = a32.p;
+        na.B = b32.p;
+        na.C = c32.p;
+    } else {
+        c64.alloc(count * bb, s);
+        na.C = c64.p;
+        if (prec == QT_F64) {
+            a64.alloc(bb, s);
+            b64.alloc(bb, s);
+            k_probe_fill<<<grid(bb), T, 0, s>>>(a64.p, bb);
+            k_probe_fill<<<grid(bb), T, 0, s>>>(b64.p, bb);
+            QT_LAUNCH("k_probe_fill");
+            na.A = a64.p;
+            na.B = b64.p;
+        } else {
+            // hi parts 0.5 (bf16 0x3f00), lo parts 0.25 (0x3e80): the operands' values
+            // do not change the MFMA time
+            split.alloc(4 * bb, s);
+            k_probe_fill16<<<grid(2 * bb), T, 0, s>>>(split.p, 2 * bb, (uint16_t)0x3f00);
+            k_probe_fill16<<<grid(2 * bb), T, 0, s>>>(split.p + 2 * bb, 2 * bb, (uint16_t)0x3e80);
+            QT_LAUNCH("k_probe_fill16");
+            na.Ahi = split.p;
+            na.Bhi_t = split.p + bb;
+            na.Alo = split.p + 2 * bb;
+            na.Blo_t = split.p + 3 * bb;
+        }
+    }
+    hipEvent_t e0, e1;
+    timing_event(&e0);
+    timing_event(&e1);
+    constexpr int kReps = 10;
+    launch_numeric(na, s);   // warm-up
+    QT_HIP(hipEventRecord(e0, s));
+    for (int r = 0; r < kReps; ++r) launch_numeric(na, s);
+    QT_HIP(hipEventRecord(e1, s));
+    QT_HIP(hipEventSynchronize(e1));
+    float ms = 0;
+    QT_HIP(hipEventElapsedTime(&ms, e0, e1));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return 2.0 * (double)bb * b * (double)count * kReps / (ms * 1e-3) / 1e12;
 }
 
 double probe_mfma(qt_prec prec, hipStream_t s) {

@@ -47,6 +47,7 @@ def test_null_handles_rejected():
     assert qt.lib.qt_build(0, 0, 32, 32, 0, None, None, None, 0, None, None) == qt.QT_ERR_ARG
     assert qt.lib.qt_probe_mfma(0, None, None) == qt.QT_ERR_ARG
     assert qt.lib.qt_to_blocks_noalloc(None, None, None, None, 0, None) == qt.QT_ERR_ARG
+    assert qt.lib.qt_probe_batched(0, 32, 64000, None, None) == qt.QT_ERR_ARG
     qt.lib.qt_free(None)
 
 

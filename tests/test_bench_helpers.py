@@ -60,3 +60,35 @@ def test_more_than_one_gpu_is_refused():
                        text=True, timeout=120)
     assert r.returncode == 2
     assert "one GPU" in r.stderr
+
+
+def test_check_path_fails_on_pattern_and_bounds():
+    ok = {"pattern_matches_oracle": True, "e_F": 1e-15, "e_max_rel": 4e-15}
+    assert bench.check_path(ok, "f64") == []
+    assert bench.check_path({"pattern_matches_oracle": False}, "f64")
+    assert bench.check_path(dict(ok, e_F=2e-12), "f64")
+    assert bench.check_path(dict(ok, e_max_rel=float("nan")), "f64")     # NaN never passes
+    # the fp32 path is held to its own, looser bound
+    assert bench.check_path(dict(ok, e_F=4e-7, e_max_rel=2e-6), "f32") == []
+    assert bench.check_path(dict(ok, e_F=4e-5), "f32")
+    assert bench.check_path(dict(ok, e_F=8e-7, e_max_rel=2e-6), "bf16x3") == []
+
+
+def test_row_sample_takes_leading_block_rows():
+    import numpy as np
+    import workloads as wl
+    rng = np.random.default_rng(3)
+    n = 16
+    pos = np.sort(rng.choice(n * n, size=60, replace=False))
+    I, J = (pos // n).astype(np.int32), (pos % n).astype(np.int32)
+    A = wl.BlockMatrix(n * 4, n * 4, 4, I, J, rng.standard_normal((60, 4, 4)))
+    rowcnt = np.bincount(I, minlength=n)
+    P = int(sum(rowcnt[j] for j in J))
+    full = bench.row_sample(wl, A, P, 1e18, "t")
+    assert full[0] is A and full[1] == P and full[2] is None
+    flops_half = 2.0 * 4 ** 3 * P / 2
+    Ao, P_o, R, _ = bench.row_sample(wl, A, P, flops_half, "t")
+    assert (Ao.I < R).all() and Ao.nnz == int((I < R).sum())
+    # block products of the sampled rows: sum over their blocks (i, k) of the blocks in row k
+    assert P_o == int(sum(rowcnt[k] for i, k in zip(I, J) if i < R))
+    assert 2.0 * 4 ** 3 * P_o >= flops_half

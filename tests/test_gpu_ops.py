@@ -310,3 +310,24 @@ def test_probe_mfma_rates(qt):
     assert 10.0 < f64 < 80.0
     assert 20.0 < f32 < 160.0
     assert 200.0 < bf < 2600.0
+
+
+@pytest.mark.parametrize("prec,b", [("f64", 16), ("f64", 32), ("f64", 64), ("f32", 16), ("f32", 32), ("f32", 64),
+                                    ("bf16x3", 32), ("bf16x3", 64)])
+def test_probe_batched_rates(qt, prec, b):
+    """The batched-GEMM practical peak (64000 uniform products) runs through
+    the numeric kernels at a rate below the published MFMA peak."""
+    peak = {"f64": 78.6, "f32": 157.3, "bf16x3": 157.3}[prec]
+    tf = qt.probe_batched(prec, b, 64000)
+    print("batched", prec, b, tf, flush=True)
+    assert 0.5 < tf <= 1.05 * peak
+
+
+def test_probe_batched_errors(qt):
+    import ctypes
+    out = ctypes.c_double()
+    L = qt.lib
+    assert L.qt_probe_batched(0, 48, 100, None, ctypes.byref(out)) == qt.QT_ERR_SHAPE
+    assert L.qt_probe_batched(0, 32, 0, None, ctypes.byref(out)) == qt.QT_ERR_ARG
+    assert L.qt_probe_batched(2, 16, 100, None, ctypes.byref(out)) == qt.QT_ERR_UNSUPPORTED
+    assert L.qt_probe_batched(7, 32, 100, None, ctypes.byref(out)) == qt.QT_ERR_ARG
