@@ -95,6 +95,13 @@ __device__ __forceinline__ uint32_t mask_row(uint64_t m, int r, int lb) {
     return (uint32_t)((m >> (r * lb)) & ((1ull << lb) - 1));
 }
 
+// the OR of all lb rows of such a mask: bit k set iff column k holds a block
+// (for a column-major mask: bit k set iff row k does)
+__device__ __forceinline__ uint32_t mask_fold(uint64_t m, int lb) {
+    for (int sh = lb * lb / 2; sh >= lb; sh >>= 1) m |= m >> sh;
+    return (uint32_t)(m & ((1ull << lb) - 1));
+}
+
 // ------------------------------------------------- one level of the tree
 
 struct TreeStep {
@@ -433,6 +440,10 @@ __device__ __forceinline__ bool leaf_block_kept(const LeafStep& st, uint64_t lea
 }
 
 // Lane q (a block of the C leaf, local Morton index) counts its products.
+// The leaf pairs are taken 64 at a time, one per lane, and only those that
+// can add a block product at all are walked: some inner index k with column
+// k of the op(A) leaf and row k of the op(B) leaf both occupied. In an
+// unstructured product most leaf pairs have none (random65536: four in five).
 __device__ int leaf_lane_count(const LeafStep& st, int32_t s0, int32_t len, int lane, int i, int j, int lb,
                                bool on) {
     int cnt = 0;
@@ -443,7 +454,8 @@ __device__ int leaf_lane_count(const LeafStep& st, int32_t s0, int32_t len, int 
             ra = st.Arm[st.fa[s0 + base + lane]];
             cb = st.Bcm[st.fb[s0 + base + lane]];
         }
-        for (int t = 0; t < nb; ++t) {
+        for (uint64_t live = __ballot((mask_fold(ra, lb) & mask_fold(cb, lb)) != 0); live; live &= live - 1) {
+            const int t = __ffsll((unsigned long long)live) - 1;
             const uint64_t rat = lane_value(ra, t);
             const uint64_t cbt = lane_value(cb, t);
             if (on) cnt += __popc(mask_row(rat, i, lb) & mask_row(cbt, j, lb));
@@ -506,7 +518,8 @@ __device__ void leaf_fill_node(const LeafStep& st, int32_t c, int lane, int64_t 
             ab = st.Abase[a];
             bb = st.Bbase[b];
         }
-        for (int t = 0; t < nb; ++t) {
+        for (uint64_t live = __ballot((mask_fold(ra, lb) & mask_fold(cb, lb)) != 0); live; live &= live - 1) {
+            const int t = __ffsll((unsigned long long)live) - 1;
             const uint64_t rat = lane_value(ra, t);
             const uint64_t cbt = lane_value(cb, t);
             uint32_t m = on ? (mask_row(rat, i, lb) & mask_row(cbt, j, lb)) : 0u;
@@ -732,7 +745,7 @@ constexpr int64_t ORDER_MAX_POSITIONS = int64_t(1) << 22;
 // workgroup and one k the slots are claimed by LDS atomics, so that order
 // varies from call to call; each C block is still computed by one wave with
 // its products in ascending k, so no result depends on it.
-constexpr int KORDER_THREADS = 256, KORDER_ITEMS = 16;
+constexpr int KORDER_THREADS = 64, KORDER_ITEMS = 32;   // single waves (see the scan)
 constexpr int64_t KORDER_WG = KORDER_THREADS * KORDER_ITEMS;   // C blocks per workgroup
 constexpr int64_t KORDER_MAX_K = 16384;                        // LDS table of 64 KiB
 constexpr int64_t KORDER_MAX_CELLS = int64_t(1) << 24;         // (k, workgroup) counts
@@ -1130,7 +1143,8 @@ void symbolic(qt_matrix* A, qt_matrix* B, qt_prec prec, hipStream_t s, SymbolicO
         gsum_total += (level_wgs(ncap[l]) + (1 << AGG_GROUP_LOG) - 1) >> AGG_GROUP_LOG;
         scan_elems = std::max(scan_elems, scan_tmp_elems(ncap[l]));
     }
-    const size_t o_gsum = tmp.take(std::max<int64_t>(gsum_total, 1) * sizeof(int64_t));
+    const int64_t nzero = std::max<int64_t>(gsum_total, 1);
+    const size_t o_gsum = tmp.take(nzero * sizeof(int64_t));
     const size_t o_scan = tmp.take((scan_elems + 1) * sizeof(int64_t));
     const size_t o_prodA = tmp.take(P * sizeof(int32_t));
     const size_t o_prodB = tmp.take(P * sizeof(int32_t));
@@ -1211,9 +1225,9 @@ void symbolic(qt_matrix* A, qt_matrix* B, qt_prec prec, hipStream_t s, SymbolicO
         return st;
     };
     RootInit root{(int32_t*)at(W, o_fa[0]), (int32_t*)at(W, o_fb[0]), (int32_t*)at(W, o_cseg[0]),
-                  (uint64_t*)at(W, u_key[0]), dcount, (int64_t*)at(W, o_gsum), gsum_total};
+                  (uint64_t*)at(W, u_key[0]), dcount, (int64_t*)at(W, o_gsum), nzero};
 
-    k_fill_flags<<<(unsigned)((foff[L + 1] + 255) / 256), 256, 0, ss>>>(nflags, foff[L + 1]);
+    k_fill_flags<<<(unsigned)((foff[L + 1] + 63) / 64), 64, 0, ss>>>(nflags, foff[L + 1]);
     QT_LAUNCH("k_fill_flags");
     k_root_init<<<1, 64, 0, ss>>>(root);
     QT_LAUNCH("k_root_init");
@@ -1275,16 +1289,16 @@ void symbolic(qt_matrix* A, qt_matrix* B, qt_prec prec, hipStream_t s, SymbolicO
         int32_t* otab = (int32_t*)at(W, o_otab);
         int32_t* ocnt = (int32_t*)at(W, o_ocnt);
         int32_t* ooff = (int32_t*)at(W, o_ooff);
-        const unsigned gp = (unsigned)((lpos + 255) / 256);
-        k_order_clear<<<gp, 256, 0, ss>>>(otab, lpos);
+        const unsigned gp = (unsigned)((lpos + 63) / 64);
+        k_order_clear<<<gp, 64, 0, ss>>>(otab, lpos);
         QT_LAUNCH("k_order_clear");
-        k_order_place<<<(unsigned)((ncap[L] + 255) / 256), 256, 0, ss>>>(ls.ckey, ls.ncount, ls.ncap, lrows, lcols,
+        k_order_place<<<(unsigned)((ncap[L] + 63) / 64), 64, 0, ss>>>(ls.ckey, ls.ncount, ls.ncap, lrows, lcols,
                                                                           otab);
         QT_LAUNCH("k_order_place");
-        k_order_counts<<<gp, 256, 0, ss>>>(otab, lpos, ls.lmo, ocnt);
+        k_order_counts<<<gp, 64, 0, ss>>>(otab, lpos, ls.lmo, ocnt);
         QT_LAUNCH("k_order_counts");
         exclusive_scan(ocnt, ooff, lpos, (int32_t*)at(W, o_oscan), ss);
-        k_order_fill<<<gp, 256, 0, ss>>>(otab, lpos, ls.lbase, ocnt, ooff, ls.cap, order);
+        k_order_fill<<<gp, 64, 0, ss>>>(otab, lpos, ls.lbase, ocnt, ooff, ls.cap, order);
         QT_LAUNCH("k_order_fill");
     }
     {
@@ -1313,10 +1327,10 @@ void symbolic(qt_matrix* A, qt_matrix* B, qt_prec prec, hipStream_t s, SymbolicO
         nt.rm = (uint64_t*)at(K, o_lrm);
         nt.cm = (uint64_t*)at(K, o_lcm);
         nt.kept = dcount + 2 * L + 3;
-        k_nil_mark<<<(unsigned)((ncap[L] + 255) / 256), 256, 0, ss>>>(nt);
+        k_nil_mark<<<(unsigned)((ncap[L] + 63) / 64), 64, 0, ss>>>(nt);
         QT_LAUNCH("k_nil_mark");
         exclusive_scan(nflags, (int32_t*)at(W, o_nex), foff[L + 1], (int32_t*)at(W, o_nscan), ss);
-        k_nil_compact<<<(unsigned)((foff[L + 1] + 255) / 256), 256, 0, ss>>>(nt);
+        k_nil_compact<<<(unsigned)((foff[L + 1] + 63) / 64), 64, 0, ss>>>(nt);
         QT_LAUNCH("k_nil_compact");
     }
     if (prof) QT_HIP(hipEventRecord(ev.e1, ss));

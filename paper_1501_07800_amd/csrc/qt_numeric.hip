@@ -103,7 +103,8 @@ static unsigned xcd_grid(int64_t tiles) {
 template <class T, int BS>
 __device__ __forceinline__ void wave_block(const T* __restrict__ A, const T* __restrict__ B,
                                            const int32_t* __restrict__ prodA, const int32_t* __restrict__ prodB,
-                                           int32_t t0, int32_t t1, T* __restrict__ c, int sub) {
+                                           int32_t t0, int32_t t1, T* __restrict__ c, int sub, int32_t ia0,
+                                           int32_t ib0) {
     typedef Geo<BS> G;
     typedef typename Mfma<T>::acc acc_t;
     constexpr int VEC = 16 / sizeof(T);            // elements per 16-byte load
@@ -126,8 +127,9 @@ __device__ __forceinline__ void wave_block(const T* __restrict__ A, const T* __r
     //   k = (ks / VEC) * 4*VEC + g*VEC + ks % VEC,
     // so each 16-byte A load of a lane is VEC consecutive entries of its row
     // and the four lane groups together read one contiguous run per row.
-    // Block indices of the next product are fetched while this one runs.
-    int32_t ia = prodA[t0], ib = prodB[t0];
+    // Block indices of the next product are fetched while this one runs;
+    // the caller gives the first product's (ia0, ib0).
+    int32_t ia = ia0, ib = ib0;
     for (int32_t t = t0; t < t1; ++t) {
         const T* a = A + (size_t)ia * (BS * BS);
         const T* b = B + (size_t)ib * (BS * BS);
@@ -435,7 +437,9 @@ __global__ __launch_bounds__(64, (MinWaves<T, BS>::value)) void k_numeric(const 
     const int64_t q = tile / G::WPB;
     if (q >= nseg) return;
     const int64_t s = order ? order[q] : q;
-    wave_block<T, BS>(A, B, prodA, prodB, seg[s], seg[s + 1], C + (size_t)s * (BS * BS), (int)(tile % G::WPB));
+    const int32_t t0 = seg[s];
+    wave_block<T, BS>(A, B, prodA, prodB, t0, seg[s + 1], C + (size_t)s * (BS * BS), (int)(tile % G::WPB),
+                      prodA[t0], prodB[t0]);
 }
 
 template <int BS>
@@ -940,8 +944,9 @@ __device__ __forceinline__ void batch_item(const BatchProblem* __restrict__ prob
     const int64_t local = it - item_base[lo];
     const int64_t s = local / WPB;
     const int sub = (int)(local - s * WPB);
-    wave_block<T, BS>((const T*)P.A, (const T*)P.B, P.prodA, P.prodB, P.seg[s], P.seg[s + 1],
-                      (T*)P.C + (size_t)s * (BS * BS), sub);
+    const int32_t t0 = P.seg[s];
+    wave_block<T, BS>((const T*)P.A, (const T*)P.B, P.prodA, P.prodB, t0, P.seg[s + 1],
+                      (T*)P.C + (size_t)s * (BS * BS), sub, P.prodA[t0], P.prodB[t0]);
 }
 
 template <int BS>

@@ -1,20 +1,23 @@
 // Exclusive prefix sums of int32 or int64 counts (reduce / scan block sums /
 // rescan).
 //
-// A tile of SCAN_TILE counts goes to one 256-thread workgroup: the tile is
-// staged in LDS with coalesced loads, each thread sums 16 consecutive counts,
-// the 256 thread sums are scanned across the four wavefronts, and the tile is
-// rescanned with the tile's global offset. Tiles beyond one are handled by
-// scanning the per-tile sums recursively.
+// A tile of SCAN_TILE counts goes to one single-wave workgroup: the tile is
+// staged in LDS with coalesced loads, each lane sums 16 consecutive counts,
+// the 64 lane sums are scanned across the wave, and the tile is rescanned
+// with the tile's global offset. Tiles beyond one are handled by scanning the
+// per-tile sums recursively. Single waves, because these scans run in the
+// symbolic phase beside the previous multiply's numeric kernel, whose
+// single-wave workgroups take every wave slot that frees up: a workgroup of
+// several waves would wait until that kernel drained.
 #include "qt_internal.h"
 
 namespace qt {
 
-constexpr int SCAN_T = 256;
+constexpr int SCAN_T = 64;
 constexpr int SCAN_I = 16;
 constexpr int SCAN_TILE = SCAN_T * SCAN_I;
 
-// Exclusive scan of one value per thread across the 256-thread workgroup.
+// Exclusive scan of one value per thread across the workgroup.
 template <class T>
 __device__ inline T wg_exclusive_scan(T v, T* lds_waves, T* total) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
