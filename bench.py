@@ -344,7 +344,12 @@ def bench_batch(args, qt, torch, wl):
     log("bench: generating the 64-problem batch (seed 5)")
     probs = wl.batch_mix(64, 5)
     b = probs[0][0].b
+    # the leaf tuner's choices per pattern class go through the tuning cache file
+    cache_path = os.environ.get("QT_TUNE_CACHE", os.path.join(os.path.expanduser("~"), ".cache", "qt", "tune.txt"))
+    os.makedirs(os.path.dirname(cache_path), exist_ok=True)
+    qt.tune_cache(cache_path)
     cache = {}
+    hits = 0
     hs = []
     t_tune = time.perf_counter()
     for A, B in probs:
@@ -352,7 +357,9 @@ def bench_batch(args, qt, torch, wl):
         cls = (A.meta.get("pattern"), int(round(math.log2(A.nb_rows))), int(round(math.log2(fill * 1000))))
         if cls not in cache:
             ha, hb = qt.from_blockmatrix(A, 8 * b), qt.from_blockmatrix(B, 8 * b)
-            cache[cls], _ = qt.tune_leaf(ha, hb, prec, reps=2)
+            cache[cls], cached = qt.tune_leaf_cached(ha, hb, f"{cls[0]} nb2^{cls[1]} fill2^{cls[2]}/1000", prec,
+                                                     reps=2)
+            hits += int(cached)
             del ha, hb
         leaf = cache[cls]
         ha, hb = qt.from_blockmatrix(A, leaf), qt.from_blockmatrix(B, leaf)
@@ -384,7 +391,8 @@ def bench_batch(args, qt, torch, wl):
     plan = qt.Plan([a for a, _ in hs], [bb for _, bb in hs], prec)
     torch.cuda.synchronize()
     t_plan = time.perf_counter() - t0
-    sched, sched_ms = plan.tune(reps=3)
+    sched, sched_ms = plan.tune(reps=3)   # every configuration, for the record
+    log("bench: plan configurations (ms): " + ", ".join(f"{k} {v:.3f}" for k, v in sched_ms.items()))
     for _ in range(args.warmup):
         plan.execute(graph=True)
     torch.cuda.synchronize()
@@ -412,7 +420,10 @@ def bench_batch(args, qt, torch, wl):
                    "op": "C_i = A_i*B_i, i = 1..64", "leaf_by_class": {str(k): v for k, v in cache.items()}},
         "mfma_peak_frac": value / peak,
         "plan": {"schedule": sched, "schedule_ms": sched_ms, "create_s": t_plan, "tune_s": t_tune,
-                 "host_ms_per_step": t_exec * 1e3},
+                 "host_ms_per_step": t_exec * 1e3, "flat_ms": sched_ms.get("flat"),
+                 "best_persistent": min(((k, v) for k, v in sched_ms.items() if not k.startswith("flat")),
+                                        key=lambda kv: kv[1], default=None),
+                 "tuning_cache": {"path": cache_path, "leaf_classes": len(cache), "hits": hits}},
         "sequential": {"tflops_end_to_end": flops / t_seq / 1e12, "ms_per_step": t_seq * 1e3,
                        "numeric_ms_sum": seq_numeric_ms,
                        "numeric_tflops": flops / (seq_numeric_ms * 1e-3) / 1e12},

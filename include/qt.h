@@ -272,37 +272,61 @@ void qt_free(qt_matrix* M);
  * Algorithm 1, Sec. 3) of every problem now -- it synchronizes `stream` and
  * allocates every C_i -- and lays the numeric work of all problems out as one
  * work list: problems by decreasing block products, C blocks of a problem in
- * Morton order.
+ * its launch order (see QT_PLAN_ORDER_MORTON below).
  *   count:  number of problems (>= 1); A[i], B[i] as for qt_multiply (same
  *           block size across the batch; leaf sizes may differ per problem).
  * Errors: ARG, SHAPE, OOM, DEVICE, UNSUPPORTED.
  *
  * qt_plan_execute computes every C_i: one kernel launch (plus a one-thread
- * counter reset for the persistent schedules) that allocates nothing and does
+ * counter reset for the dynamic schedules) that allocates nothing and does
  * not synchronize. With use_graph != 0 the first call captures that launch
  * sequence into a HIP graph and every call replays it on `stream`; with
  * use_graph == 0 the kernels are launched directly. Executions on one plan
  * must not overlap (they share the plan's work counter and the C_i).
  *
- * qt_plan_tune times every schedule of the batch kernel (flat grid;
- * persistent with 1, 4 or 16 C-block tiles per grab) on this plan, `reps`
- * runs each, keeps the fastest and reports it in *schedule; ms (may be NULL)
- * receives QT_PLAN_SCHEDULES mean times. It computes the C_i as a side effect
- * and synchronizes `stream`.
+ * A plan runs in one of QT_PLAN_CONFIGS configurations, a schedule (0 .. 3)
+ * plus option bits:
+ *   schedule 0  flat grid: one workgroup per work item, the hardware
+ *               dispatcher balancing the uneven problems;
+ *   schedule 1  persistent, balanced: as many workgroups as fit on the GPU
+ *               at once, each taking a contiguous run of work items that
+ *               holds an equal share of the work (block products plus one per
+ *               C block, summed when the plan is created; no counter);
+ *   schedule 2  persistent, dynamic per XCD: each workgroup takes 4 items at
+ *               a time from a counter of its XCD, over the flat grid's runs
+ *               of neighbouring items per XCD;
+ *   schedule 3  persistent, dynamic: 16 items at a time from a counter;
+ *   QT_PLAN_ORDER_MORTON  every problem's C blocks in Morton order (without
+ *               it a problem whose C blocks average under two block products
+ *               is launched grouped by inner index, as qt_multiply does);
+ *   QT_PLAN_TILE_WAVE     at b = 64, one wave per 32 x 32 tile instead of one
+ *               four-wave workgroup per C block sharing its operands through
+ *               LDS (no effect at other block sizes).
+ * Every configuration gives bitwise the same C_i (and the same as
+ * qt_multiply). A new plan starts in configuration 0.
  *
- * qt_plan_set_schedule picks a schedule directly (e.g. one tuned earlier).
+ * qt_plan_tune times every configuration that differs on this plan, `reps`
+ * runs each, keeps the fastest and reports it in *schedule; ms (may be NULL)
+ * receives QT_PLAN_CONFIGS mean times, -1 for configurations not tried. It
+ * computes the C_i as a side effect and synchronizes `stream`.
+ *
+ * qt_plan_set_schedule picks a configuration directly (e.g. one tuned
+ * earlier); ARG unless 0 <= schedule < QT_PLAN_CONFIGS.
  *
  * qt_plan_result returns C_i, owned by the plan: valid until
  * qt_plan_destroy, and qt_free on it does nothing. qt_plan_info reports the
- * number of work items (C-block tiles), block products and the schedule.
+ * number of work items, block products and the configuration.
  * qt_plan_destroy waits for the plan's last execution and releases all of it.
  */
 #define QT_PLAN_SCHEDULES 4
+#define QT_PLAN_ORDER_MORTON 4
+#define QT_PLAN_TILE_WAVE 8
+#define QT_PLAN_CONFIGS 16
 qt_status qt_plan_create(int32_t count, const qt_matrix* const* A, const qt_matrix* const* B, qt_prec prec,
                          void* stream, qt_plan** plan);
 qt_status qt_plan_execute(qt_plan* plan, void* stream, int use_graph);
 qt_status qt_plan_tune(qt_plan* plan, void* stream, int reps, int32_t* schedule, float* ms);
-qt_status qt_plan_set_schedule(qt_plan* plan, int32_t schedule);   /* 0 .. QT_PLAN_SCHEDULES-1; ARG if not */
+qt_status qt_plan_set_schedule(qt_plan* plan, int32_t schedule);   /* a configuration, 0 .. QT_PLAN_CONFIGS-1 */
 qt_status qt_plan_result(const qt_plan* plan, int32_t i, qt_matrix** C);
 qt_status qt_plan_info(const qt_plan* plan, int64_t* work_items, int64_t* products, int32_t* schedule);
 void qt_plan_destroy(qt_plan* plan);
@@ -319,6 +343,29 @@ void qt_plan_destroy(qt_plan* plan);
  */
 qt_status qt_tune_leaf(const qt_matrix* A, const qt_matrix* B, qt_prec prec, void* stream, int reps,
                        int32_t* best_leaf, int32_t* leaves, float* ms, int32_t max_out, int32_t* n_tried);
+
+/*
+ * Tuning cache: the choices of the tuners kept in a text file (one line per
+ * choice, "key<TAB>value") and reused instead of timing again. The key is
+ * the GPU architecture (e.g. gfx950), the block size, the precision, the
+ * tuner and a class the caller names: for qt_tune_leaf_cached a pattern class
+ * (e.g. "random n2^11 fill2^-6": the leaf size that suits a problem depends on
+ * its pattern, size and fill), for qt_plan_tune_cached the batch (its
+ * configuration depends on the mix of problems).
+ * qt_tune_cache(path) sets the file and reads what it holds (a missing file
+ * is made on the first new choice; NULL stops using a file). Every new choice
+ * rewrites the file (to path.tmp, then renamed over path). The tuners
+ * otherwise behave as qt_tune_leaf and qt_plan_tune; *cached (may be NULL) is
+ * 1 when the choice came from the file (nothing was timed, and the plan was
+ * only set to it), else 0. Without a file they always time.
+ * Errors: ARG (NULL argument, unknown precision, the file cannot be written),
+ * and those of the tuner.
+ */
+qt_status qt_tune_cache(const char* path);
+qt_status qt_tune_leaf_cached(const qt_matrix* A, const qt_matrix* B, qt_prec prec, void* stream, int reps,
+                              const char* pattern_class, int32_t* best_leaf, int32_t* cached);
+qt_status qt_plan_tune_cached(qt_plan* plan, void* stream, int reps, const char* batch_class, int32_t* schedule,
+                              int32_t* cached);
 
 /* Per-phase GPU timing of qt_multiply, from HIP events recorded on the
  * multiply's stream. qt_profile(1) starts recording (and clears totals),

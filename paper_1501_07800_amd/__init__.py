@@ -94,6 +94,12 @@ def _load():
     lib.qt_tune_leaf.restype = ctypes.c_int
     lib.qt_tune_leaf.argtypes = [vp, vp, ctypes.c_int, vp, ctypes.c_int, i32p, i32p, ctypes.POINTER(ctypes.c_float),
                                  i32, i32p]
+    lib.qt_tune_cache.restype = ctypes.c_int
+    lib.qt_tune_cache.argtypes = [ctypes.c_char_p]
+    lib.qt_tune_leaf_cached.restype = ctypes.c_int
+    lib.qt_tune_leaf_cached.argtypes = [vp, vp, ctypes.c_int, vp, ctypes.c_int, ctypes.c_char_p, i32p, i32p]
+    lib.qt_plan_tune_cached.restype = ctypes.c_int
+    lib.qt_plan_tune_cached.argtypes = [vp, vp, ctypes.c_int, ctypes.c_char_p, i32p, i32p]
     lib.qt_last_error.restype = ctypes.c_char_p
     lib.qt_last_error.argtypes = []
     lib.qt_probe_batched.restype = ctypes.c_int
@@ -216,10 +222,30 @@ def _default_allocator():
 
 EXPORTS = ("qt_build", "qt_multiply", "qt_multiply_ex", "qt_add", "qt_truncate", "qt_sysq", "qt_info", "qt_to_blocks", "qt_to_blocks_noalloc", "qt_get_blocks", "qt_stats", "qt_levels", "qt_prepare", "qt_free",
            "qt_plan_create", "qt_plan_execute", "qt_plan_tune", "qt_plan_set_schedule", "qt_plan_result", "qt_plan_info",
-           "qt_plan_destroy", "qt_tune_leaf", "qt_profile", "qt_profile_read", "qt_probe_mfma", "qt_probe_batched", "qt_last_error", "qt_version",
+           "qt_plan_destroy", "qt_tune_leaf", "qt_tune_cache", "qt_tune_leaf_cached", "qt_plan_tune_cached", "qt_profile", "qt_profile_read", "qt_probe_mfma", "qt_probe_batched", "qt_last_error", "qt_version",
            "qt_set_allocator")
 NOALLOC_MAX_BLOCKS = 1 << 20   # QT_NOALLOC_MAX_BLOCKS
-PLAN_SCHEDULES = ("flat", "persistent-1", "persistent-4", "persistent-16")
+PLAN_SCHEDULES = ("flat", "balanced", "xcd-dynamic", "dynamic-16")   # QT_PLAN_SCHEDULES
+PLAN_ORDER_MORTON, PLAN_TILE_WAVE, PLAN_CONFIGS = 4, 8, 16
+
+
+def plan_config_name(c: int) -> str:
+    """Name of plan configuration c: the schedule, then '+morton' (every
+    problem in Morton order) and '+wave-tiles' (b = 64: a wave per 32 x 32
+    tile instead of a workgroup per C block sharing operands through LDS)."""
+    return PLAN_SCHEDULES[c & 3] + ("+morton" if c & PLAN_ORDER_MORTON else "") + \
+        ("+wave-tiles" if c & PLAN_TILE_WAVE else "")
+
+
+def plan_config(name) -> int:
+    """Inverse of plan_config_name (an int is returned as it is)."""
+    if isinstance(name, int):
+        return name
+    parts = name.split("+")
+    c = PLAN_SCHEDULES.index(parts[0])
+    for p in parts[1:]:
+        c |= {"morton": PLAN_ORDER_MORTON, "wave-tiles": PLAN_TILE_WAVE}[p]
+    return c
 
 
 def _check(status: int):
@@ -395,13 +421,24 @@ class Plan:
         _check(lib.qt_plan_execute(self._h, _stream_ptr(stream), 1 if graph else 0))
 
     def tune(self, reps: int = 3, stream=None):
-        sched = ctypes.c_int32()
-        ms = (ctypes.c_float * 4)()
-        _check(lib.qt_plan_tune(self._h, _stream_ptr(stream), reps, ctypes.byref(sched), ms))
-        return PLAN_SCHEDULES[sched.value], {PLAN_SCHEDULES[i]: ms[i] for i in range(4)}
+        """qt_plan_tune: the fastest configuration's name and the mean time
+        (ms) of every configuration it tried."""
+        cfg = ctypes.c_int32()
+        ms = (ctypes.c_float * PLAN_CONFIGS)()
+        _check(lib.qt_plan_tune(self._h, _stream_ptr(stream), reps, ctypes.byref(cfg), ms))
+        return plan_config_name(cfg.value), {plan_config_name(i): ms[i] for i in range(PLAN_CONFIGS) if ms[i] >= 0}
 
-    def set_schedule(self, name: str):
-        _check(lib.qt_plan_set_schedule(self._h, PLAN_SCHEDULES.index(name)))
+    def tune_cached(self, batch_class: str, reps: int = 3, stream=None):
+        """qt_plan_tune_cached: the configuration the tuning cache holds for
+        this batch class, else the tuner's (then stored); (name, cached)."""
+        cfg, cached = ctypes.c_int32(), ctypes.c_int32()
+        _check(lib.qt_plan_tune_cached(self._h, _stream_ptr(stream), reps, batch_class.encode(), ctypes.byref(cfg),
+                                       ctypes.byref(cached)))
+        return plan_config_name(cfg.value), bool(cached.value)
+
+    def set_schedule(self, name):
+        """qt_plan_set_schedule with a configuration name (or number)."""
+        _check(lib.qt_plan_set_schedule(self._h, plan_config(name)))
 
     def result(self, i: int) -> Matrix:
         out = ctypes.c_void_p()
@@ -411,7 +448,8 @@ class Plan:
     def info(self) -> dict:
         items, prods, sched = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int32()
         _check(lib.qt_plan_info(self._h, ctypes.byref(items), ctypes.byref(prods), ctypes.byref(sched)))
-        return {"work_items": items.value, "products": prods.value, "schedule": PLAN_SCHEDULES[sched.value]}
+        return {"work_items": items.value, "products": prods.value, "schedule": plan_config_name(sched.value),
+                "config": sched.value}
 
     def destroy(self):
         if self._h is not None and self._h.value:
@@ -434,6 +472,20 @@ def tune_leaf(A: Matrix, B: Matrix, prec: str = "f64", reps: int = 3, stream=Non
     _check(lib.qt_tune_leaf(A.handle, B.handle, PREC[prec], _stream_ptr(stream), reps, ctypes.byref(best), leaves,
                             ms, 8, ctypes.byref(n)))
     return best.value, {leaves[i]: ms[i] for i in range(n.value)}
+
+
+def tune_cache(path):
+    """qt_tune_cache: keep the tuners' choices in the text file `path` (None: no file)."""
+    _check(lib.qt_tune_cache(None if path is None else os.fsencode(path)))
+
+
+def tune_leaf_cached(A: Matrix, B: Matrix, pattern_class: str, prec: str = "f64", reps: int = 3, stream=None):
+    """qt_tune_leaf_cached: the leaf size the tuning cache holds for this
+    pattern class, else the tuner's (then stored); (leaf, cached)."""
+    best, cached = ctypes.c_int32(), ctypes.c_int32()
+    _check(lib.qt_tune_leaf_cached(A.handle, B.handle, PREC[prec], _stream_ptr(stream), reps, pattern_class.encode(),
+                                   ctypes.byref(best), ctypes.byref(cached)))
+    return best.value, bool(cached.value)
 
 
 OP_TRANS_A, OP_TRANS_B, OP_UPPER = 1, 2, 4

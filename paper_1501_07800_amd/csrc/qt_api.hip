@@ -17,6 +17,9 @@ void get_blocks(const qt_matrix*, int64_t, const int32_t*, const int32_t*, void*
 qt_plan* plan_create(int32_t, const qt_matrix* const*, const qt_matrix* const*, qt_prec, hipStream_t);
 void plan_execute(qt_plan*, hipStream_t, int);
 int plan_tune(qt_plan*, hipStream_t, int, float*);
+void tune_cache_set(const char*);
+int32_t tune_leaf_cached(const qt_matrix*, const qt_matrix*, qt_prec, hipStream_t, int, const char*, int*);
+int32_t plan_tune_cached(qt_plan*, hipStream_t, int, const char*, int*);
 int32_t tune_leaf(const qt_matrix*, const qt_matrix*, qt_prec, hipStream_t, int, int32_t*, float*, int32_t,
                   int32_t*);
 int32_t plan_count(const qt_plan*);
@@ -404,7 +407,7 @@ qt_status qt_plan_tune(qt_plan* plan, void* stream, int reps, int32_t* schedule,
 }
 
 qt_status qt_plan_set_schedule(qt_plan* plan, int32_t schedule) {
-    if (!plan || schedule < 0 || schedule >= kBatchVariants) {
+    if (!plan || schedule < 0 || schedule >= QT_PLAN_CONFIGS) {
         set_last_error("bad plan or schedule");
         return QT_ERR_ARG;
     }
@@ -446,6 +449,46 @@ qt_status qt_tune_leaf(const qt_matrix* A, const qt_matrix* B, qt_prec prec, voi
     }
     QT_GUARD_BEGIN
     *best_leaf = tune_leaf(A, B, prec, (hipStream_t)stream, reps, leaves, ms, max_out, n_tried);
+    return QT_OK;
+    QT_GUARD_END
+}
+
+qt_status qt_tune_cache(const char* path) {
+    QT_GUARD_BEGIN
+    tune_cache_set(path);
+    return QT_OK;
+    QT_GUARD_END
+}
+
+qt_status qt_tune_leaf_cached(const qt_matrix* A, const qt_matrix* B, qt_prec prec, void* stream, int reps,
+                              const char* pattern_class, int32_t* best_leaf, int32_t* cached) {
+    if (!A || !B || !best_leaf || !pattern_class) {
+        set_last_error("bad argument");
+        return QT_ERR_ARG;
+    }
+    if (prec != QT_F64 && prec != QT_F32 && prec != QT_BF16X3) {
+        set_last_error("unknown precision");
+        return QT_ERR_ARG;
+    }
+    QT_GUARD_BEGIN
+    int c = 0;
+    *best_leaf = tune_leaf_cached(A, B, prec, (hipStream_t)stream, reps, pattern_class, &c);
+    if (cached) *cached = c;
+    return QT_OK;
+    QT_GUARD_END
+}
+
+qt_status qt_plan_tune_cached(qt_plan* plan, void* stream, int reps, const char* batch_class, int32_t* schedule,
+                              int32_t* cached) {
+    if (!plan || !batch_class) {
+        set_last_error("bad argument");
+        return QT_ERR_ARG;
+    }
+    QT_GUARD_BEGIN
+    int c = 0;
+    const int32_t v = plan_tune_cached(plan, (hipStream_t)stream, reps, batch_class, &c);
+    if (schedule) *schedule = v;
+    if (cached) *cached = c;
     return QT_OK;
     QT_GUARD_END
 }

@@ -253,31 +253,37 @@ void launch_numeric(const NumericArgs& a, hipStream_t s);
 double probe_mfma(qt_prec prec, hipStream_t s);   // TFLOP/s of a register-only MFMA loop
 double probe_batched(qt_prec prec, int b, int64_t count, hipStream_t s);   // TFLOP/s of count block products
 
-// One problem of a batch, as the batch kernels read it (device memory).
+// One problem of a batch, as the batch kernels read it (device memory): the
+// problem's arrays as byte offsets from the launch's base pointer (a kernel
+// argument, so the compiler addresses them as device memory; -1: none).
 struct BatchProblem {
-    const void* A;            // fp64 / fp32 operands
-    const void* B;
-    const uint16_t* Ahi; const uint16_t* Alo;     // split-bf16 operands
-    const uint16_t* Bhi_t; const uint16_t* Blo_t;
-    const int32_t* prodA;
-    const int32_t* prodB;
-    const int32_t* seg;
-    void* C;
+    int64_t A, B;             // fp64 / fp32 operands
+    int64_t Ahi, Alo;         // split-bf16 operands
+    int64_t Bhi_t, Blo_t;
+    int64_t prodA, prodB, seg;
+    int64_t order;            // launch order of C's blocks (-1: Morton order)
+    int64_t C;
 };
+// schedules of the batch kernel: 0 flat grid, 1 persistent with work-balanced
+// contiguous runs, 2 persistent taking 4 items per grab from a counter per
+// XCD, 3 persistent taking 16 items per grab from one counter
+constexpr int kBatchSchedules = 4;
 struct BatchLaunch {
     int b = 0;
     qt_prec prec = QT_F64;
-    int variant = 0;          // 0 flat grid; 1, 2, 3 persistent with 1, 4, 16 items per grab
+    int schedule = 0;
+    bool lds = false;         // b = 64: one four-wave workgroup per C block, operands shared through LDS
     const BatchProblem* probs = nullptr;
+    const char* base = nullptr;           // the problems' offsets are from here
     const int64_t* item_base = nullptr;   // nprob + 1 prefix offsets of work items
     int32_t nprob = 0;
     int64_t total_items = 0;
-    unsigned long long* counter = nullptr;
-    int persistent_grid = 0;
+    unsigned long long* counter = nullptr;   // 64 words: the work counters
+    const int64_t* cum = nullptr;         // balanced schedules: exclusive scan of the items' work
 };
 void launch_batch(const BatchLaunch& L, hipStream_t s);
-int batch_persistent_grid(int b, qt_prec prec);
-constexpr int kBatchVariants = 4;
+// work of every item of L (block products + 1) into cost[0 .. total_items)
+void batch_item_costs(const BatchLaunch& L, int64_t* cost, hipStream_t s);
 
 // profiling ----------------------------------------------------------------
 bool profiling_on();

@@ -39,6 +39,8 @@
 #include "qt_internal.h"
 
 #include <algorithm>
+#include <map>
+#include <mutex>
 
 namespace qt {
 
@@ -505,23 +507,19 @@ __global__ __launch_bounds__(64) void k_numeric_bf16x3_op(SplitOps ops, const in
 constexpr int F64L_AROW = 34;
 constexpr int F64L_BROW = 72;
 
-__global__ __launch_bounds__(256, 4) void k_numeric_f64_b64(const double* __restrict__ A, const double* __restrict__ B,
-                                                         const int32_t* __restrict__ prodA,
-                                                         const int32_t* __restrict__ prodB,
-                                                         const int32_t* __restrict__ seg, int32_t nseg,
-                                                         const int32_t* __restrict__ order, double* __restrict__ C) {
+// One C block of the LDS-sharing kernel below, products t0 .. t1-1, into c
+// (all four waves of the workgroup take part).
+__device__ __forceinline__ void lds_block_f64(const double* __restrict__ A, const double* __restrict__ B,
+        const int32_t* __restrict__ prodA, const int32_t* __restrict__ prodB, int32_t t0, int32_t t1,
+        double* __restrict__ c) {
     constexpr int BS = 64, MT = 2, KH = 32;
     typedef double v2d_t __attribute__((ext_vector_type(2)));
     __shared__ __attribute__((aligned(16))) double la[64 * F64L_AROW];   // A[:, half]
     __shared__ __attribute__((aligned(16))) double lb[KH * F64L_BROW];   // B[half, :]
-    const int64_t q = xcd_logical<8>(blockIdx.x);
-    if (q >= nseg) return;   // uniform over the workgroup
-    const int64_t s = order ? order[q] : q;
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
     const int r16 = lane & 15, g = lane >> 4;
     const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
-    const int32_t t0 = seg[s], t1 = seg[s + 1];
 
     v4d acc[MT][MT];
 #pragma unroll
@@ -585,7 +583,6 @@ __global__ __launch_bounds__(256, 4) void k_numeric_f64_b64(const double* __rest
         }
     }
 #undef QT_F64L_FETCH
-    double* c = C + (size_t)s * (BS * BS);
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
@@ -594,6 +591,17 @@ __global__ __launch_bounds__(256, 4) void k_numeric_f64_b64(const double* __rest
             for (int i = 0; i < 4; ++i)
                 __builtin_nontemporal_store(acc[mt][nt][i],
                                             c + (wm + mt * 16 + Mfma<double>::row(g, i)) * BS + wn + nt * 16 + r16);
+}
+
+__global__ __launch_bounds__(256, 4) void k_numeric_f64_b64(const double* __restrict__ A, const double* __restrict__ B,
+                                                         const int32_t* __restrict__ prodA,
+                                                         const int32_t* __restrict__ prodB,
+                                                         const int32_t* __restrict__ seg, int32_t nseg,
+                                                         const int32_t* __restrict__ order, double* __restrict__ C) {
+    const int64_t q = xcd_logical<8>(blockIdx.x);
+    if (q >= nseg) return;   // uniform over the workgroup
+    const int64_t s = order ? order[q] : q;
+    lds_block_f64(A, B, prodA, prodB, seg[s], seg[s + 1], C + (size_t)s * (64 * 64));
 }
 
 // b = 64 fp32 with the operands shared through LDS, like the fp64 kernel
@@ -608,23 +616,19 @@ __global__ __launch_bounds__(256, 4) void k_numeric_f64_b64(const double* __rest
 constexpr int F32L_AROW = 36;
 constexpr int F32L_BROW = 72;
 
-__global__ __launch_bounds__(256) void k_numeric_f32_b64(const float* __restrict__ A, const float* __restrict__ B,
-                                                         const int32_t* __restrict__ prodA,
-                                                         const int32_t* __restrict__ prodB,
-                                                         const int32_t* __restrict__ seg, int32_t nseg,
-                                                         const int32_t* __restrict__ order, float* __restrict__ C) {
+// One C block of the LDS-sharing kernel below, products t0 .. t1-1, into c
+// (all four waves of the workgroup take part).
+__device__ __forceinline__ void lds_block_f32(const float* __restrict__ A, const float* __restrict__ B,
+        const int32_t* __restrict__ prodA, const int32_t* __restrict__ prodB, int32_t t0, int32_t t1,
+        float* __restrict__ c) {
     constexpr int BS = 64, MT = 2, KH = 32;
     typedef float v2f_t __attribute__((ext_vector_type(2)));
     __shared__ __attribute__((aligned(16))) float la[64 * F32L_AROW];   // A[:, half]
     __shared__ __attribute__((aligned(16))) float lb[KH * F32L_BROW];   // B[half, :]
-    const int64_t q = xcd_logical<8>(blockIdx.x);
-    if (q >= nseg) return;   // uniform over the workgroup
-    const int64_t s = order ? order[q] : q;
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
     const int r16 = lane & 15, g = lane >> 4;
     const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
-    const int32_t t0 = seg[s], t1 = seg[s + 1];
 
     v4f acc[MT][MT];
 #pragma unroll
@@ -689,7 +693,6 @@ __global__ __launch_bounds__(256) void k_numeric_f32_b64(const float* __restrict
         }
     }
 #undef QT_F32L_FETCH
-    float* c = C + (size_t)s * (BS * BS);
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
@@ -698,6 +701,17 @@ __global__ __launch_bounds__(256) void k_numeric_f32_b64(const float* __restrict
             __builtin_nontemporal_store(
                 v, reinterpret_cast<v2f_t*>(c + (wm + mt * 16 + Mfma<float>::row(g, i)) * BS + wn + 2 * r16));
         }
+}
+
+__global__ __launch_bounds__(256) void k_numeric_f32_b64(const float* __restrict__ A, const float* __restrict__ B,
+                                                         const int32_t* __restrict__ prodA,
+                                                         const int32_t* __restrict__ prodB,
+                                                         const int32_t* __restrict__ seg, int32_t nseg,
+                                                         const int32_t* __restrict__ order, float* __restrict__ C) {
+    const int64_t q = xcd_logical<8>(blockIdx.x);
+    if (q >= nseg) return;   // uniform over the workgroup
+    const int64_t s = order ? order[q] : q;
+    lds_block_f32(A, B, prodA, prodB, seg[s], seg[s + 1], C + (size_t)s * (64 * 64));
 }
 
 template <class T, int BS>
@@ -734,25 +748,17 @@ typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));   // a 16-byte p
 constexpr int BFL_ROW = 72;
 constexpr int BFL_ARR = 64 * BFL_ROW;      // elements per staged block
 
-__global__ __launch_bounds__(256, 2) void k_numeric_bf16x3_b64(const uint16_t* __restrict__ Ahi,
-                                                                const uint16_t* __restrict__ Alo,
-                                                                const uint16_t* __restrict__ Bhi_t,
-                                                                const uint16_t* __restrict__ Blo_t,
-                                                                const int32_t* __restrict__ prodA,
-                                                                const int32_t* __restrict__ prodB,
-                                                                const int32_t* __restrict__ seg, int32_t nseg,
-                                                                const int32_t* __restrict__ order,
-                                                                double* __restrict__ C) {
+// One C block of the LDS-sharing kernel below, products t0 .. t1-1, into c
+// (all four waves of the workgroup take part).
+__device__ __forceinline__ void lds_block_bf16x3(const uint16_t* __restrict__ Ahi, const uint16_t* __restrict__ Alo, const uint16_t* __restrict__ Bhi_t, const uint16_t* __restrict__ Blo_t,
+        const int32_t* __restrict__ prodA, const int32_t* __restrict__ prodB, int32_t t0, int32_t t1,
+        double* __restrict__ c) {
     constexpr int BS = 64, MT = 2;
     __shared__ __attribute__((aligned(16))) uint16_t lds[4 * BFL_ARR];   // Ahi, Alo, Bhi^T, Blo^T
-    const int64_t q = xcd_logical<8>(blockIdx.x);
-    if (q >= nseg) return;   // uniform over the workgroup
-    const int64_t s = order ? order[q] : q;
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
     const int r16 = lane & 15, g = lane >> 4;
     const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
-    const int32_t t0 = seg[s], t1 = seg[s + 1];
 
     // thread tid moves 16-byte pieces tid and tid + 256 of each 64 x 64 block:
     // piece q is row q / 8, elements 8 * (q % 8) .. + 7
@@ -827,7 +833,6 @@ __global__ __launch_bounds__(256, 2) void k_numeric_bf16x3_b64(const uint16_t* _
 #pragma unroll
                 for (int i = 0; i < 4; ++i) acc[mt][nt][i] += (double)f[mt][nt][i];
     }
-    double* c = C + (size_t)s * (BS * BS);
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
@@ -836,6 +841,21 @@ __global__ __launch_bounds__(256, 2) void k_numeric_bf16x3_b64(const uint16_t* _
             for (int i = 0; i < 4; ++i)
                 __builtin_nontemporal_store(acc[mt][nt][i], c + (wm + mt * 16 + 4 * g + i) * BS + wn + nt * 16 + r16);
 #undef QT_BFL_FETCH
+}
+
+__global__ __launch_bounds__(256, 2) void k_numeric_bf16x3_b64(const uint16_t* __restrict__ Ahi,
+                                                                const uint16_t* __restrict__ Alo,
+                                                                const uint16_t* __restrict__ Bhi_t,
+                                                                const uint16_t* __restrict__ Blo_t,
+                                                                const int32_t* __restrict__ prodA,
+                                                                const int32_t* __restrict__ prodB,
+                                                                const int32_t* __restrict__ seg, int32_t nseg,
+                                                                const int32_t* __restrict__ order,
+                                                                double* __restrict__ C) {
+    const int64_t q = xcd_logical<8>(blockIdx.x);
+    if (q >= nseg) return;   // uniform over the workgroup
+    const int64_t s = order ? order[q] : q;
+    lds_block_bf16x3(Ahi, Alo, Bhi_t, Blo_t, prodA, prodB, seg[s], seg[s + 1], C + (size_t)s * (64 * 64));
 }
 
 template <int BS>
@@ -918,20 +938,40 @@ void launch_numeric(const NumericArgs& a, hipStream_t s) {
 
 // ------------------------------------------------- a batch of multiplies
 //
-// Work item i of the batch is one wave's tile of one C block. Problem p owns
-// items item_base[p] .. item_base[p+1]-1 (C blocks in Morton order, WPB tiles
-// each). Two schedules:
-//   flat:       one launch whose grid covers every item, one wave per
-//               workgroup in the XCD-run order above (the hardware
-//               dispatcher balances the uneven problems);
-//   persistent: a grid sized to fill the GPU once; each wave takes the next
-//               CHUNK items from a counter until none are left, so every
-//               wave exits after at most total/CHUNK + 1 rounds.
+// Work item i of the batch is one wave's tile of one C block (or, for the
+// b = 64 kernels that share operands through LDS, one C block and its
+// four-wave workgroup). Problem p owns items item_base[p] .. item_base[p+1]-1:
+// its C blocks in its launch order (Morton order, or grouped by inner index
+// where C blocks average under two block products), WPB tiles each. Problems
+// come largest first. Four schedules:
+//   flat:          one launch whose grid covers every item, one workgroup per
+//                  item in the XCD-run order above; the hardware dispatcher
+//                  balances the uneven problems;
+//   balanced:      a persistent grid of as many workgroups as fit on the GPU
+//                  at once; each takes a contiguous run of items holding an
+//                  equal share of the work (block products plus one per C
+//                  block, summed at plan creation), so no counter, no
+//                  dispatch per item and no tail of long items on few waves;
+//   xcd-dynamic:   a persistent grid whose workgroups take 4 items at a time
+//                  from a counter per XCD, over the flat grid's XCD runs;
+//   dynamic-16:    a persistent grid that takes 16 items at a time from one
+//                  counter until none are left.
+// Every schedule ends: a balanced workgroup after its run, a dynamic one at
+// its first grab past the end.
 
-template <class T, int BS>
-__device__ __forceinline__ void batch_item(const BatchProblem* __restrict__ probs,
-                                           const int64_t* __restrict__ item_base, int32_t nprob, int64_t it) {
-    constexpr int WPB = Geo<BS>::WPB;
+// A problem's arrays are addressed from the launch's base pointer, a kernel
+// argument: a pointer read out of memory would be a generic pointer to the
+// compiler, which then addresses every operand load and C store through the
+// flat address space (flat loads count against both wait counters, and a
+// wait for the next operands becomes a wait for all memory traffic, the
+// previous block's C stores included).
+template <class T>
+__device__ __forceinline__ T* at(const char* base, int64_t off) {
+    return (T*)(base + off);
+}
+
+template <int WPB>
+__device__ __forceinline__ int32_t batch_problem(const int64_t* __restrict__ item_base, int32_t nprob, int64_t it) {
     int32_t lo = 0, hi = nprob - 1;                  // last p with item_base[p] <= it
     while (lo < hi) {
         const int32_t mid = (lo + hi + 1) >> 1;
@@ -940,20 +980,105 @@ __device__ __forceinline__ void batch_item(const BatchProblem* __restrict__ prob
         else
             hi = mid - 1;
     }
-    const BatchProblem& P = probs[lo];
-    const int64_t local = it - item_base[lo];
-    const int64_t s = local / WPB;
-    const int sub = (int)(local - s * WPB);
-    const int32_t t0 = P.seg[s];
-    wave_block<T, BS>((const T*)P.A, (const T*)P.B, P.prodA, P.prodB, t0, P.seg[s + 1],
-                      (T*)P.C + (size_t)s * (BS * BS), sub, P.prodA[t0], P.prodB[t0]);
+    return lo;
+}
+
+template <class T, int BS>
+__device__ __forceinline__ void batch_item(const BatchProblem* __restrict__ probs, const char* __restrict__ base,
+                                           const int64_t* __restrict__ item_base, int32_t nprob, int64_t it) {
+    constexpr int WPB = Geo<BS>::WPB;
+    const int32_t p = batch_problem<WPB>(item_base, nprob, it);
+    const BatchProblem& P = probs[p];
+    const int64_t local = it - item_base[p];
+    const int64_t q = local / WPB;
+    const int sub = (int)(local - q * WPB);
+    const int32_t* prodA = at<const int32_t>(base, P.prodA);
+    const int32_t* prodB = at<const int32_t>(base, P.prodB);
+    const int32_t* seg = at<const int32_t>(base, P.seg);
+    const int64_t s = P.order >= 0 ? at<const int32_t>(base, P.order)[q] : q;
+    const int32_t t0 = seg[s];
+    wave_block<T, BS>(at<const T>(base, P.A), at<const T>(base, P.B), prodA, prodB, t0, seg[s + 1],
+                      at<T>(base, P.C) + (size_t)s * (BS * BS), sub, prodA[t0], prodB[t0]);
 }
 
 template <int BS>
 __device__ __forceinline__ void batch_item_bf16x3(const BatchProblem* __restrict__ probs,
+                                                  const char* __restrict__ base,
                                                   const int64_t* __restrict__ item_base, int32_t nprob,
                                                   int64_t it) {
     constexpr int WPB = (BS / 32) * (BS / 32);
+    const int32_t p = batch_problem<WPB>(item_base, nprob, it);
+    const BatchProblem& P = probs[p];
+    const int64_t local = it - item_base[p];
+    const int64_t q = local / WPB;
+    const int sub = (int)(local - q * WPB);
+    const int32_t* seg = at<const int32_t>(base, P.seg);
+    const int64_t s = P.order >= 0 ? at<const int32_t>(base, P.order)[q] : q;
+    wave_block_bf16x3<BS>(at<const uint16_t>(base, P.Ahi), at<const uint16_t>(base, P.Alo),
+                          at<const uint16_t>(base, P.Bhi_t), at<const uint16_t>(base, P.Blo_t),
+                          at<const int32_t>(base, P.prodA), at<const int32_t>(base, P.prodB), seg[s], seg[s + 1],
+                          at<double>(base, P.C) + (size_t)s * (BS * BS), sub);
+}
+
+// one C block of a b = 64 problem by a whole four-wave workgroup (LDS sharing)
+template <int KIND>
+__device__ __forceinline__ void batch_item_lds(const BatchProblem* __restrict__ probs, const char* __restrict__ base,
+                                               const int64_t* __restrict__ item_base, int32_t nprob, int64_t it) {
+    const int32_t p = batch_problem<1>(item_base, nprob, it);
+    const BatchProblem& P = probs[p];
+    const int64_t q = it - item_base[p];
+    const int32_t* seg = at<const int32_t>(base, P.seg);
+    const int32_t* prodA = at<const int32_t>(base, P.prodA);
+    const int32_t* prodB = at<const int32_t>(base, P.prodB);
+    const int64_t s = P.order >= 0 ? at<const int32_t>(base, P.order)[q] : q;
+    const int32_t t0 = seg[s], t1 = seg[s + 1];
+    if constexpr (KIND == 0)
+        lds_block_f64(at<const double>(base, P.A), at<const double>(base, P.B), prodA, prodB, t0, t1,
+                      at<double>(base, P.C) + (size_t)s * (64 * 64));
+    else if constexpr (KIND == 1)
+        lds_block_f32(at<const float>(base, P.A), at<const float>(base, P.B), prodA, prodB, t0, t1,
+                      at<float>(base, P.C) + (size_t)s * (64 * 64));
+    else
+        lds_block_bf16x3(at<const uint16_t>(base, P.Ahi), at<const uint16_t>(base, P.Alo),
+                         at<const uint16_t>(base, P.Bhi_t), at<const uint16_t>(base, P.Blo_t), prodA, prodB, t0,
+                         t1, at<double>(base, P.C) + (size_t)s * (64 * 64));
+}
+
+// Item dispatch for one (precision, block size, LDS sharing) instance; the
+// LDS instances exist at b = 64 only and run 256-thread workgroups.
+template <int KIND, int BS, bool LDS> struct Item {
+    static constexpr int THREADS = LDS ? 256 : 64;
+    static __device__ __forceinline__ void run(const BatchProblem* p, const char* base, const int64_t* ib, int32_t n,
+                                               int64_t it) {
+        if constexpr (LDS)
+            batch_item_lds<KIND>(p, base, ib, n, it);
+        else if constexpr (KIND == 0)
+            batch_item<double, BS>(p, base, ib, n, it);
+        else if constexpr (KIND == 1)
+            batch_item<float, BS>(p, base, ib, n, it);
+        else
+            batch_item_bf16x3<BS>(p, base, ib, n, it);
+    }
+};
+
+template <int KIND, int BS, bool LDS>
+__global__ __launch_bounds__(LDS ? 256 : 64) void k_batch_flat(const BatchProblem* __restrict__ probs,
+                                                                 const char* __restrict__ base,
+                                                                 const int64_t* __restrict__ item_base,
+                                                                 int32_t nprob) {
+    const int64_t it = LDS ? xcd_logical<8>(blockIdx.x) : xcd_logical<>(blockIdx.x);
+    if (it >= item_base[nprob]) return;
+    Item<KIND, BS, LDS>::run(probs, base, item_base, nprob, it);
+}
+
+// Work of every item, for the balanced schedule: the block products of its
+// C block plus one (the C block's own store and set-up).
+template <bool LDS>
+__global__ void k_batch_item_cost(const BatchProblem* __restrict__ probs, const char* __restrict__ base,
+                                  const int64_t* __restrict__ item_base, int32_t nprob, int wpb,
+                                  int64_t* __restrict__ cost) {
+    const int64_t it = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (it >= item_base[nprob]) return;
     int32_t lo = 0, hi = nprob - 1;
     while (lo < hi) {
         const int32_t mid = (lo + hi + 1) >> 1;
@@ -963,110 +1088,183 @@ __device__ __forceinline__ void batch_item_bf16x3(const BatchProblem* __restrict
             hi = mid - 1;
     }
     const BatchProblem& P = probs[lo];
-    const int64_t local = it - item_base[lo];
-    const int64_t s = local / WPB;
-    const int sub = (int)(local - s * WPB);
-    wave_block_bf16x3<BS>(P.Ahi, P.Alo, P.Bhi_t, P.Blo_t, P.prodA, P.prodB, P.seg[s], P.seg[s + 1],
-                          (double*)P.C + (size_t)s * (BS * BS), sub);
+    const int64_t q = (it - item_base[lo]) / wpb;
+    const int32_t* seg = at<const int32_t>(base, P.seg);
+    const int64_t s = P.order >= 0 ? at<const int32_t>(base, P.order)[q] : q;
+    cost[it] = (int64_t)(seg[s + 1] - seg[s]) + 1;
 }
 
-// Item dispatch for one (precision, block size) instance.
-template <int KIND, int BS> struct Item;
-template <int BS> struct Item<0, BS> {   // fp64
-    static __device__ __forceinline__ void run(const BatchProblem* p, const int64_t* ib, int32_t n, int64_t it) {
-        batch_item<double, BS>(p, ib, n, it);
+// first i in [0, n] with cum[i] >= v (cum ascending, cum[0] = 0)
+__device__ __forceinline__ int64_t lower_bound64(const int64_t* __restrict__ cum, int64_t n, int64_t v) {
+    int64_t lo = 0, hi = n;
+    while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (cum[mid] < v)
+            lo = mid + 1;
+        else
+            hi = mid;
     }
-};
-template <int BS> struct Item<1, BS> {   // fp32
-    static __device__ __forceinline__ void run(const BatchProblem* p, const int64_t* ib, int32_t n, int64_t it) {
-        batch_item<float, BS>(p, ib, n, it);
-    }
-};
-template <int BS> struct Item<2, BS> {   // split bf16
-    static __device__ __forceinline__ void run(const BatchProblem* p, const int64_t* ib, int32_t n, int64_t it) {
-        batch_item_bf16x3<BS>(p, ib, n, it);
-    }
-};
-
-template <int KIND, int BS>
-__global__ __launch_bounds__(64) void k_batch_flat(const BatchProblem* __restrict__ probs,
-                                                   const int64_t* __restrict__ item_base, int32_t nprob) {
-    const int64_t it = xcd_logical<>(blockIdx.x);
-    if (it >= item_base[nprob]) return;
-    Item<KIND, BS>::run(probs, item_base, nprob, it);
+    return lo;
 }
 
-template <int KIND, int BS, int CHUNK>
-__global__ __launch_bounds__(64) void k_batch_persistent(const BatchProblem* __restrict__ probs,
-                                                          const int64_t* __restrict__ item_base, int32_t nprob,
-                                                          unsigned long long* __restrict__ counter) {
-    const int lane = threadIdx.x & 63;
+// Balanced schedule: workgroup r of the grid takes the items whose work
+// starts in [r W / G, (r + 1) W / G), W the batch's total work (cum[n]) --
+// a contiguous run, so neighbouring C blocks (and their operands) stay with
+// one wave.
+template <int KIND, int BS, bool LDS>
+__global__ __launch_bounds__(LDS ? 256 : 64) void k_batch_balanced(
+    const BatchProblem* __restrict__ probs, const char* __restrict__ base, const int64_t* __restrict__ item_base,
+    int32_t nprob, const int64_t* __restrict__ cum) {
+    const int64_t n = item_base[nprob];
+    const int64_t g = gridDim.x, r = blockIdx.x;
+    const int64_t W = cum[n];
+    const int64_t i0 = lower_bound64(cum, n, W * r / g);
+    const int64_t i1 = lower_bound64(cum, n, W * (r + 1) / g);
+    for (int64_t it = i0; it < i1; ++it) Item<KIND, BS, LDS>::run(probs, base, item_base, nprob, it);
+}
+
+// Per-XCD dynamic schedule: workgroup w is counted to XCD x = w % 8 and takes
+// XCD_GRAB consecutive positions at a time from that XCD's counter; XCD x's
+// positions are its runs of items x, x + 8, x + 16, ... (as the flat grid's
+// launch order gives them), so the workgroups of an XCD share a window of
+// neighbouring items in its L2 while each takes the next work as it gets
+// free. The next grab is taken while the current items run. Every item is
+// taken exactly once wherever a workgroup really runs (the counters are
+// device-wide atomics); a workgroup leaves at its first position past the end.
+constexpr int XCD_GRAB = 4;
+
+template <int KIND, int BS, bool LDS>
+__global__ __launch_bounds__(LDS ? 256 : 64) void k_batch_xcd(
+    const BatchProblem* __restrict__ probs, const char* __restrict__ base, const int64_t* __restrict__ item_base,
+    int32_t nprob, unsigned long long* __restrict__ counters) {
+    constexpr int LOG = LDS ? 8 : XCD_CHUNK_LOG;
+    __shared__ unsigned long long grab[2];
+    const int64_t total = item_base[nprob];
+    const int64_t x = blockIdx.x & 7;
+    unsigned long long* my = counters + 8 * x;   // 64 bytes apart
+    if (threadIdx.x == 0) grab[0] = atomicAdd(my, (unsigned long long)XCD_GRAB);
+    __syncthreads();
+    for (int k = 0;; k ^= 1) {
+        const int64_t first = (int64_t)grab[k];
+        if (threadIdx.x == 0) grab[k ^ 1] = atomicAdd(my, (unsigned long long)XCD_GRAB);   // the next grab
+        bool done = false;
+        for (int64_t pos = first; pos < first + XCD_GRAB; ++pos) {
+            const int64_t it = ((((pos >> LOG) << 3) + x) << LOG) | (pos & ((int64_t(1) << LOG) - 1));
+            if (it >= total) {   // positions map to increasing items: all later ones are past the end too
+                done = true;
+                break;
+            }
+            Item<KIND, BS, LDS>::run(probs, base, item_base, nprob, it);
+        }
+        __syncthreads();   // the next grab is in place, and every wave has read the current one
+        if (done) break;
+    }
+}
+
+template <int KIND, int BS, bool LDS, int CHUNK>
+__global__ __launch_bounds__(LDS ? 256 : 64) void k_batch_persistent(
+    const BatchProblem* __restrict__ probs, const char* __restrict__ base, const int64_t* __restrict__ item_base,
+    int32_t nprob, unsigned long long* __restrict__ counter) {
+    __shared__ unsigned long long grab;
     const int64_t total = item_base[nprob];
     while (true) {
-        unsigned long long base = 0;
-        if (lane == 0) base = atomicAdd(counter, (unsigned long long)CHUNK);
-        base = __shfl(base, 0, 64);
-        if ((int64_t)base >= total) break;
-        const int64_t end = min((int64_t)base + CHUNK, total);
-        for (int64_t it = (int64_t)base; it < end; ++it) Item<KIND, BS>::run(probs, item_base, nprob, it);
+        if (threadIdx.x == 0) grab = atomicAdd(counter, (unsigned long long)CHUNK);
+        __syncthreads();
+        const int64_t first = (int64_t)grab;
+        __syncthreads();   // every wave has read grab before the next one is written
+        if (first >= total) break;
+        const int64_t end = min(first + CHUNK, total);
+        for (int64_t it = first; it < end; ++it) Item<KIND, BS, LDS>::run(probs, base, item_base, nprob, it);
     }
 }
 
-// Clears the work counter (a kernel rather than a memset, so the launch
+// Clears the work counters (a kernel rather than a memset, so the launch
 // sequence can be captured into a graph and replayed).
-__global__ void k_batch_reset(unsigned long long* counter) { *counter = 0ull; }
+__global__ void k_batch_reset(unsigned long long* counter, int n) {
+    if ((int)threadIdx.x < n) counter[threadIdx.x] = 0ull;
+}
 
-template <int KIND, int BS>
-static void launch_batch_kb(const BatchLaunch& L, hipStream_t s) {
-    if (L.variant == 0) {
-        const unsigned grid = xcd_grid<>(L.total_items);
-        k_batch_flat<KIND, BS><<<grid, 64, 0, s>>>(L.probs, L.item_base, L.nprob);
+// Workgroups that fit on the GPU at once for a persistent kernel (a multiple of 8).
+static int resident_grid(const void* kernel, int threads) {
+    static std::mutex mu;
+    static std::map<std::pair<const void*, int>, int> cache;
+    int dev = 0;
+    QT_HIP(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = cache.find({kernel, dev});
+    if (it != cache.end()) return it->second;
+    int cus = 0, per_cu = 0;
+    QT_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    QT_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, 0));
+    const int g = std::max(8, (cus * std::max(1, per_cu)) / 8 * 8);
+    cache[{kernel, dev}] = g;
+    return g;
+}
+
+template <int KIND, int BS, bool LDS>
+static void launch_batch_k(const BatchLaunch& L, hipStream_t s) {
+    constexpr int T = Item<KIND, BS, LDS>::THREADS;
+    const int64_t items = L.total_items;
+    if (L.schedule == 0) {
+        const unsigned grid = LDS ? xcd_grid<8>(items) : xcd_grid<>(items);
+        k_batch_flat<KIND, BS, LDS><<<grid, T, 0, s>>>(L.probs, L.base, L.item_base, L.nprob);
         QT_LAUNCH("k_batch_flat");
         return;
     }
-    k_batch_reset<<<1, 1, 0, s>>>(L.counter);
+    if (L.schedule == 1) {
+        // every workgroup resident at once (a multiple of 8), at most one per item
+        const int64_t res = resident_grid((const void*)k_batch_balanced<KIND, BS, LDS>, T);
+        const unsigned g = (unsigned)std::max<int64_t>(8, std::min<int64_t>(res, (items + 7) / 8 * 8));
+        k_batch_balanced<KIND, BS, LDS><<<g, T, 0, s>>>(L.probs, L.base, L.item_base, L.nprob, L.cum);
+        QT_LAUNCH("k_batch_balanced");
+        return;
+    }
+    if (L.schedule == 2) {
+        k_batch_reset<<<1, 64, 0, s>>>(L.counter, 64);
+        QT_LAUNCH("k_batch_reset");
+        const unsigned g = (unsigned)resident_grid((const void*)k_batch_xcd<KIND, BS, LDS>, T);
+        k_batch_xcd<KIND, BS, LDS><<<g, T, 0, s>>>(L.probs, L.base, L.item_base, L.nprob, L.counter);
+        QT_LAUNCH("k_batch_xcd");
+        return;
+    }
+    k_batch_reset<<<1, 64, 0, s>>>(L.counter, 1);
     QT_LAUNCH("k_batch_reset");
-    const unsigned g = (unsigned)L.persistent_grid;
-    if (L.variant == 1)
-        k_batch_persistent<KIND, BS, 1><<<g, 64, 0, s>>>(L.probs, L.item_base, L.nprob, L.counter);
-    else if (L.variant == 2)
-        k_batch_persistent<KIND, BS, 4><<<g, 64, 0, s>>>(L.probs, L.item_base, L.nprob, L.counter);
-    else
-        k_batch_persistent<KIND, BS, 16><<<g, 64, 0, s>>>(L.probs, L.item_base, L.nprob, L.counter);
+    const unsigned g = (unsigned)resident_grid((const void*)k_batch_persistent<KIND, BS, LDS, 16>, T);
+    k_batch_persistent<KIND, BS, LDS, 16><<<g, T, 0, s>>>(L.probs, L.base, L.item_base, L.nprob, L.counter);
     QT_LAUNCH("k_batch_persistent");
 }
 
-template <int KIND, int BS>
-static int persistent_grid_kb() {
-    int dev = 0, cus = 0, per_cu = 0;
-    QT_HIP(hipGetDevice(&dev));
-    QT_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-    QT_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch_persistent<KIND, BS, 4>, 64, 0));
-    return std::max(1, cus * std::max(1, per_cu));
+void batch_item_costs(const BatchLaunch& L, int64_t* cost, hipStream_t s) {
+    if (L.total_items <= 0) return;
+    const int wpb = (L.b == 64 && !L.lds) ? 4 : 1;
+    const unsigned g = (unsigned)((L.total_items + 255) / 256);
+    if (L.lds)
+        k_batch_item_cost<true><<<g, 256, 0, s>>>(L.probs, L.base, L.item_base, L.nprob, wpb, cost);
+    else
+        k_batch_item_cost<false><<<g, 256, 0, s>>>(L.probs, L.base, L.item_base, L.nprob, wpb, cost);
+    QT_LAUNCH("k_batch_item_cost");
 }
-
-#define QT_BATCH_DISPATCH(FN, ...)                                                  \
-    do {                                                                            \
-        const int kind = (prec == QT_F64) ? 0 : (prec == QT_F32) ? 1 : 2;           \
-        if (kind == 0 && b == 16) return FN<0, 16>(__VA_ARGS__);                    \
-        if (kind == 0 && b == 32) return FN<0, 32>(__VA_ARGS__);                    \
-        if (kind == 0 && b == 64) return FN<0, 64>(__VA_ARGS__);                    \
-        if (kind == 1 && b == 16) return FN<1, 16>(__VA_ARGS__);                    \
-        if (kind == 1 && b == 32) return FN<1, 32>(__VA_ARGS__);                    \
-        if (kind == 1 && b == 64) return FN<1, 64>(__VA_ARGS__);                    \
-        if (kind == 2 && b == 32) return FN<2, 32>(__VA_ARGS__);                    \
-        if (kind == 2 && b == 64) return FN<2, 64>(__VA_ARGS__);                    \
-        fail(QT_ERR_UNSUPPORTED, "no batch kernel for this block size and precision"); \
-    } while (0)
-
-int batch_persistent_grid(int b, qt_prec prec) { QT_BATCH_DISPATCH(persistent_grid_kb); }
 
 void launch_batch(const BatchLaunch& L, hipStream_t s) {
     if (L.total_items <= 0) return;
-    if (L.variant < 0 || L.variant > 3) fail(QT_ERR_ARG, "unknown batch schedule");
+    if (L.schedule < 0 || L.schedule >= kBatchSchedules) fail(QT_ERR_ARG, "unknown batch schedule");
+    const int kind = (L.prec == QT_F64) ? 0 : (L.prec == QT_F32) ? 1 : 2;
     const int b = L.b;
-    const qt_prec prec = L.prec;
-    QT_BATCH_DISPATCH(launch_batch_kb, L, s);
+    if (L.lds && b != 64) fail(QT_ERR_ARG, "LDS-sharing batch kernels need b = 64");
+    if (L.lds) {
+        if (kind == 0) return launch_batch_k<0, 64, true>(L, s);
+        if (kind == 1) return launch_batch_k<1, 64, true>(L, s);
+        return launch_batch_k<2, 64, true>(L, s);
+    }
+    if (kind == 0 && b == 16) return launch_batch_k<0, 16, false>(L, s);
+    if (kind == 0 && b == 32) return launch_batch_k<0, 32, false>(L, s);
+    if (kind == 0 && b == 64) return launch_batch_k<0, 64, false>(L, s);
+    if (kind == 1 && b == 16) return launch_batch_k<1, 16, false>(L, s);
+    if (kind == 1 && b == 32) return launch_batch_k<1, 32, false>(L, s);
+    if (kind == 1 && b == 64) return launch_batch_k<1, 64, false>(L, s);
+    if (kind == 2 && b == 32) return launch_batch_k<2, 32, false>(L, s);
+    if (kind == 2 && b == 64) return launch_batch_k<2, 64, false>(L, s);
+    fail(QT_ERR_UNSUPPORTED, "no batch kernel for this block size and precision");
 }
 
 }  // namespace qt

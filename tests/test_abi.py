@@ -48,6 +48,9 @@ def test_null_handles_rejected():
     assert qt.lib.qt_probe_mfma(0, None, None) == qt.QT_ERR_ARG
     assert qt.lib.qt_to_blocks_noalloc(None, None, None, None, 0, None) == qt.QT_ERR_ARG
     assert qt.lib.qt_probe_batched(0, 32, 64000, None, None) == qt.QT_ERR_ARG
+    assert qt.lib.qt_tune_leaf_cached(None, None, 0, None, 1, b"c", None, None) == qt.QT_ERR_ARG
+    assert qt.lib.qt_plan_tune_cached(None, None, 1, b"c", None, None) == qt.QT_ERR_ARG
+    assert qt.lib.qt_tune_cache(None) == qt.QT_OK
     qt.lib.qt_free(None)
 
 

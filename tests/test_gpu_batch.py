@@ -55,7 +55,8 @@ def _check_against_oracle(C, A, B, leaf, tol):
     assert e_cw <= tol, e_cw
 
 
-@pytest.mark.parametrize("schedule", ["flat", "persistent-1", "persistent-4", "persistent-16"])
+@pytest.mark.parametrize("schedule", ["flat", "balanced", "xcd-dynamic", "dynamic-16", "balanced+morton",
+                                      "flat+morton"])
 def test_plan_matches_single_multiplies(qt, schedule):
     probs = _problems()
     leaf = 128
@@ -81,7 +82,7 @@ def test_plan_graph_replays(qt):
     probs = _problems(seed=1)
     hs = [(qt.from_blockmatrix(A, 64), qt.from_blockmatrix(B, 64)) for A, B in probs]
     plan = qt.Plan([a for a, _ in hs], [b for _, b in hs], "f64")
-    plan.set_schedule("persistent-4")
+    plan.set_schedule("balanced")
     plan.execute(graph=False)
     eager = [_blocks(plan.result(i), A, B) for i, (A, B) in enumerate(probs)]
     other = qt.from_blockmatrix(probs[1][0], 64)
@@ -115,11 +116,39 @@ def test_plan_precisions_and_block_sizes(qt, prec, b):
     _say("plan", prec, "b", b)
     plan = qt.Plan([a for a, _ in hs], [bb for _, bb in hs], prec)
     sched, times = plan.tune(reps=2)
-    assert sched in qt.PLAN_SCHEDULES and len(times) == 4
+    assert sched in times and qt.plan_config(sched) == plan.info()["config"]
+    assert len(times) >= 4 and all(t > 0 for t in times.values())
+    if b == 64:   # the tile shape is among the choices
+        assert "flat+wave-tiles" in times and "balanced+wave-tiles" in times
     plan.execute(graph=True)
     for i, (A, B) in enumerate(probs):
         C = _blocks(plan.result(i), A, B)
         assert np.array_equal(C.V, singles[i].V)
+    plan.destroy()
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32", "bf16x3"])
+def test_plan_every_config_bitwise_at_b64(qt, prec):
+    """At b = 64 every configuration (schedules, launch orders, LDS-shared or
+    per-wave tiles) gives bitwise the single multiply's result, on problems
+    with and without a launch order of their own."""
+    rng = np.random.default_rng(8)
+    b = 64
+    probs = [(random_pattern(rng, 24, 24, 0.04, b), random_pattern(rng, 24, 24, 0.04, b)),   # ~1 product per C block
+             (wl.decay3d(192, 12.0, 16, b, seed=11), wl.decay3d(192, 12.0, 16, b, seed=12)),
+             (random_pattern(rng, 7, 11, 0.4, b), random_pattern(rng, 11, 5, 0.4, b))]
+    hs = [(qt.from_blockmatrix(A, 2 * b), qt.from_blockmatrix(B, 2 * b)) for A, B in probs]
+    singles = [_blocks(qt.multiply(a, bb, prec), A, B) for (a, bb), (A, B) in zip(hs, probs)]
+    plan = qt.Plan([a for a, _ in hs], [bb for _, bb in hs], prec)
+    for c in range(qt.PLAN_CONFIGS):
+        name = qt.plan_config_name(c)
+        _say("plan b=64", prec, name)
+        plan.set_schedule(name)
+        plan.execute(graph=(c % 2 == 0))
+        for i, (A, B) in enumerate(probs):
+            C = _blocks(plan.result(i), A, B)
+            assert np.array_equal(positions(C), positions(singles[i])), (name, i)
+            assert np.array_equal(C.V, singles[i].V), (name, i)
     plan.destroy()
 
 
@@ -145,3 +174,36 @@ def test_tune_leaf(qt):
     hb = qt.from_blockmatrix(A, best)
     C = _blocks(qt.multiply(hb, hb), A, A)
     _check_against_oracle(C, A, A, best, 1e-12)
+
+
+def test_tuning_cache_file(qt, tmp_path):
+    """The tuners' choices go to the cache file and come back from it: the
+    first call times and stores, a repeat (also after re-reading the file)
+    returns the stored choice without timing, and a plan is set to it."""
+    path = str(tmp_path / "tune.txt")
+    A = wl.decay3d(512, 16.0, 16, 32, seed=13)
+    h = qt.from_blockmatrix(A, 64)
+    qt.tune_cache(path)
+    try:
+        leaf, cached = qt.tune_leaf_cached(h, h, "decay n2^9 test", "f64", reps=1)
+        assert not cached and leaf in (32, 64, 128, 256)
+        text = open(path).read()
+        assert "leaf decay n2^9 test" in text and ("\t%d\n" % leaf) in text
+        assert qt.tune_leaf_cached(h, h, "decay n2^9 test", "f64", reps=1) == (leaf, True)
+        qt.tune_cache(path)                                   # read the file again
+        assert qt.tune_leaf_cached(h, h, "decay n2^9 test", "f64", reps=1) == (leaf, True)
+        assert qt.tune_leaf_cached(h, h, "decay n2^9 test", "f32", reps=1)[1] is False   # another precision
+        probs = _problems(seed=3)[:3]
+        hs = [(qt.from_blockmatrix(a, 64), qt.from_blockmatrix(b, 64)) for a, b in probs]
+        plan = qt.Plan([a for a, _ in hs], [b for _, b in hs], "f64")
+        name, cached = plan.tune_cached("three problems", reps=1)
+        assert not cached and plan.info()["schedule"] == name
+        plan.set_schedule("dynamic-16" if name != "dynamic-16" else "flat")
+        assert plan.tune_cached("three problems", reps=1) == (name, True)
+        assert plan.info()["schedule"] == name                # set to the stored configuration
+        plan.execute()
+        for i, (a, b) in enumerate(probs):
+            _check_against_oracle(_blocks(plan.result(i), a, b), a, b, 64, 1e-12)
+        plan.destroy()
+    finally:
+        qt.tune_cache(None)
