@@ -64,7 +64,7 @@ def load(path: str):
     lib.qo_multiply.restype = ctypes.c_int
     lib.qo_multiply.argtypes = [i64, i64, i64, i32p, i32p, f64p,
                                 i64, i64, i64, i32p, i32p, f64p,
-                                ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_int,
                                 ctypes.POINTER(ctypes.c_void_p)]
     lib.qo_result_nnz.restype = i64
     lib.qo_result_nnz.argtypes = [ctypes.c_void_p]
@@ -74,6 +74,8 @@ def load(path: str):
     lib.qo_result_copy.argtypes = [ctypes.c_void_p, i32p, i32p, f64p]
     lib.qo_result_stats.restype = None
     lib.qo_result_stats.argtypes = [ctypes.c_void_p] + [ctypes.POINTER(ctypes.c_int64)] * 4
+    lib.qo_result_pruned.restype = None
+    lib.qo_result_pruned.argtypes = [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]
     lib.qo_result_free.restype = None
     lib.qo_result_free.argtypes = [ctypes.c_void_p]
     lib.qo_add.restype = ctypes.c_int
@@ -96,15 +98,19 @@ class OracleStats:
     c_nodes: np.ndarray        # non-NIL nodes of C per level
     block_products: int        # leaf block products A(i,k) B(k,j)
     leaf_block_adds: int       # block additions inside leaf adds
+    pruned_tasks: np.ndarray = None    # multiply tasks dropped by the norm threshold, per level
+    pruned_products: int = 0           # block products dropped by it
 
 
 def multiply(A: BlockMatrix, B: BlockMatrix, leaf: int, use_abs: bool = False,
-             par_levels: int = 3, threads: int | None = None, lib=None):
+             par_levels: int = 3, threads: int | None = None, lib=None, tau: float = 0.0):
     """C = A*B (or |A|*|B|) by the quadtree algorithm; returns (C, stats).
 
     C lists its blocks in row-major (I, J) order. ``threads`` caps the OpenMP
     thread count for this call (None: the OpenMP default). ``lib`` selects
-    another compiled copy of the oracle (see ``load``).
+    another compiled copy of the oracle (see ``load``). ``tau`` > 0 drops every
+    multiply task and block product whose operands' Frobenius norms multiply
+    to less than tau (the norm-thresholded product; tau = 0 is exact).
     """
     lib = _lib() if lib is None else lib
     if A.b != B.b:
@@ -121,7 +127,7 @@ def multiply(A: BlockMatrix, B: BlockMatrix, leaf: int, use_abs: bool = False,
                          _ptr(Va, ctypes.c_double),
                          B.n_rows, B.n_cols, B.nnz, _ptr(Ib, ctypes.c_int32), _ptr(Jb, ctypes.c_int32),
                          _ptr(Vb, ctypes.c_double),
-                         b, leaf, 1 if use_abs else 0, par_levels if threads != 1 else 0,
+                         b, leaf, 1 if use_abs else 0, float(tau), par_levels if threads != 1 else 0,
                          ctypes.byref(out))
     if rc != 0:
         raise OracleError(rc)
@@ -137,10 +143,13 @@ def multiply(A: BlockMatrix, B: BlockMatrix, leaf: int, use_abs: bool = False,
         nodes = np.zeros(nl, np.int64)
         st = np.zeros(2, np.int64)
         lib.qo_result_stats(out, *[_ptr(x, ctypes.c_int64) for x in (mul, add, nodes, st)])
+        ptasks = np.zeros(nl, np.int64)
+        pprods = np.zeros(1, np.int64)
+        lib.qo_result_pruned(out, _ptr(ptasks, ctypes.c_int64), _ptr(pprods, ctypes.c_int64))
     finally:
         lib.qo_result_free(out)
     C = BlockMatrix(A.n_rows, B.n_cols, b, I, J, V, {"from": "oracle", "leaf": leaf})
-    stats = OracleStats(mul, add, nodes, int(st[0]), int(st[1]))
+    stats = OracleStats(mul, add, nodes, int(st[0]), int(st[1]), ptasks, int(pprods[0]))
     return C, stats
 
 

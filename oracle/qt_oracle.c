@@ -59,6 +59,8 @@ struct qo_node {
     int is_leaf;
     qo_node *child[4];   /* internal: quadrant (m, n) at index 2*m + n; NULL is NIL */
     double **blk;        /* leaf: lb*lb blocks, row-major (i*lb + j); NULL = zero block */
+    double n2;           /* input trees: squared Frobenius norm of the submatrix */
+    double *bn2;         /* input leaves: squared Frobenius norm of every block (lb*lb) */
 };
 
 typedef struct {
@@ -66,11 +68,14 @@ typedef struct {
     int lb;              /* blocks per leaf side */
     int L;               /* leaf level (root is level 0) */
     int use_abs;         /* multiply |A| by |B| (for error bounds) */
+    double tau2;         /* norm threshold squared: drop what has ||A|| ||B|| < tau (0: none) */
     int par_levels;      /* spawn OpenMP tasks above this depth */
     int64_t mul_tasks[QO_MAX_LEVELS];
     int64_t add_tasks[QO_MAX_LEVELS];
     int64_t block_products;
     int64_t leaf_block_adds;
+    int64_t pruned_tasks[QO_MAX_LEVELS];   /* multiply tasks dropped by the norm threshold */
+    int64_t pruned_products;               /* block products dropped by it */
 } qo_ctx;
 
 typedef struct {
@@ -83,6 +88,8 @@ typedef struct {
     int64_t block_products;
     int64_t leaf_block_adds;
     int64_t nodes_per_level[QO_MAX_LEVELS];   /* non-NIL nodes of C per level */
+    int64_t pruned_tasks[QO_MAX_LEVELS];
+    int64_t pruned_products;
 } qo_result;
 
 /* ------------------------------------------------------------------ trees */
@@ -98,6 +105,14 @@ static qo_node *node_new(int is_leaf, int lb) {
     return n;
 }
 
+/* Squared Frobenius norm of a b x b block: the squares of its entries summed
+ * in row-major order. */
+static double block_norm2(const double *x, int b) {
+    double s = 0.0;
+    for (int e = 0; e < b * b; ++e) s += x[e] * x[e];
+    return s;
+}
+
 /* Free a tree. Input trees point into caller memory (own_blocks = 0). */
 static void tree_free(qo_node *n, int lb, int own_blocks) {
     if (!n) return;
@@ -105,6 +120,7 @@ static void tree_free(qo_node *n, int lb, int own_blocks) {
         if (own_blocks)
             for (int q = 0; q < lb * lb; ++q) free(n->blk[q]);
         free(n->blk);
+        free(n->bn2);
     } else {
         for (int c = 0; c < 4; ++c) tree_free(n->child[c], lb, own_blocks);
     }
@@ -122,10 +138,18 @@ static qo_node *tree_build(const int32_t *I, const int32_t *J, const double *V,
     if (side == lb) {
         qo_node *n = node_new(1, lb);
         if (!n) { *err = QO_ERR_OOM; return NULL; }
+        n->bn2 = (double *)calloc((size_t)lb * lb, sizeof(double));
+        if (!n->bn2) { tree_free(n, lb, 0); *err = QO_ERR_OOM; return NULL; }
         for (int64_t t = 0; t < cnt; ++t) {
             int64_t i = I[idx[t]] - r0, j = J[idx[t]] - c0;
             n->blk[i * lb + j] = (double *)(V + (size_t)idx[t] * b * b);
         }
+        /* norms: every block's, and the leaf's as their sum (row-major block order) */
+        for (int q = 0; q < lb * lb; ++q)
+            if (n->blk[q]) {
+                n->bn2[q] = block_norm2(n->blk[q], b);
+                n->n2 += n->bn2[q];
+            }
         return n;
     }
     int64_t half = side / 2;
@@ -154,6 +178,8 @@ static qo_node *tree_build(const int32_t *I, const int32_t *J, const double *V,
     }
     free(part);
     if (*err || !any) { tree_free(n, lb, 0); return NULL; }
+    for (int q = 0; q < 4; ++q)   /* a node's squared norm: the sum of its children's */
+        if (n->child[q]) n->n2 += n->child[q]->n2;
     return n;
 }
 
@@ -178,13 +204,15 @@ static qo_node *leaf_multiply(qo_ctx *ctx, const qo_node *A, const qo_node *B, i
     int lb = ctx->lb, b = ctx->b;
     qo_node *X = node_new(1, lb);
     if (!X) { *err = QO_ERR_OOM; return NULL; }
-    int64_t prods = 0;
+    int64_t prods = 0, pruned = 0;
     int any = 0;
     for (int i = 0; i < lb; ++i)
         for (int j = 0; j < lb; ++j)
             for (int k = 0; k < lb; ++k) {
                 const double *a = A->blk[i * lb + k], *x = B->blk[k * lb + j];
                 if (!a || !x) continue;
+                /* a block product of negligible norm is dropped (with tau = 0, none) */
+                if (A->bn2[i * lb + k] * B->bn2[k * lb + j] < ctx->tau2) { ++pruned; continue; }
                 double **dst = &X->blk[i * lb + j];
                 if (!*dst) {
                     *dst = (double *)calloc((size_t)b * b, sizeof(double));
@@ -196,6 +224,8 @@ static qo_node *leaf_multiply(qo_ctx *ctx, const qo_node *A, const qo_node *B, i
             }
 #pragma omp atomic
     ctx->block_products += prods;
+#pragma omp atomic
+    ctx->pruned_products += pruned;
     if (!any) { tree_free(X, lb, 1); return NULL; }
     return X;
 }
@@ -247,6 +277,13 @@ static qo_node *qt_add(qo_ctx *ctx, int level, qo_node *X, qo_node *Y) {
 
 static qo_node *qt_mul(qo_ctx *ctx, int level, const qo_node *A, const qo_node *B, int *err) {
     if (!A || !B) return NULL;                       /* fallback: NIL */
+    /* a product of negligible norm is NIL as well: every block product below
+     * has a norm product at most this one (with tau = 0, nothing is dropped) */
+    if (A->n2 * B->n2 < ctx->tau2) {
+#pragma omp atomic
+        ctx->pruned_tasks[level] += 1;
+        return NULL;
+    }
 #pragma omp atomic
     ctx->mul_tasks[level] += 1;
     if (level == ctx->L) return leaf_multiply(ctx, A, B, err);
@@ -353,12 +390,22 @@ static int is_pow2(int64_t x) { return x > 0 && (x & (x - 1)) == 0; }
  * C = A * B (or |A| * |B| when use_abs != 0).
  * Dimensions are scalar; b is the block size, leaf the leaf dimension
  * (a power-of-two multiple of b). On success *out holds the result.
+ *
+ * tau > 0 makes it the norm-thresholded product the paper's conclusions
+ * point to (storing each submatrix's Frobenius norm in the quadtree, after
+ * Bock and Challacombe): every node of the input trees carries its squared
+ * Frobenius norm, a multiply task whose operands have ||A|| ||B|| < tau is
+ * NIL, and at the leaves every block product with ||A(i,k)|| ||B(k,j)|| < tau
+ * is left out (compared as squares). A node's norm bounds the norm of every
+ * block below it, so the task rule never drops a block product the block
+ * rule would keep: C(I,J) is the sum over the K with ||A(I,K)|| ||B(K,J)|| >=
+ * tau, present iff one such K exists. tau = 0 is the exact product.
  */
 int qo_multiply(int64_t a_rows, int64_t a_cols, int64_t a_nnz,
                 const int32_t *Ia, const int32_t *Ja, const double *Va,
                 int64_t b_rows, int64_t b_cols, int64_t b_nnz,
                 const int32_t *Ib, const int32_t *Jb, const double *Vb,
-                int b, int leaf, int use_abs, int par_levels, qo_result **out) {
+                int b, int leaf, int use_abs, double tau, int par_levels, qo_result **out) {
     *out = NULL;
     if (b <= 0 || leaf <= 0 || a_rows < 0 || a_cols < 0 || b_rows < 0 || b_cols < 0)
         return QO_ERR_ARG;
@@ -398,7 +445,9 @@ int qo_multiply(int64_t a_rows, int64_t a_cols, int64_t a_nnz,
 
     qo_ctx ctx;
     memset(&ctx, 0, sizeof(ctx));
+    if (!(tau >= 0.0)) { tree_free(A, lb, 0); tree_free(B, lb, 0); free(res); return QO_ERR_ARG; }
     ctx.b = b; ctx.lb = lb; ctx.L = L; ctx.use_abs = use_abs; ctx.par_levels = par_levels;
+    ctx.tau2 = tau * tau;
     qo_node *C = NULL;
 #pragma omp parallel
 #pragma omp single
@@ -428,8 +477,10 @@ int qo_multiply(int64_t a_rows, int64_t a_cols, int64_t a_nnz,
     tree_free(C, lb, 1);
     memcpy(res->mul_tasks, ctx.mul_tasks, sizeof(ctx.mul_tasks));
     memcpy(res->add_tasks, ctx.add_tasks, sizeof(ctx.add_tasks));
+    memcpy(res->pruned_tasks, ctx.pruned_tasks, sizeof(ctx.pruned_tasks));
     res->block_products = ctx.block_products;
     res->leaf_block_adds = ctx.leaf_block_adds;
+    res->pruned_products = ctx.pruned_products;
     *out = res;
     return QO_OK;
 }
@@ -540,6 +591,12 @@ void qo_result_stats(const qo_result *r, int64_t *mul_tasks, int64_t *add_tasks,
     }
     stats[0] = r->block_products;
     stats[1] = r->leaf_block_adds;
+}
+
+/* Multiply tasks dropped by the norm threshold per level, and block products. */
+void qo_result_pruned(const qo_result *r, int64_t *tasks, int64_t *products) {
+    for (int l = 0; l <= r->L; ++l) tasks[l] = r->pruned_tasks[l];
+    *products = r->pruned_products;
 }
 
 void qo_result_free(qo_result *r) {

@@ -94,3 +94,54 @@ def symmetric_from_upper(U: BlockMatrix) -> BlockMatrix:
     J = np.concatenate([U.J, U.I[k]])
     V = np.concatenate([U.V, U.V[k].transpose(0, 2, 1)])
     return make(U.n_rows, U.n_cols, U.b, I, J, V)
+
+
+def norm_thresholded_by_definition(A, B, tau):
+    """C(I,J) = sum over K with ||A(I,K)||_F ||B(K,J)||_F >= tau of A(I,K) B(K,J),
+    straight from the definition (numpy block norms, a loop over all block
+    pairs): returns (C as BlockMatrix, kept products, dropped products, sum
+    of ||A(I,K)|| ||B(K,J)|| over the dropped ones)."""
+    na = np.linalg.norm(A.V.reshape(A.nnz, -1), axis=1)
+    nb = np.linalg.norm(B.V.reshape(B.nnz, -1), axis=1)
+    rows = {}
+    for t, (i, k) in enumerate(zip(A.I.tolist(), A.J.tolist())):
+        rows.setdefault(k, []).append((i, t))
+    acc = {}
+    kept = dropped = 0
+    dropped_norm = 0.0
+    for u, (k, j) in enumerate(zip(B.I.tolist(), B.J.tolist())):
+        for i, t in rows.get(k, []):
+            if na[t] * nb[u] >= tau:
+                kept += 1
+                key = (i, j)
+                acc[key] = acc.get(key, 0.0) + A.V[t] @ B.V[u]
+            else:
+                dropped += 1
+                dropped_norm += na[t] * nb[u]
+    keys = sorted(acc)
+    I = np.array([k[0] for k in keys], np.int32)
+    J = np.array([k[1] for k in keys], np.int32)
+    V = np.array([acc[k] for k in keys]).reshape(len(keys), A.b, B.b) if keys else np.zeros((0, A.b, A.b))
+    return BlockMatrix(A.n_rows, B.n_cols, A.b, I, J, V), kept, dropped, dropped_norm
+
+
+def tau_in_gap(A, B, quantile, rel_gap=1e-6):
+    """A threshold near the given quantile of the block products' norm
+    products, placed in the middle of a gap between two of them that is at
+    least rel_gap wide (relative), so that no product's norm lies within
+    rounding of it whatever the order its norms were summed in."""
+    na = np.linalg.norm(A.V.reshape(A.nnz, -1), axis=1)
+    nb = np.linalg.norm(B.V.reshape(B.nnz, -1), axis=1)
+    cols = {}
+    for t, k in enumerate(A.J.tolist()):
+        cols.setdefault(k, []).append(na[t])
+    prods = []
+    for u, k in enumerate(B.I.tolist()):
+        prods.extend(x * nb[u] for x in cols.get(k, []))
+    prods = np.sort(np.array(prods))
+    start = int(quantile * (len(prods) - 1))
+    for m in range(start, len(prods) - 1):
+        lo, hi = prods[m], prods[m + 1]
+        if hi > lo * (1 + rel_gap):
+            return float(np.sqrt(lo * hi))
+    raise ValueError("no gap")

@@ -14,7 +14,7 @@ import pytest
 
 import oracle
 import workloads as wl
-from tests._util import positions, random_pattern, to_dense
+from tests._util import norm_thresholded_by_definition, positions, random_pattern, tau_in_gap, to_dense
 
 MUTANTS = {
     "B child index transposed": ("const qo_node *x = B->child[2 * k + n];",
@@ -33,7 +33,20 @@ MUTANTS = {
     "local block sum restarts per t": ("s += a * x;", "s = a * x;"),
     "abs mode drops B's absolute value": ("if (use_abs) { a = fabs(a); x = fabs(x); }",
                                           "if (use_abs) { a = fabs(a); }"),
+    "task norm rule reads A twice": ("if (A->n2 * B->n2 < ctx->tau2) {", "if (A->n2 * A->n2 < ctx->tau2) {"),
+    "block norm rule transposes B's block": ("if (A->bn2[i * lb + k] * B->bn2[k * lb + j] < ctx->tau2)",
+                                             "if (A->bn2[i * lb + k] * B->bn2[j * lb + k] < ctx->tau2)"),
+    "block norm not squared": ("for (int e = 0; e < b * b; ++e) s += x[e] * x[e];",
+                               "for (int e = 0; e < b * b; ++e) s += fabs(x[e]);"),
+    "node norm keeps only the last child": ("if (n->child[q]) n->n2 += n->child[q]->n2;",
+                                            "if (n->child[q]) n->n2 = n->child[q]->n2;"),
 }
+
+
+def _graded(rng, nbr, nbc, fill, b):
+    M = random_pattern(rng, nbr, nbc, fill, b)
+    scale = 10.0 ** rng.uniform(-6, 0, size=M.nnz)
+    return wl.BlockMatrix(M.n_rows, M.n_cols, b, M.I, M.J, M.V * scale[:, None, None])
 
 
 def _battery(lib):
@@ -58,6 +71,16 @@ def _run_pins(lib):
         ok &= np.array_equal(positions(C), oracle.pattern_by_definition(A, B))
         Cabs, _ = oracle.multiply(A, B, lb * b, use_abs=True, lib=lib)
         ok &= bool(np.all(np.abs(to_dense(Cabs) - bound) <= 1e-13 * bound))
+    # the norm-thresholded product against its definition (graded block norms)
+    for b, lb, q in ((4, 2, 0.3), (2, 4, 0.6), (4, 8, 0.8)):
+        A = _graded(rng, 20, 24, 0.3, b)
+        B = _graded(rng, 24, 18, 0.3, b)
+        tau = tau_in_gap(A, B, q)
+        ref, kept, _, _ = norm_thresholded_by_definition(A, B, tau)
+        C, st = oracle.multiply(A, B, lb * b, tau=tau, lib=lib)
+        ok &= np.array_equal(positions(C), positions(ref)) and st.block_products == kept
+        if np.array_equal(positions(C), positions(ref)):
+            ok &= bool(np.allclose(C.V, ref.V, rtol=1e-12, atol=1e-300))
     g = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "banded1024_counts.json")))
     A = wl.config("banded1024")
     C, st = oracle.multiply(A, A, 256, lib=lib)

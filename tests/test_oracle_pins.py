@@ -14,7 +14,7 @@ import pytest
 
 import oracle
 import workloads as wl
-from tests._util import (block_permutation, compare, identity, make, positions,
+from tests._util import (norm_thresholded_by_definition, tau_in_gap, block_permutation, compare, identity, make, positions,
                          random_pattern, to_dense)
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
@@ -370,3 +370,61 @@ def test_truncation_ties_follow_z_order():
     assert sorted(zip(T.I.tolist(), T.J.tolist())) == [(1, 0), (1, 1)]
     T, k = oracle.truncate(M, float(np.sqrt(3.5)))
     assert k == 3 and list(zip(T.I.tolist(), T.J.tolist())) == [(1, 1)]
+
+
+# ------------------------------------------------- norm-thresholded product
+
+def _graded(rng, nbr, nbc, fill, b):
+    """Random pattern whose blocks are scaled over six decades, so that their
+    norm products spread over twelve."""
+    M = random_pattern(rng, nbr, nbc, fill, b)
+    scale = 10.0 ** rng.uniform(-6, 0, size=M.nnz)
+    return wl.BlockMatrix(M.n_rows, M.n_cols, b, M.I, M.J, M.V * scale[:, None, None])
+
+
+@pytest.mark.parametrize("b,lb,q", [(4, 2, 0.3), (2, 4, 0.6), (3, 1, 0.5), (4, 8, 0.8)])
+def test_norm_threshold_matches_definition(b, lb, q):
+    """The oracle's norm-thresholded product (tasks dropped at every level by
+    their node norms, block products by their block norms) equals the
+    definition by block norms alone, and keeps exactly its products
+    (Sec. 7: Frobenius norms per submatrix in the quadtree)."""
+    rng = np.random.default_rng(31 + lb)
+    A = _graded(rng, 20, 24, 0.3, b)
+    B = _graded(rng, 24, 18, 0.3, b)
+    tau = tau_in_gap(A, B, q)
+    ref, kept, dropped, _ = norm_thresholded_by_definition(A, B, tau)
+    C, st = oracle.multiply(A, B, lb * b, tau=tau)
+    assert np.array_equal(positions(C), positions(ref))
+    absAB, _ = oracle.multiply(A, B, lb * b, use_abs=True, tau=tau)
+    assert np.all(np.abs(C.V - ref.V) <= 1e-13 * absAB.V + 1e-300)
+    assert st.block_products == kept and kept + dropped == oracle.product_count(A, B)
+    assert 0 < kept and 0 < dropped
+    # the dropped block products are all that is missing, within their norm sum
+    Cx, _ = oracle.multiply(A, B, lb * b)
+    err = np.linalg.norm(to_dense(Cx) - to_dense(C))
+    _, _, _, bound = norm_thresholded_by_definition(A, B, tau)
+    assert err <= bound * (1 + 1e-12)
+
+
+def test_norm_threshold_zero_is_exact_and_prunes_tasks():
+    rng = np.random.default_rng(37)
+    A = _graded(rng, 32, 32, 0.2, 4)
+    C0, st0 = oracle.multiply(A, A, 16)
+    Ct, stt = oracle.multiply(A, A, 16, tau=0.0)
+    assert np.array_equal(positions(C0), positions(Ct)) and np.array_equal(C0.V, Ct.V)
+    assert stt.pruned_products == 0 and not stt.pruned_tasks.any()
+    # a threshold above every norm product leaves C empty, dropping the root task
+    big = float(np.linalg.norm(A.V)) ** 2 * 2
+    Cb, stb = oracle.multiply(A, A, 16, tau=big)
+    assert Cb.nnz == 0 and stb.pruned_tasks[0] == 1 and stb.block_products == 0
+    # tasks are dropped above the leaves too: with the lower-right quadrant of
+    # A scaled down, its products with itself fall below tau as a whole
+    low = (A.I >= 16) & (A.J >= 16)
+    As = wl.BlockMatrix(A.n_rows, A.n_cols, 4, A.I, A.J, A.V * np.where(low, 1e-9, 1.0)[:, None, None])
+    tau = tau_in_gap(As, As, 0.3)
+    C, st = oracle.multiply(As, As, 16, tau=tau)
+    assert st.pruned_tasks[1] >= 1
+    ref, kept, _, _ = norm_thresholded_by_definition(As, As, tau)
+    assert np.array_equal(positions(C), positions(ref)) and st.block_products == kept
+    with pytest.raises(oracle.OracleError):
+        oracle.multiply(A, A, 16, tau=-1.0)
