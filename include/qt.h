@@ -148,6 +148,40 @@ qt_status qt_multiply_ex(const qt_matrix* A, const qt_matrix* B, int32_t op_flag
                          qt_matrix** C);
 
 /*
+ * C = A * B without the negligible products: the product with a norm
+ * threshold that storing each submatrix's Frobenius norm in the quadtree
+ * makes possible (the paper's conclusions, Sec. 7, after Bock and
+ * Challacombe). Every node and block of A and B gets its squared Frobenius
+ * norm (made once per handle, as qt_norms); the traversal drops every pair
+ * (A node, B node) with ||A node||_F ||B node||_F < tau at any level, and the
+ * leaf step every block product with ||A(I,K)||_F ||B(K,J)||_F < tau. A
+ * node's norm bounds those of the blocks below it, so C(I,J) is the sum over
+ * the K with ||A(I,K)|| ||B(K,J)|| >= tau, present iff one such K exists, and
+ * ||C - A B||_F is at most the sum of ||A(I,K)|| ||B(K,J)|| over the dropped
+ * products. tau = 0 gives the exact product (as qt_multiply). Comparisons are
+ * made on squares in fp64; a product whose norm lies within rounding of tau
+ * may go either way. The norms are made on `stream` from the operands'
+ * values, and the traversal waits for them there; otherwise as qt_multiply
+ * (qt_stats counts the pairs and products actually formed).
+ * Errors: ARG (NULL argument, tau negative, NaN or above 1e150), SHAPE, OOM,
+ * DEVICE, UNSUPPORTED (a structure-only operand, as made for qt_sysq).
+ */
+qt_status qt_multiply_tau(const qt_matrix* A, const qt_matrix* B, double tau, qt_prec prec, void* stream,
+                          qt_matrix** C);
+
+/*
+ * Squared Frobenius norms (the per-submatrix norms of the paper's
+ * conclusions, Sec. 7): block_norm2 (may be NULL) receives ||M(I,J)||_F^2 of
+ * every stored block in (I, J) row-major order, as qt_to_blocks lists them;
+ * total_norm2 (may be NULL) receives ||M||_F^2 (the quadtree root's, summed
+ * up the tree). Both arrays are host or device memory as `where` says. The
+ * norms of every node are made once per handle (on `stream`) and kept with
+ * it. Synchronizes `stream` when `where` is QT_MEM_HOST.
+ * Errors: ARG, OOM, DEVICE, UNSUPPORTED (a structure-only matrix).
+ */
+qt_status qt_norms(const qt_matrix* M, double* block_norm2, double* total_norm2, qt_mem where, void* stream);
+
+/*
  * C = A + B (Algorithm 2, Sec. 3): the union of the two block patterns; a
  * block present in both is the sum of the two (fp64), a block present in one
  * is copied. A and B must agree in dimensions, block size and leaf size.

@@ -50,6 +50,10 @@ def _load():
     lib.qt_multiply.argtypes = [vp, vp, ctypes.c_int, vp, ctypes.POINTER(vp)]
     lib.qt_multiply_ex.restype = ctypes.c_int
     lib.qt_multiply_ex.argtypes = [vp, vp, i32, ctypes.c_int, vp, ctypes.POINTER(vp)]
+    lib.qt_multiply_tau.restype = ctypes.c_int
+    lib.qt_multiply_tau.argtypes = [vp, vp, ctypes.c_double, ctypes.c_int, vp, ctypes.POINTER(vp)]
+    lib.qt_norms.restype = ctypes.c_int
+    lib.qt_norms.argtypes = [vp, vp, vp, ctypes.c_int, vp]
     lib.qt_add.restype = ctypes.c_int
     lib.qt_add.argtypes = [vp, vp, vp, ctypes.POINTER(vp)]
     lib.qt_truncate.restype = ctypes.c_int
@@ -220,7 +224,7 @@ def _default_allocator():
     return use_torch_allocator()
 
 
-EXPORTS = ("qt_build", "qt_multiply", "qt_multiply_ex", "qt_add", "qt_truncate", "qt_sysq", "qt_info", "qt_to_blocks", "qt_to_blocks_noalloc", "qt_get_blocks", "qt_stats", "qt_levels", "qt_prepare", "qt_free",
+EXPORTS = ("qt_build", "qt_multiply", "qt_multiply_ex", "qt_multiply_tau", "qt_norms", "qt_add", "qt_truncate", "qt_sysq", "qt_info", "qt_to_blocks", "qt_to_blocks_noalloc", "qt_get_blocks", "qt_stats", "qt_levels", "qt_prepare", "qt_free",
            "qt_plan_create", "qt_plan_execute", "qt_plan_tune", "qt_plan_set_schedule", "qt_plan_result", "qt_plan_info",
            "qt_plan_destroy", "qt_tune_leaf", "qt_tune_cache", "qt_tune_leaf_cached", "qt_plan_tune_cached", "qt_profile", "qt_profile_read", "qt_probe_mfma", "qt_probe_batched", "qt_last_error", "qt_version",
            "qt_set_allocator")
@@ -333,6 +337,14 @@ class Matrix:
         _check(lib.qt_to_blocks(self._h, I.ctypes.data, J.ctypes.data, None, PREC["f64"], MEM_HOST,
                                 _stream_ptr(stream)))
         return I, J
+
+    def norms(self, stream=None):
+        """qt_norms: (squared Frobenius norm of every block in (I, J) order, of the matrix)."""
+        n = self.info()["nblocks"]
+        bn = np.empty(max(n, 1), np.float64)
+        tot = ctypes.c_double()
+        _check(lib.qt_norms(self._h, bn.ctypes.data, ctypes.byref(tot), MEM_HOST, _stream_ptr(stream)))
+        return bn[:n], tot.value
 
     def get_blocks(self, I, J, dtype: str = "f64", stream=None):
         """Chosen blocks (I[t], J[t]) as (values, found) numpy arrays (qt_get_blocks)."""
@@ -497,6 +509,14 @@ def multiply_ex(A: Matrix, B: Matrix, trans_a: bool = False, trans_b: bool = Fal
     flags = (OP_TRANS_A if trans_a else 0) | (OP_TRANS_B if trans_b else 0) | (OP_UPPER if upper else 0)
     out = ctypes.c_void_p()
     _check(lib.qt_multiply_ex(A.handle, B.handle, flags, PREC[prec], _stream_ptr(stream), ctypes.byref(out)))
+    return Matrix(out.value)
+
+
+def multiply_tau(A: Matrix, B: Matrix, tau: float, prec: str = "f64", stream=None) -> Matrix:
+    """qt_multiply_tau: C = A*B without the products whose operands' Frobenius
+    norms multiply to less than tau (at every quadtree level)."""
+    out = ctypes.c_void_p()
+    _check(lib.qt_multiply_tau(A.handle, B.handle, float(tau), PREC[prec], _stream_ptr(stream), ctypes.byref(out)))
     return Matrix(out.value)
 
 

@@ -12,6 +12,7 @@ void set_last_error(const std::string& m) { t_last_error = m; }
 
 void to_blocks(const qt_matrix*, int32_t*, int32_t*, void*, qt_prec, qt_mem, hipStream_t);
 void to_blocks_noalloc(const qt_matrix*, int32_t*, int32_t*, void*, qt_prec, hipStream_t);
+void norms_out(qt_matrix*, double*, double*, qt_mem, hipStream_t);
 void get_blocks(const qt_matrix*, int64_t, const int32_t*, const int32_t*, void*, int32_t*, qt_prec, qt_mem,
                 hipStream_t);
 qt_plan* plan_create(int32_t, const qt_matrix* const*, const qt_matrix* const*, qt_prec, hipStream_t);
@@ -162,6 +163,36 @@ qt_status qt_multiply_ex(const qt_matrix* A, const qt_matrix* B, int32_t op_flag
     op.tb = (op_flags & QT_OP_TRANS_B) ? 1 : 0;
     op.upper = (op_flags & QT_OP_UPPER) ? 1 : 0;
     *C = multiply(const_cast<qt_matrix*>(A), const_cast<qt_matrix*>(B), prec, (hipStream_t)stream, op);
+    return QT_OK;
+    QT_GUARD_END
+}
+
+qt_status qt_multiply_tau(const qt_matrix* A, const qt_matrix* B, double tau, qt_prec prec, void* stream,
+                          qt_matrix** C) {
+    if (!C) {
+        set_last_error("NULL output handle");
+        return QT_ERR_ARG;
+    }
+    *C = nullptr;
+    if (!A || !B || !(tau >= 0.0) || tau > 1e150) {
+        set_last_error("NULL operand, or tau negative, NaN or beyond 1e150");
+        return QT_ERR_ARG;
+    }
+    QT_GUARD_BEGIN
+    MulOp op;
+    op.tau2 = tau * tau;
+    *C = multiply(const_cast<qt_matrix*>(A), const_cast<qt_matrix*>(B), prec, (hipStream_t)stream, op);
+    return QT_OK;
+    QT_GUARD_END
+}
+
+qt_status qt_norms(const qt_matrix* M, double* block_norm2, double* total_norm2, qt_mem where, void* stream) {
+    if (!M || (where != QT_MEM_HOST && where != QT_MEM_DEVICE)) {
+        set_last_error("NULL matrix or bad memory kind");
+        return QT_ERR_ARG;
+    }
+    QT_GUARD_BEGIN
+    norms_out(const_cast<qt_matrix*>(M), block_norm2, total_norm2, where, (hipStream_t)stream);
     return QT_OK;
     QT_GUARD_END
 }

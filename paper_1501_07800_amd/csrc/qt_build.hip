@@ -781,6 +781,142 @@ void to_blocks_noalloc(const qt_matrix* M, int32_t* I, int32_t* J, void* values,
     rowmajor_copy(M, rk, perm, I, J, values, out_type, s);
 }
 
+// ------------------------------------------------------------ norms
+//
+// Squared Frobenius norms of a matrix and of every submatrix in its
+// quadtree (the paper's conclusions name such per-submatrix norms as an
+// addition to the library, after Bock and Challacombe): of every block, one
+// wave per block; of every leaf, the sum over its blocks; of every node
+// above, the sum over its present children. A node's squared norm is at
+// least each block's below it, whatever the order of the sums (every term is
+// non-negative and rounding is monotone), which is what lets a product be
+// dropped by its norm at any level.
+
+template <class T>
+__global__ __launch_bounds__(64) void k_block_norm2(const T* __restrict__ v, int64_t n, int bb,
+                                                   double* __restrict__ out) {
+    const int64_t t = blockIdx.x;
+    if (t >= n) return;
+    const T* x = v + (size_t)t * bb;
+    double s = 0.0;
+    for (int e = threadIdx.x; e < bb; e += 64) {
+        const double d = (double)x[e];
+        s += d * d;
+    }
+#pragma unroll
+    for (int d = 32; d > 0; d >>= 1) s += __shfl_xor(s, d, 64);
+    if (threadIdx.x == 0) out[t] = s;
+}
+
+__global__ void k_leaf_norm2(const int32_t* __restrict__ base, const uint64_t* __restrict__ mo, int64_t n,
+                             const double* __restrict__ bn2, double* __restrict__ out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int32_t b0 = base[i], cnt = __popcll(mo[i]);
+    double s = 0.0;
+    for (int32_t k = 0; k < cnt; ++k) s += bn2[b0 + k];
+    out[i] = s;
+}
+
+__global__ void k_node_norm2(const int32_t* __restrict__ child, int64_t n, const double* __restrict__ below,
+                             double* __restrict__ out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double s = 0.0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int32_t c = child[4 * i + q];
+        if (c >= 0) s += below[c];
+    }
+    out[i] = s;
+}
+
+void build_norms(qt_matrix* M, hipStream_t s) {
+    std::lock_guard<std::mutex> lk(M->mu);
+    if (M->vsrc) fail(QT_ERR_UNSUPPORTED, "norms of a structure-only matrix");
+    if (!M->bn2) {
+        const int L = M->L;
+        int64_t total = std::max<int64_t>(M->nblocks, 1) + M->leaves.n;
+        for (int l = 0; l < L; ++l) total += M->levels[l].n;
+        M->norms.alloc(total, s);
+        double* p = M->norms.p;
+        double* bn2 = p;
+        p += std::max<int64_t>(M->nblocks, 1);
+        const int bb = M->b * M->b;
+        if (M->nblocks > 0) {
+            if (M->vtype == QT_F64)
+                k_block_norm2<double><<<(unsigned)M->nblocks, 64, 0, s>>>(M->v64.p, M->nblocks, bb, bn2);
+            else
+                k_block_norm2<float><<<(unsigned)M->nblocks, 64, 0, s>>>(M->v32.p, M->nblocks, bb, bn2);
+            QT_LAUNCH("k_block_norm2");
+        }
+        std::vector<const double*> nn2(L + 1, nullptr);
+        double* below = p;
+        p += M->leaves.n;
+        if (M->leaves.n > 0) {
+            k_leaf_norm2<<<grid_for(M->leaves.n), 256, 0, s>>>(M->leaves.base.p, M->leaves.mask_mo.p, M->leaves.n,
+                                                              bn2, below);
+            QT_LAUNCH("k_leaf_norm2");
+        }
+        nn2[L] = below;
+        for (int l = L - 1; l >= 0; --l) {
+            double* here = p;
+            p += M->levels[l].n;
+            if (M->levels[l].n > 0) {
+                k_node_norm2<<<grid_for(M->levels[l].n), 256, 0, s>>>(M->levels[l].child.p, M->levels[l].n, below,
+                                                                     here);
+                QT_LAUNCH("k_node_norm2");
+            }
+            nn2[l] = here;
+            below = here;
+        }
+        M->nn2 = nn2;
+        M->bn2 = bn2;
+        form_mark(M->ev_norms, s);
+    }
+    form_ready(M->ev_norms, s);
+}
+
+__global__ void k_gather_f64(const double* __restrict__ src, const int32_t* __restrict__ idx, int64_t n,
+                             double* __restrict__ dst);   // dst[i] = src[idx[i]] (below)
+
+// The squared norms of M's blocks in (I, J) row-major order, and of M.
+void norms_out(qt_matrix* M, double* block_norm2, double* total_norm2, qt_mem where, hipStream_t s) {
+    build_norms(M, s);
+    const int64_t n = M->nblocks;
+    if (block_norm2 && n > 0) {
+        const int64_t npow2 = pow2_at_least(n);
+        DBuf<uint64_t> rk(npow2, s);
+        DBuf<int32_t> perm(npow2, s);
+        k_rowmajor_keys<<<grid_for(n), 256, 0, s>>>(M->bkey.p, n, M->n_cols / M->b, rk.p, perm.p);
+        QT_LAUNCH("k_rowmajor_keys");
+        bitonic_sort(rk.p, perm.p, n, s);
+        DBuf<double> tmp;
+        double* out = block_norm2;
+        if (where == QT_MEM_HOST) {
+            tmp.alloc(n, s);
+            out = tmp.p;
+        }
+        k_gather_f64<<<grid_for(n), 256, 0, s>>>(M->bn2, perm.p, n, out);
+        QT_LAUNCH("k_gather_f64");
+        if (where == QT_MEM_HOST) QT_HIP(hipMemcpyAsync(block_norm2, tmp.p, n * sizeof(double), hipMemcpyDeviceToHost, s));
+    }
+    if (total_norm2) {
+        // the root's squared norm (0 for an all-NIL matrix)
+        const bool any = M->L == 0 ? M->leaves.n > 0 : M->levels[0].n > 0;
+        if (!any) {
+            if (where == QT_MEM_HOST)
+                *total_norm2 = 0.0;
+            else
+                QT_HIP(hipMemsetAsync(total_norm2, 0, sizeof(double), s));
+        } else {
+            QT_HIP(hipMemcpyAsync(total_norm2, M->nn2[0], sizeof(double),
+                                  where == QT_MEM_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice, s));
+        }
+    }
+    if (where == QT_MEM_HOST) QT_HIP(hipStreamSynchronize(s));
+}
+
 // The full symmetric matrix S from its upper block triangle A, as structure
 // only: block (I, J), I <= J, of A is block (I, J) of S, and for I < J also
 // block (J, I) of S, read transposed. S holds no values; its block map points

@@ -174,7 +174,12 @@ struct qt_matrix {
     qt::DBuf<uint16_t> bf_hi_t, bf_lo_t; // same, each block transposed
     qt::DBuf<double> v64_cache;          // fp64 copy when vtype == QT_F32
     std::unique_ptr<qt_matrix> sym_full; // structure of the full symmetric matrix from this upper triangle
-    hipEvent_t ev_v32 = nullptr, ev_v64 = nullptr, ev_bf16 = nullptr;
+    hipEvent_t ev_v32 = nullptr, ev_v64 = nullptr, ev_bf16 = nullptr, ev_norms = nullptr;
+    // squared Frobenius norms (built on demand, like the forms above): of every
+    // block (Morton order), and of every node of every level (level L: leaves)
+    qt::DBuf<double> norms;
+    const double* bn2 = nullptr;
+    std::vector<const double*> nn2;
     qt::Histograms hist;                 // built once, under mu (build_histograms)
 
     // counters of the multiply that produced this matrix
@@ -192,7 +197,7 @@ struct qt_matrix {
     qt_matrix(const qt_matrix&) = delete;
     qt_matrix& operator=(const qt_matrix&) = delete;
     ~qt_matrix() {
-        for (hipEvent_t e : {ev_v32, ev_v64, ev_bf16})
+        for (hipEvent_t e : {ev_v32, ev_v64, ev_bf16, ev_norms})
             if (e) (void)hipEventDestroy(e);
     }
 };
@@ -228,6 +233,9 @@ void build_histograms(qt_matrix* M, hipStream_t s);   // fills M->hist (synchron
 const double* operand_f64(qt_matrix* M, hipStream_t s);
 const float* operand_f32(qt_matrix* M, hipStream_t s);
 void operand_bf16(qt_matrix* M, hipStream_t s);
+// the squared Frobenius norms of M's blocks and nodes (M->bn2, M->nn2), made
+// on s the first time and waited for on s afterwards
+void build_norms(qt_matrix* M, hipStream_t s);
 uint64_t morton2(uint32_t r, uint32_t c);
 
 // numeric.hip --------------------------------------------------------------
@@ -311,6 +319,7 @@ struct SymbolicOut {
 // of C on or above the block diagonal.
 struct MulOp {
     int ta = 0, tb = 0, upper = 0;
+    double tau2 = 0;          // > 0: drop pairs and block products with ||A||^2 ||B||^2 < tau2
 };
 // launch_order: also build the launch order of C's blocks that suits the
 // product, for a numeric kernel launched from out.na (a batch plan does not)

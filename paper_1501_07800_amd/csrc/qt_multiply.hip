@@ -134,7 +134,16 @@ struct TreeStep {
     int32_t* check;           // device total of child pairs, for the host check
     int ta, tb;               // operand used transposed: child (m, k) of op(A) is child (k, m) of A
     int upper;                // keep only C nodes on or above the block diagonal
+    const double* An2;        // squared norms of the operands' next-level nodes (nullptr: no
+    const double* Bn2;        // norm threshold): a child pair is dropped when An2 Bn2 < tau2
+    double tau2;
 };
+
+// Child a of op(A) and child b of op(B) form a pair: both present and, with
+// a norm threshold, the product of their norms not below it.
+__device__ __forceinline__ bool pair_kept(const TreeStep& st, int32_t a, int32_t b) {
+    return a >= 0 && b >= 0 && (!st.An2 || st.An2[a] * st.Bn2[b] >= st.tau2);
+}
 
 // Children of an operand node in the orientation of op(X): for a transposed
 // operand the off-diagonal children swap (quadrant (m, k) of X^T is (k, m) of X).
@@ -167,10 +176,10 @@ __device__ int64_t tree_count_node(const TreeStep& st, int32_t c, int lane) {
             const int32_t p = s0 + base + lane;
             const int4 a = op_children(st.Ach, st.fa[p], st.ta);   // A child (m, k) at 2m + k
             const int4 b = op_children(st.Bch, st.fb[p], st.tb);   // B child (k, n) at 2k + n
-            t0 += (a.x >= 0 && b.x >= 0) + (a.y >= 0 && b.z >= 0);
-            t1 += (a.x >= 0 && b.y >= 0) + (a.y >= 0 && b.w >= 0);
-            t2 += (a.z >= 0 && b.x >= 0) + (a.w >= 0 && b.z >= 0);
-            t3 += (a.z >= 0 && b.y >= 0) + (a.w >= 0 && b.w >= 0);
+            t0 += pair_kept(st, a.x, b.x) + pair_kept(st, a.y, b.z);
+            t1 += pair_kept(st, a.x, b.y) + pair_kept(st, a.y, b.w);
+            t2 += pair_kept(st, a.z, b.x) + pair_kept(st, a.w, b.z);
+            t3 += pair_kept(st, a.z, b.y) + pair_kept(st, a.w, b.w);
         }
     }
     if (quadrant_dropped(st.upper, st.ckey[c], 2)) t2 = 0;
@@ -239,8 +248,8 @@ __device__ void tree_fill_node(const TreeStep& st, int32_t c, int lane, int64_t 
         for (int mn = 0; mn < 4; ++mn) {
             const int m = mn >> 1, n = mn & 1;
             const bool keep = !(mn == 2 && drop_lower);
-            const bool e0 = keep && av[2 * m] >= 0 && bv[n] >= 0;           // k' = 0
-            const bool e1 = keep && av[2 * m + 1] >= 0 && bv[2 + n] >= 0;   // k' = 1
+            const bool e0 = keep && pair_kept(st, av[2 * m], bv[n]);           // k' = 0
+            const bool e1 = keep && pair_kept(st, av[2 * m + 1], bv[2 + n]);   // k' = 1
             const uint64_t m0 = __ballot(e0), m1 = __ballot(e1);
             int out = run[mn] + __popcll(m0 & below) + __popcll(m1 & below);
             if (e0) {
@@ -421,6 +430,9 @@ struct LeafStep {
     int upper;                // keep only blocks on or above the diagonal
     const int32_t* amap;      // structure-only A: its block t is held by its value source as amap[t]
     const int32_t* bmap;
+    const double* Abn2;       // squared block norms (nullptr: no norm threshold): a block product
+    const double* Bbn2;       // is dropped when Abn2 Bbn2 < tau2
+    double tau2;
 };
 
 // Lane t's value in every lane, for a t that is the same in every lane: a
@@ -444,8 +456,12 @@ __device__ __forceinline__ bool leaf_block_kept(const LeafStep& st, uint64_t lea
 // can add a block product at all are walked: some inner index k with column
 // k of the op(A) leaf and row k of the op(B) leaf both occupied. In an
 // unstructured product most leaf pairs have none (random65536: four in five).
+__device__ int leaf_lane_count_norms(const LeafStep& st, int32_t s0, int32_t len, int lane, int i, int j, int lb,
+                                     bool on);
+
 __device__ int leaf_lane_count(const LeafStep& st, int32_t s0, int32_t len, int lane, int i, int j, int lb,
                                bool on) {
+    if (st.Abn2) return leaf_lane_count_norms(st, s0, len, lane, i, j, lb, on);
     int cnt = 0;
     for (int32_t base = 0; base < len; base += 64) {
         const int32_t nb = min(64, len - base);
@@ -459,6 +475,51 @@ __device__ int leaf_lane_count(const LeafStep& st, int32_t s0, int32_t len, int 
             const uint64_t rat = lane_value(ra, t);
             const uint64_t cbt = lane_value(cb, t);
             if (on) cnt += __popc(mask_row(rat, i, lb) & mask_row(cbt, j, lb));
+        }
+    }
+    return cnt;
+}
+
+// Local Morton positions of A(i,k) and B(k,j) in the stored (untransposed) leaves.
+__device__ __forceinline__ void leaf_positions(const LeafStep& st, int i, int k, int j, uint32_t& qa, uint32_t& qb) {
+    qa = st.ta ? (uint32_t)morton_key((uint32_t)k, (uint32_t)i) : (uint32_t)morton_key((uint32_t)i, (uint32_t)k);
+    qb = st.tb ? (uint32_t)morton_key((uint32_t)j, (uint32_t)k) : (uint32_t)morton_key((uint32_t)k, (uint32_t)j);
+}
+
+// leaf_lane_count with a norm threshold: every candidate product A(i,k)
+// B(k,j) is looked at on its own, kept when its blocks' squared norms
+// multiply to at least tau2.
+__device__ int leaf_lane_count_norms(const LeafStep& st, int32_t s0, int32_t len, int lane, int i, int j, int lb,
+                                     bool on) {
+    int cnt = 0;
+    for (int32_t base = 0; base < len; base += 64) {
+        const int32_t nb = min(64, len - base);
+        uint64_t ra = 0, cb = 0, amo = 0, bmo = 0;
+        int32_t ab = 0, bb = 0;
+        if (lane < nb) {
+            const int32_t a = st.fa[s0 + base + lane], b = st.fb[s0 + base + lane];
+            ra = st.Arm[a];
+            cb = st.Bcm[b];
+            amo = st.Amo[a];
+            bmo = st.Bmo[b];
+            ab = st.Abase[a];
+            bb = st.Bbase[b];
+        }
+        for (uint64_t live = __ballot((mask_fold(ra, lb) & mask_fold(cb, lb)) != 0); live; live &= live - 1) {
+            const int t = __ffsll((unsigned long long)live) - 1;
+            uint32_t m = on ? (mask_row(lane_value(ra, t), i, lb) & mask_row(lane_value(cb, t), j, lb)) : 0u;
+            if (__ballot(m != 0) == 0) continue;
+            const uint64_t amot = lane_value(amo, t), bmot = lane_value(bmo, t);
+            const int32_t abt = (int32_t)lane_value((uint32_t)ab, t), bbt = (int32_t)lane_value((uint32_t)bb, t);
+            while (m) {
+                const int k = __ffs(m) - 1;
+                m &= m - 1;
+                uint32_t qa, qb;
+                leaf_positions(st, i, k, j, qa, qb);
+                const int32_t ia = abt + __popcll(amot & ((1ull << qa) - 1));
+                const int32_t ib = bbt + __popcll(bmot & ((1ull << qb) - 1));
+                cnt += st.Abn2[ia] * st.Bbn2[ib] >= st.tau2;
+            }
         }
     }
     return cnt;
@@ -533,15 +594,13 @@ __device__ void leaf_fill_node(const LeafStep& st, int32_t c, int lane, int64_t 
             while (m) {
                 const int k = __ffs(m) - 1;
                 m &= m - 1;
-                // local Morton position of A(i,k) / B(k,j) in the stored (untransposed) leaf
-                const uint32_t qa = st.ta ? (uint32_t)morton_key((uint32_t)k, (uint32_t)i)
-                                          : (uint32_t)morton_key((uint32_t)i, (uint32_t)k);
-                const uint32_t qb = st.tb ? (uint32_t)morton_key((uint32_t)j, (uint32_t)k)
-                                          : (uint32_t)morton_key((uint32_t)k, (uint32_t)j);
+                uint32_t qa, qb;   // local Morton positions of A(i,k) / B(k,j) in the stored leaves
+                leaf_positions(st, i, k, j, qa, qb);
+                const int32_t ia = abt + __popcll(amot & ((1ull << qa) - 1));
+                const int32_t ib = bbt + __popcll(bmot & ((1ull << qb) - 1));
+                if (st.Abn2 && st.Abn2[ia] * st.Bbn2[ib] < st.tau2) continue;   // dropped by its norm
                 if (out < st.P) {
                     // the block of the value source, with the transposition bit
-                    const int32_t ia = abt + __popcll(amot & ((1ull << qa) - 1));
-                    const int32_t ib = bbt + __popcll(bmot & ((1ull << qb) - 1));
                     st.prodA[out] = st.amap ? st.amap[ia] : (int32_t)((uint32_t)ia | (st.ta ? PROD_TRANS : 0u));
                     st.prodB[out] = st.bmap ? st.bmap[ib] : (int32_t)((uint32_t)ib | (st.tb ? PROD_TRANS : 0u));
                 }
@@ -1009,6 +1068,12 @@ void symbolic(qt_matrix* A, qt_matrix* B, qt_prec prec, hipStream_t s, SymbolicO
     if (op.upper && (op.ta ? A->n_cols : A->n_rows) != (op.tb ? B->n_rows : B->n_cols))
         fail(QT_ERR_SHAPE, "an upper-triangular product must be square");
     if (prec == QT_BF16X3 && A->b == 16) fail(QT_ERR_UNSUPPORTED, "split-bf16 path needs b = 32 or 64");
+    const bool prune = op.tau2 > 0;   // a norm threshold
+    if (prune && (op.ta || op.tb || op.upper || A->vsrc || B->vsrc))
+        fail(QT_ERR_UNSUPPORTED, "a norm threshold needs C = A * B of stored operands");
+    // with a norm threshold (or only the upper triangle) the counts known
+    // beforehand are bounds, not exact
+    const bool bounds = op.upper || prune;
     const int L = std::max(A->L, B->L);
     const int liftA = L - A->L, liftB = L - B->L;
     out.na = NumericArgs{};
@@ -1021,6 +1086,17 @@ void symbolic(qt_matrix* A, qt_matrix* B, qt_prec prec, hipStream_t s, SymbolicO
     const hipStream_t ss = side_stream();   // the traversal's stream
     build_histograms(A, ss);
     build_histograms(B, ss);
+    if (prune) {
+        // the norms read the operands' values, ready in order on the caller's
+        // stream: made there, and the traversal waits for them
+        build_norms(A, s);
+        build_norms(B, s);
+        hipEvent_t ready = nullptr;
+        QT_HIP(hipEventCreateWithFlags(&ready, hipEventDisableTiming));
+        QT_HIP(hipEventRecord(ready, s));
+        QT_HIP(hipStreamWaitEvent(ss, ready, 0));
+        QT_HIP(hipEventDestroy(ready));
+    }
 
     // pair counts per level and block products: exact, or upper bounds when
     // only the upper triangle of C is formed. Columns of op(A) are rows of A
@@ -1222,6 +1298,13 @@ void symbolic(qt_matrix* A, qt_matrix* B, qt_prec prec, hipStream_t s, SymbolicO
         st.ta = op.ta;
         st.tb = op.tb;
         st.upper = op.upper;
+        if (prune) {
+            // norms of the next level's nodes; above a shallower operand's root
+            // (the lifted levels) every child is its root
+            st.An2 = (l + 1 <= liftA) ? A->nn2[0] : A->nn2[l + 1 - liftA];
+            st.Bn2 = (l + 1 <= liftB) ? B->nn2[0] : B->nn2[l + 1 - liftB];
+            st.tau2 = op.tau2;
+        }
         return st;
     };
     RootInit root{(int32_t*)at(W, o_fa[0]), (int32_t*)at(W, o_fb[0]), (int32_t*)at(W, o_cseg[0]),
@@ -1259,6 +1342,11 @@ void symbolic(qt_matrix* A, qt_matrix* B, qt_prec prec, hipStream_t s, SymbolicO
     ls.upper = op.upper;
     ls.amap = A->vsrc ? A->bmap.p : nullptr;
     ls.bmap = B->vsrc ? B->bmap.p : nullptr;
+    if (prune) {
+        ls.Abn2 = A->bn2;
+        ls.Bbn2 = B->bn2;
+        ls.tau2 = op.tau2;
+    }
     ls.Amo = A->leaves.mask_mo.p;
     ls.Bmo = B->leaves.mask_mo.p;
     ls.Abase = A->leaves.base.p;
@@ -1343,13 +1431,13 @@ void symbolic(qt_matrix* A, qt_matrix* B, qt_prec prec, hipStream_t s, SymbolicO
         if (hc[2 * L + 3 + l] < 0 || hc[2 * L + 3 + l] > hc[l])
             fail(QT_ERR_DEVICE, "symbolic phase: kept C node count out of range");
         const int64_t expect = (l < L) ? pairs[l + 1] : P;
-        const bool bad = op.upper ? (hc[L + 2 + l] < 0 || hc[L + 2 + l] > expect) : (hc[L + 2 + l] != expect);
+        const bool bad = bounds ? (hc[L + 2 + l] < 0 || hc[L + 2 + l] > expect) : (hc[L + 2 + l] != expect);
         if (bad) fail(QT_ERR_DEVICE, "symbolic phase: pair count mismatch");
         if (l < L) C->pairs[l + 1] = hc[L + 2 + l];   // pairs actually formed
     }
     C->products = hc[2 * L + 2];
     const int32_t nnzC = hc[L + 1];
-    if (nnzC < 0 || nnzC > cap || (nnzC == 0 && !op.upper)) fail(QT_ERR_DEVICE, "symbolic phase: C block count out of range");
+    if (nnzC < 0 || nnzC > cap || (nnzC == 0 && !bounds)) fail(QT_ERR_DEVICE, "symbolic phase: C block count out of range");
 
     const bool leafrow = make_order && C->products >= 2 * (int64_t)nnzC;
     const bool korder = may_korder && nnzC > 0 && C->products < 2 * (int64_t)nnzC;

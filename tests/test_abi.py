@@ -51,6 +51,9 @@ def test_null_handles_rejected():
     assert qt.lib.qt_tune_leaf_cached(None, None, 0, None, 1, b"c", None, None) == qt.QT_ERR_ARG
     assert qt.lib.qt_plan_tune_cached(None, None, 1, b"c", None, None) == qt.QT_ERR_ARG
     assert qt.lib.qt_tune_cache(None) == qt.QT_OK
+    assert qt.lib.qt_multiply_tau(None, None, 0.0, 0, None, ctypes.byref(out)) == qt.QT_ERR_ARG
+    assert qt.lib.qt_multiply_tau(None, None, -1.0, 0, None, None) == qt.QT_ERR_ARG
+    assert qt.lib.qt_norms(None, None, None, 0, None) == qt.QT_ERR_ARG
     qt.lib.qt_free(None)
 
 
