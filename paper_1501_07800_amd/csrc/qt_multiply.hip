@@ -362,11 +362,6 @@ __global__ __launch_bounds__(64 * W) void k_tree_fill(TreeStep st) {
     }
 }
 
-__global__ void k_fill_flags(int32_t* __restrict__ f, int64_t n) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) f[i] = 0;
-}
-
 // Level-0 frontier: the pair of roots, one C node.
 struct RootInit {
     int32_t* fa;
@@ -376,11 +371,17 @@ struct RootInit {
     int32_t* ncount;
     int64_t* zero;            // the group sums of all levels, cleared here
     int64_t nzero;
+    int32_t* clear;           // the NIL flags and their tile counts, cleared here
+    int64_t nclear;
 };
 
-// The first kernel of the traversal (every thread takes part in the clearing).
+// The first kernel of the traversal: every workgroup clears its part of the
+// NIL flags; the first also clears the group sums and writes the roots.
 __device__ void root_init(const RootInit& r) {
-    for (int64_t i = threadIdx.x; i < r.nzero; i += blockDim.x) r.zero[i] = 0;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < r.nclear) r.clear[i] = 0;
+    if (blockIdx.x != 0) return;
+    for (int64_t z = threadIdx.x; z < r.nzero; z += blockDim.x) r.zero[z] = 0;
     if (threadIdx.x == 0) {
         r.fa[0] = 0;
         r.fb[0] = 0;
@@ -394,6 +395,38 @@ __device__ void root_init(const RootInit& r) {
 __global__ __launch_bounds__(64) void k_root_init(RootInit r) { root_init(r); }
 
 // ------------------------------------------------------ the leaf step
+
+// NIL normalisation of C (see below): the leaf step flags every C leaf that
+// receives a block, and its ancestors, as it fills the leaf.
+constexpr int NIL_MAX_LEVELS = 32;
+
+struct NilMark {
+    int L;
+    int64_t foff[NIL_MAX_LEVELS + 2];              // flags of level l at foff[l] .. foff[l+1]-1
+    const int32_t* uparent[NIL_MAX_LEVELS + 1];    // parent of every C node, levels 1 .. L
+    int32_t* flags;                                // foff[L+1] entries, cleared before the traversal
+    int32_t* tcnt;                                 // flags set per tile of 64, cleared with them
+};
+
+// Flags C node p of level l; true when this call set it. Each flag is set
+// once (an atomic exchange), and each first setting is counted in its tile.
+__device__ __forceinline__ bool nil_flag(const NilMark& m, int l, int32_t p) {
+    const int64_t f = m.foff[l] + p;
+    if (atomicExch(m.flags + f, 1) != 0) return false;
+    atomicAdd(m.tcnt + (f >> 6), 1);
+    return true;
+}
+
+// C leaf c holds a block: it and its ancestors are kept. A walk stops at the
+// first node flagged already: whoever flagged it walks on from there.
+__device__ void nil_mark_up(const NilMark& m, int32_t c) {
+    if (!nil_flag(m, m.L, c)) return;
+    int32_t p = c;
+    for (int l = m.L; l > 0; --l) {
+        p = m.uparent[l][p];
+        if (!nil_flag(m, l - 1, p)) return;
+    }
+}
 
 struct LeafStep {
     const int32_t* fa;        // A leaf of each leaf pair
@@ -433,6 +466,7 @@ struct LeafStep {
     const double* Abn2;       // squared block norms (nullptr: no norm threshold): a block product
     const double* Bbn2;       // is dropped when Abn2 Bbn2 < tau2
     double tau2;
+    NilMark nil;              // the fill flags the kept C leaves and their ancestors
 };
 
 // Lane t's value in every lane, for a t that is the same in every lane: a
@@ -615,6 +649,7 @@ __device__ void leaf_fill_node(const LeafStep& st, int32_t c, int lane, int64_t 
         st.lmo[c] = em;
         st.lrm[c] = rm;
         st.lcm[c] = cm;
+        if (em) nil_mark_up(st.nil, c);
     }
 }
 
@@ -655,30 +690,33 @@ __global__ __launch_bounds__(64 * W) void k_leaf_fill(LeafStep st) {
 // B(k,j) both present) holds no block, and so does a node above only such
 // leaves. Zero submatrices are NIL at every level of the quadtree (Sec. 3.1),
 // so C's tree keeps exactly the nodes with a stored block below them:
-//   mark:    every leaf that holds a block flags itself and its ancestors
-//            (parents were recorded by the traversal; a walk stops at the
-//            first ancestor already flagged);
-//   scan:    one exclusive scan over the flags of all levels, concatenated,
-//            gives every kept node its index among the kept nodes of its level;
+//   mark:    the leaf fill flags every leaf that receives a block, and its
+//            ancestors (parents were recorded by the traversal), counting
+//            the flags set per tile of 64 (nil_mark_up);
+//   offsets: one wave per tile adds up the counts of the tiles before it and
+//            ranks its own flags with a ballot: the exclusive scan of the
+//            flags of all levels, concatenated, which gives every kept node
+//            its index among the kept nodes of its level (one launch, where
+//            a general scan takes three);
 //   compact: kept nodes are copied into C's tree, child tables remapped
 //            (a child that is not kept becomes NIL), and the kept counts of
 //            every level are written for the read-back.
 // C's blocks, their order and the product lists do not change: an empty leaf
-// owns none of them.
-constexpr int NIL_MAX_LEVELS = 32;
+// owns none of them. The traversal runs beside the previous multiply's
+// numeric kernel, where each launch waits tens of microseconds for wave
+// slots; folding the marks into the leaf fill and the scan into one launch
+// leaves two launches of the five a separate pass would take.
 
 struct NilTree {
     int L;
     int64_t foff[NIL_MAX_LEVELS + 2];        // flags of level l at foff[l] .. foff[l+1]-1
-    const int32_t* ncount;                   // traversal's C node counts, levels 0 .. L
-    const int32_t* uparent[NIL_MAX_LEVELS + 1];   // levels 1 .. L
     const int32_t* uchild[NIL_MAX_LEVELS];   // levels 0 .. L-1 (4 per node)
     const uint64_t* ukey[NIL_MAX_LEVELS + 1];
     const int32_t* ubase;                    // leaves
     const uint64_t* umo;
     const uint64_t* urm;
     const uint64_t* ucm;
-    int32_t* flags;                          // foff[L+1] entries, cleared before the traversal
+    const int32_t* flags;                    // foff[L+1] entries, set by the leaf fill
     const int32_t* ex;                       // exclusive scan of flags (foff[L+1] + 1 entries)
     int32_t* child[NIL_MAX_LEVELS];          // the kept tree
     uint64_t* key[NIL_MAX_LEVELS + 1];
@@ -689,18 +727,21 @@ struct NilTree {
     int32_t* kept;                           // kept nodes per level, levels 0 .. L
 };
 
-__global__ void k_nil_mark(NilTree t) {
-    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int L = t.L;
-    if (c >= t.ncount[L] || t.umo[c] == 0) return;
-    t.flags[t.foff[L] + c] = 1;
-    int32_t p = (int32_t)c;
-    for (int l = L; l > 0; --l) {
-        p = t.uparent[l][p];
-        int32_t* f = t.flags + t.foff[l - 1] + p;
-        if (*f) break;   // that ancestor and its own ancestors are flagged already
-        *f = 1;
-    }
+// ex[i] = number of flags set before i, for i <= n: one wave per tile of 64
+// indices, n / 64 + 1 tiles (the lane of index n writes the total); tcnt
+// holds the flags set in each tile.
+__global__ __launch_bounds__(64) void k_nil_offsets(const int32_t* __restrict__ flags,
+                                                    const int32_t* __restrict__ tcnt, int64_t n,
+                                                    int32_t* __restrict__ ex) {
+    const int lane = threadIdx.x;
+    const int64_t t = blockIdx.x;
+    int before = 0;
+    for (int64_t u = lane; u < t; u += 64) before += tcnt[u];
+    before = wave_sum(before);
+    const int64_t i = t * 64 + lane;
+    const uint64_t set = __ballot(i < n && flags[i] != 0);
+    if (i < n) ex[i] = before + __popcll(set & lanes_below(lane));
+    if (i == n) ex[n] = before + __popcll(set);
 }
 
 __device__ __forceinline__ int32_t nil_rank(const NilTree& t, int l, int64_t c) {
@@ -1199,9 +1240,11 @@ void symbolic(qt_matrix* A, qt_matrix* B, qt_prec prec, hipStream_t s, SymbolicO
     std::vector<int64_t> foff(L + 2, 0);
     for (int l = 0; l <= L; ++l) foff[l + 1] = foff[l] + ncap[l];
     if (foff[L + 1] > kMaxI32) fail(QT_ERR_UNSUPPORTED, "too many C nodes");
-    const size_t o_nflags = tmp.take(foff[L + 1] * sizeof(int32_t));
+    // NIL flags of all levels, then their counts per tile of 64 (cleared together)
+    const int64_t nil_tiles = foff[L + 1] / 64 + 1;
+    const int64_t nil_clear = foff[L + 1] + nil_tiles;
+    const size_t o_nflags = tmp.take(nil_clear * sizeof(int32_t));
     const size_t o_nex = tmp.take((foff[L + 1] + 1) * sizeof(int32_t));
-    const size_t o_nscan = tmp.take((scan_tmp_elems(foff[L + 1]) + 1) * sizeof(int32_t));
     std::vector<size_t> o_fa(L + 1), o_fb(L + 1), o_cseg(L + 1), o_cnt(L + 1), o_off(L + 1), o_tot(L + 1),
         o_wagg(L + 1);
     std::vector<int64_t> gsum_at(L + 1);
@@ -1308,11 +1351,9 @@ void symbolic(qt_matrix* A, qt_matrix* B, qt_prec prec, hipStream_t s, SymbolicO
         return st;
     };
     RootInit root{(int32_t*)at(W, o_fa[0]), (int32_t*)at(W, o_fb[0]), (int32_t*)at(W, o_cseg[0]),
-                  (uint64_t*)at(W, u_key[0]), dcount, (int64_t*)at(W, o_gsum), nzero};
+                  (uint64_t*)at(W, u_key[0]), dcount, (int64_t*)at(W, o_gsum), nzero, nflags, nil_clear};
 
-    k_fill_flags<<<(unsigned)((foff[L + 1] + 63) / 64), 64, 0, ss>>>(nflags, foff[L + 1]);
-    QT_LAUNCH("k_fill_flags");
-    k_root_init<<<1, 64, 0, ss>>>(root);
+    k_root_init<<<(unsigned)((nil_clear + 63) / 64), 64, 0, ss>>>(root);
     QT_LAUNCH("k_root_init");
     int64_t* scan_tmp = (int64_t*)at(W, o_scan);
     for (int l = 0; l < L; ++l) {
@@ -1369,6 +1410,11 @@ void symbolic(qt_matrix* A, qt_matrix* B, qt_prec prec, hipStream_t s, SymbolicO
     ls.lcm = (uint64_t*)at(W, u_lcm);
     ls.nblocks_out = dcount + L + 1;
     ls.check = dcount + 2 * L + 2;
+    ls.nil.L = L;
+    for (int l = 0; l <= L + 1; ++l) ls.nil.foff[l] = foff[l];
+    for (int l = 1; l <= L; ++l) ls.nil.uparent[l] = (const int32_t*)at(W, u_parent[l]);
+    ls.nil.flags = nflags;
+    ls.nil.tcnt = nflags + foff[L + 1];
     QT_LEVEL_LAUNCH(k_leaf_count, ncap[L], leaf_wgs, ss, ls);
     if (!ls.use_agg) exclusive_scan(ls.cnt, ls.off, ncap[L], scan_tmp, ss);
     QT_LEVEL_LAUNCH(k_leaf_fill, ncap[L], leaf_wgs, ss, ls);
@@ -1394,8 +1440,6 @@ void symbolic(qt_matrix* A, qt_matrix* B, qt_prec prec, hipStream_t s, SymbolicO
         NilTree nt{};
         nt.L = L;
         for (int l = 0; l <= L + 1; ++l) nt.foff[l] = foff[l];
-        nt.ncount = dcount;
-        for (int l = 1; l <= L; ++l) nt.uparent[l] = (const int32_t*)at(W, u_parent[l]);
         for (int l = 0; l < L; ++l) {
             nt.uchild[l] = (const int32_t*)at(W, u_child[l]);
             nt.child[l] = (int32_t*)at(K, o_child[l]);
@@ -1415,9 +1459,9 @@ void symbolic(qt_matrix* A, qt_matrix* B, qt_prec prec, hipStream_t s, SymbolicO
         nt.rm = (uint64_t*)at(K, o_lrm);
         nt.cm = (uint64_t*)at(K, o_lcm);
         nt.kept = dcount + 2 * L + 3;
-        k_nil_mark<<<(unsigned)((ncap[L] + 63) / 64), 64, 0, ss>>>(nt);
-        QT_LAUNCH("k_nil_mark");
-        exclusive_scan(nflags, (int32_t*)at(W, o_nex), foff[L + 1], (int32_t*)at(W, o_nscan), ss);
+        k_nil_offsets<<<(unsigned)nil_tiles, 64, 0, ss>>>(nflags, ls.nil.tcnt, foff[L + 1],
+                                                            (int32_t*)at(W, o_nex));
+        QT_LAUNCH("k_nil_offsets");
         k_nil_compact<<<(unsigned)((foff[L + 1] + 63) / 64), 64, 0, ss>>>(nt);
         QT_LAUNCH("k_nil_compact");
     }
