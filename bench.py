@@ -625,6 +625,12 @@ def main():
                     entry["error_sample"] = f"C block rows 0..{sample_rows - 1}"
         if prec == "bf16x3":
             entry["mfma_utilisation"] = 3 * r["numeric_tflops"] / PEAK["bf16x3"]
+        # operand bytes the kernel loads per launch (every block product's two
+        # operand blocks; hi and lo parts for the split path), over its time:
+        # the feed from L2 into the CUs
+        op_bytes = r["P"] * 2 * b * b * {"f64": 8, "f32": 4, "bf16x3": 4}[prec]
+        entry["operand_feed_gbs"] = op_bytes / (r["numeric_ms"] * 1e-3) / 1e9
+        entry["traffic_bytes"] = measured_traffic(args.workload, prec)
         paths[prec] = entry
 
     failed = [msg for prec, e in paths.items() for msg in check_path(e, prec)]
@@ -732,6 +738,7 @@ def hbm_config_entry(qt, torch, wl, name, steps, warmup, samples=64):
             entry["e_max_rel"] = float(np.abs(d).max() / np.abs(sref).max())
             entry["e_F"] = float(np.linalg.norm(d) / np.linalg.norm(sref))
             entry["error_sample"] = f"{len(sI)} C blocks drawn uniformly, against the definition"
+        entry["roofline"]["traffic"] = measured_traffic(name, prec)
         C.free()
         log(f"bench: {name} {prec}: {entry['tflops']:.2f} TFLOP/s end to end, numeric {num_ms:.3f} ms = "
             f"{entry['roofline']['achieved']:.0f} {entry['roofline']['unit']} ({entry['roofline']['frac']:.2f} "
