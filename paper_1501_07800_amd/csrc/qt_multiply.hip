@@ -137,6 +137,19 @@ struct TreeStep {
     const double* An2;        // squared norms of the operands' next-level nodes (nullptr: no
     const double* Bn2;        // norm threshold): a child pair is dropped when An2 Bn2 < tau2
     double tau2;
+    // The next level's counts, made by this level's fill when ncnt is set (a
+    // single-wave next level): the fill holds every pair of each child node it
+    // creates, so it counts their child pairs too, and the next level needs no
+    // count kernel of its own.
+    const int32_t* nAch;      // child tables of A and B at the next level
+    const int32_t* nBch;
+    const double* nAn2;       // norms of the nodes two levels down (norm threshold)
+    const double* nBn2;
+    int64_t* ncnt;            // the next level's cnt, tot4, off, wagg, gsum
+    int4* ntot4;
+    int64_t* noff;
+    int64_t* nwagg;
+    int64_t* ngsum;
 };
 
 // Child a of op(A) and child b of op(B) form a pair: both present and, with
@@ -203,6 +216,55 @@ __device__ void tree_level_totals(const TreeStep& st, int64_t T) {
     *st.check = lo32(T);
 }
 
+// Workgroup aggregates of a level are summed in groups of 64 (aggregate path, below).
+constexpr int AGG_GROUP_LOG = 6;
+
+// Child pairs of the next level's pairs, per quadrant q, summed over the
+// wave (the rule of tree_count_node one level down): each lane holds at most
+// one pair (a, b) (valid: `has`); the totals are wave-uniform, kept in scalar
+// registers (popcounts of ballots).
+__device__ __forceinline__ void next_level_count(const TreeStep& st, bool has, int32_t a, int32_t b,
+                                                 uint32_t (&u)[4]) {
+    int4 x = make_int4(-1, -1, -1, -1), y = make_int4(-1, -1, -1, -1);
+    if (has) {
+        x = op_children(st.nAch, a, st.ta);
+        y = op_children(st.nBch, b, st.tb);
+    }
+    auto kept = [&](int32_t p, int32_t q) {
+        return p >= 0 && q >= 0 && (!st.nAn2 || st.nAn2[p] * st.nBn2[q] >= st.tau2);
+    };
+    u[0] += __popcll(__ballot(kept(x.x, y.x))) + __popcll(__ballot(kept(x.y, y.z)));
+    u[1] += __popcll(__ballot(kept(x.x, y.y))) + __popcll(__ballot(kept(x.y, y.w)));
+    u[2] += __popcll(__ballot(kept(x.z, y.x))) + __popcll(__ballot(kept(x.w, y.z)));
+    u[3] += __popcll(__ballot(kept(x.z, y.y))) + __popcll(__ballot(kept(x.w, y.w)));
+}
+
+// The counts of c's children, as the next level's count kernel would write
+// them for single-wave workgroups (node c2 is workgroup c2, its offset inside
+// the workgroup 0); lane mn writes those of child quadrant mn.
+__device__ void next_level_write(const TreeStep& st, int32_t c, int lane, const int (&cid)[4],
+                                 const uint32_t (&u)[4][4]) {
+    if (lane >= 4) return;
+    int c2 = -1;
+    int mine[4] = {0, 0, 0, 0};
+#pragma unroll
+    for (int mn = 0; mn < 4; ++mn)
+        if (mn == lane) {
+            c2 = cid[mn];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) mine[q] = (int)u[mn][q];
+        }
+    if (c2 < 0 || c2 >= st.nc_next) return;
+    if (quadrant_dropped(st.upper, st.ckey[c] * 4 + (uint64_t)lane, 2)) mine[2] = 0;
+    const int64_t v = pack2(mine[0] + mine[1] + mine[2] + mine[3],
+                            (mine[0] > 0) + (mine[1] > 0) + (mine[2] > 0) + (mine[3] > 0));
+    st.ncnt[c2] = v;
+    st.ntot4[c2] = make_int4(mine[0], mine[1], mine[2], mine[3]);
+    st.noff[c2] = 0;
+    st.nwagg[c2] = v;
+    if (v) atomicAdd((unsigned long long*)(st.ngsum + (c2 >> AGG_GROUP_LOG)), (unsigned long long)v);
+}
+
 // o: (first child pair, first child C node) of node c in the next level.
 __device__ void tree_fill_node(const TreeStep& st, int32_t c, int lane, int64_t o) {
     if (c >= *st.ncount) return;
@@ -234,6 +296,8 @@ __device__ void tree_fill_node(const TreeStep& st, int32_t c, int lane, int64_t 
     const int32_t s0 = st.cseg[c], len = st.cseg[c + 1] - s0;
     const uint64_t below = lanes_below(lane);
     const bool drop_lower = quadrant_dropped(st.upper, st.ckey[c], 2);
+    const bool counts = st.ncnt != nullptr;
+    uint32_t u[4][4] = {};   // per child quadrant mn of c: that child's child pairs, per quadrant
     for (int32_t base = 0; base < len; base += 64) {
         const bool act = base + lane < len;
         int4 a = make_int4(-1, -1, -1, -1), b = make_int4(-1, -1, -1, -1);
@@ -264,8 +328,13 @@ __device__ void tree_fill_node(const TreeStep& st, int32_t c, int lane, int64_t 
                 st.nfb[out] = bv[2 + n];
             }
             run[mn] += __popcll(m0) + __popcll(m1);
+            if (counts) {
+                next_level_count(st, e0, av[2 * m], bv[n], u[mn]);
+                next_level_count(st, e1, av[2 * m + 1], bv[2 + n], u[mn]);
+            }
         }
     }
+    if (counts) next_level_write(st, c, lane, cid, u);
 }
 
 // The per-level kernels run W waves (one C node each) per workgroup: W = 1
@@ -277,7 +346,6 @@ __device__ void tree_fill_node(const TreeStep& st, int32_t c, int lane, int64_t 
 constexpr int64_t WIDE_LEVEL = 65536;
 static inline int level_waves(int64_t n) { return n <= WIDE_LEVEL ? 1 : 4; }
 
-constexpr int AGG_GROUP_LOG = 6;
 constexpr int32_t AGG_MAX = 65536;   // workgroups per level on the aggregate path
 
 __device__ __forceinline__ int64_t wave_sum64(int64_t x) {
@@ -369,19 +437,16 @@ struct RootInit {
     int32_t* cseg;
     uint64_t* ckey;
     int32_t* ncount;
-    int64_t* zero;            // the group sums of all levels, cleared here
-    int64_t nzero;
-    int32_t* clear;           // the NIL flags and their tile counts, cleared here
+    int32_t* clear;           // NIL flags and tile counts, group sums, workgroup aggregates (as words)
     int64_t nclear;
 };
 
 // The first kernel of the traversal: every workgroup clears its part of the
-// NIL flags; the first also clears the group sums and writes the roots.
+// scratch that later kernels accumulate into; the first writes the roots.
 __device__ void root_init(const RootInit& r) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < r.nclear) r.clear[i] = 0;
     if (blockIdx.x != 0) return;
-    for (int64_t z = threadIdx.x; z < r.nzero; z += blockDim.x) r.zero[z] = 0;
     if (threadIdx.x == 0) {
         r.fa[0] = 0;
         r.fb[0] = 0;
@@ -443,6 +508,7 @@ struct LeafStep {
     const int32_t* Abase;
     const int32_t* Bbase;
     int64_t* cnt;             // per C leaf: (products, C blocks)
+    int32_t* lane_cnt;        // per C leaf, 64 entries: the block products of each block position
     int64_t* off;             // scan path: exclusive scan of cnt; aggregate path: offset inside the workgroup
     int64_t* wagg;            // aggregate path: per count workgroup, the sum of its leaves' cnt
     int64_t* gsum;            // aggregate path: per group of 64 count workgroups, their sum (zeroed first)
@@ -569,6 +635,7 @@ __device__ int64_t leaf_count_node(const LeafStep& st, int32_t c, int lane) {
     const bool on = lane < lb * lb && leaf_block_kept(st, st.ckey[c], i, j);
     const int32_t s0 = st.cseg[c], len = st.cseg[c + 1] - s0;
     const int cnt = leaf_lane_count(st, s0, len, lane, i, j, lb, on);
+    st.lane_cnt[(int64_t)c * 64 + lane] = cnt;   // the fill reads it instead of walking the pairs twice
     const uint64_t em = __ballot(cnt > 0);
     const int tot = wave_sum(cnt);
     const int64_t v = pack2(tot, __popcll(em));
@@ -591,7 +658,7 @@ __device__ void leaf_fill_node(const LeafStep& st, int32_t c, int lane, int64_t 
     const int i = (int)morton_row((uint64_t)lane), j = (int)morton_col((uint64_t)lane);
     const bool on = lane < lb * lb && leaf_block_kept(st, st.ckey[c], i, j);
     const int32_t s0 = st.cseg[c], len = st.cseg[c + 1] - s0;
-    const int cnt = leaf_lane_count(st, s0, len, lane, i, j, lb, on);
+    const int cnt = st.lane_cnt[(int64_t)c * 64 + lane];   // from the count kernel
     const bool exists = cnt > 0;
     const uint64_t em = __ballot(exists);
     const int32_t bidx = hi32(o) + __popcll(em & lanes_below(lane));
@@ -1240,15 +1307,26 @@ void symbolic(qt_matrix* A, qt_matrix* B, qt_prec prec, hipStream_t s, SymbolicO
     std::vector<int64_t> foff(L + 2, 0);
     for (int l = 0; l <= L; ++l) foff[l + 1] = foff[l] + ncap[l];
     if (foff[L + 1] > kMaxI32) fail(QT_ERR_UNSUPPORTED, "too many C nodes");
-    // NIL flags of all levels, then their counts per tile of 64 (cleared together)
+    // Cleared by the traversal's first kernel, in one run: the NIL flags of all
+    // levels and their counts per tile of 64, the group sums of every level's
+    // workgroup aggregates, and the aggregates themselves (the levels whose
+    // counts the previous level's fill makes have no count kernel to write
+    // the aggregates of workgroups without a node).
     const int64_t nil_tiles = foff[L + 1] / 64 + 1;
-    const int64_t nil_clear = foff[L + 1] + nil_tiles;
-    const size_t o_nflags = tmp.take(nil_clear * sizeof(int32_t));
-    const size_t o_nex = tmp.take((foff[L + 1] + 1) * sizeof(int32_t));
-    std::vector<size_t> o_fa(L + 1), o_fb(L + 1), o_cseg(L + 1), o_cnt(L + 1), o_off(L + 1), o_tot(L + 1),
-        o_wagg(L + 1);
+    const int64_t nil_flags = foff[L + 1] + nil_tiles;
+    const size_t o_nflags = tmp.take(nil_flags * sizeof(int32_t));
     std::vector<int64_t> gsum_at(L + 1);
     int64_t gsum_total = 0;
+    for (int l = 0; l <= L; ++l) {
+        gsum_at[l] = gsum_total;
+        gsum_total += (level_wgs(ncap[l]) + (1 << AGG_GROUP_LOG) - 1) >> AGG_GROUP_LOG;
+    }
+    const size_t o_gsum = tmp.take(std::max<int64_t>(gsum_total, 1) * sizeof(int64_t));
+    std::vector<size_t> o_fa(L + 1), o_fb(L + 1), o_cseg(L + 1), o_cnt(L + 1), o_off(L + 1), o_tot(L + 1),
+        o_wagg(L + 1);
+    for (int l = 0; l <= L; ++l) o_wagg[l] = tmp.take(level_wgs(ncap[l]) * sizeof(int64_t));
+    const int64_t nclear = (int64_t)(tmp.bytes - o_nflags) / (int64_t)sizeof(int32_t);
+    const size_t o_nex = tmp.take((foff[L + 1] + 1) * sizeof(int32_t));
     size_t scan_elems = 0;
     for (int l = 0; l <= L; ++l) {
         o_fa[l] = tmp.take(pairs[l] * sizeof(int32_t));
@@ -1257,14 +1335,10 @@ void symbolic(qt_matrix* A, qt_matrix* B, qt_prec prec, hipStream_t s, SymbolicO
         o_cnt[l] = tmp.take(ncap[l] * sizeof(int64_t));
         o_off[l] = tmp.take((ncap[l] + 1) * sizeof(int64_t));
         o_tot[l] = tmp.take(ncap[l] * sizeof(int4));
-        o_wagg[l] = tmp.take(level_wgs(ncap[l]) * sizeof(int64_t));
-        gsum_at[l] = gsum_total;
-        gsum_total += (level_wgs(ncap[l]) + (1 << AGG_GROUP_LOG) - 1) >> AGG_GROUP_LOG;
         scan_elems = std::max(scan_elems, scan_tmp_elems(ncap[l]));
     }
-    const int64_t nzero = std::max<int64_t>(gsum_total, 1);
-    const size_t o_gsum = tmp.take(nzero * sizeof(int64_t));
     const size_t o_scan = tmp.take((scan_elems + 1) * sizeof(int64_t));
+    const size_t o_lcnt = tmp.take(ncap[L] * 64 * sizeof(int32_t));   // leaf step: products per block position
     const size_t o_prodA = tmp.take(P * sizeof(int32_t));
     const size_t o_prodB = tmp.take(P * sizeof(int32_t));
     const size_t o_cbseg = tmp.take((cap + 1) * sizeof(int32_t));
@@ -1351,18 +1425,34 @@ void symbolic(qt_matrix* A, qt_matrix* B, qt_prec prec, hipStream_t s, SymbolicO
         return st;
     };
     RootInit root{(int32_t*)at(W, o_fa[0]), (int32_t*)at(W, o_fb[0]), (int32_t*)at(W, o_cseg[0]),
-                  (uint64_t*)at(W, u_key[0]), dcount, (int64_t*)at(W, o_gsum), nzero, nflags, nil_clear};
+                  (uint64_t*)at(W, u_key[0]), dcount, nflags, nclear};
 
-    k_root_init<<<(unsigned)((nil_clear + 63) / 64), 64, 0, ss>>>(root);
+    k_root_init<<<(unsigned)((nclear + 63) / 64), 64, 0, ss>>>(root);
     QT_LAUNCH("k_root_init");
     int64_t* scan_tmp = (int64_t*)at(W, o_scan);
+    bool counted = false;   // this level's counts were made by the previous level's fill
     for (int l = 0; l < L; ++l) {
-        const TreeStep st = tree_step(l);
-        TreeStep sl = st;
+        TreeStep sl = tree_step(l);
         const int64_t wgs = level_wgs(ncap[l]);
         sl.use_agg = wgs <= AGG_MAX;
-        QT_LEVEL_LAUNCH(k_tree_count, ncap[l], wgs, ss, sl);
-        if (!sl.use_agg) exclusive_scan(sl.cnt, sl.off, ncap[l], scan_tmp, ss);
+        if (!counted) {
+            QT_LEVEL_LAUNCH(k_tree_count, ncap[l], wgs, ss, sl);
+            if (!sl.use_agg) exclusive_scan(sl.cnt, sl.off, ncap[l], scan_tmp, ss);
+        }
+        // a single-wave next tree level gets its counts from this fill
+        counted = l + 1 < L && level_waves(ncap[l + 1]) == 1;
+        if (counted) {
+            const TreeStep nx = tree_step(l + 1);
+            sl.nAch = nx.Ach;
+            sl.nBch = nx.Bch;
+            sl.nAn2 = nx.An2;
+            sl.nBn2 = nx.Bn2;
+            sl.ncnt = nx.cnt;
+            sl.ntot4 = nx.tot4;
+            sl.noff = nx.off;
+            sl.nwagg = nx.wagg;
+            sl.ngsum = nx.gsum;
+        }
         QT_LEVEL_LAUNCH(k_tree_fill, ncap[l], wgs, ss, sl);
     }
 
@@ -1393,6 +1483,7 @@ void symbolic(qt_matrix* A, qt_matrix* B, qt_prec prec, hipStream_t s, SymbolicO
     ls.Abase = A->leaves.base.p;
     ls.Bbase = B->leaves.base.p;
     ls.cnt = (int64_t*)at(W, o_cnt[L]);
+    ls.lane_cnt = (int32_t*)at(W, o_lcnt);
     ls.off = (int64_t*)at(W, o_off[L]);
     ls.wagg = (int64_t*)at(W, o_wagg[L]);
     ls.gsum = (int64_t*)at(W, o_gsum) + gsum_at[L];
