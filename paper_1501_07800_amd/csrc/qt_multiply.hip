@@ -160,14 +160,29 @@ __device__ __forceinline__ bool pair_kept(const TreeStep& st, int32_t a, int32_t
 
 // Children of an operand node in the orientation of op(X): for a transposed
 // operand the off-diagonal children swap (quadrant (m, k) of X^T is (k, m) of X).
-__device__ __forceinline__ int4 op_children(const int32_t* tab, int32_t node, int transposed) {
-    int4 c = *reinterpret_cast<const int4*>(tab + 4 * (int64_t)node);
+__device__ __forceinline__ int4 op_swap(int4 c, int transposed) {
     if (transposed) {
         const int t = c.y;
         c.y = c.z;
         c.z = t;
     }
     return c;
+}
+
+__device__ __forceinline__ int4 op_children(const int32_t* tab, int32_t node, int transposed) {
+    return op_swap(*reinterpret_cast<const int4*>(tab + 4 * (int64_t)node), transposed);
+}
+
+// The child tables of A node a and B node b, both loads issued before either
+// is used (left alone, the compiler waits for the first before it issues
+// the second).
+__device__ __forceinline__ void op_children2(const int32_t* atab, int32_t a, int ta, const int32_t* btab, int32_t b,
+                                             int tb, int4& x, int4& y) {
+    const int4 ra = *reinterpret_cast<const int4*>(atab + 4 * (int64_t)a);
+    const int4 rb = *reinterpret_cast<const int4*>(btab + 4 * (int64_t)b);
+    __builtin_amdgcn_sched_barrier(0);
+    x = op_swap(ra, ta);
+    y = op_swap(rb, tb);
 }
 
 // Quadrant mn of C node `key` is dropped when only the upper triangle is
@@ -187,8 +202,8 @@ __device__ int64_t tree_count_node(const TreeStep& st, int32_t c, int lane) {
     for (int32_t base = 0; base < len; base += 64) {
         if (base + lane < len) {
             const int32_t p = s0 + base + lane;
-            const int4 a = op_children(st.Ach, st.fa[p], st.ta);   // A child (m, k) at 2m + k
-            const int4 b = op_children(st.Bch, st.fb[p], st.tb);   // B child (k, n) at 2k + n
+            int4 a, b;   // A child (m, k) at 2m + k, B child (k, n) at 2k + n
+            op_children2(st.Ach, st.fa[p], st.ta, st.Bch, st.fb[p], st.tb, a, b);
             t0 += pair_kept(st, a.x, b.x) + pair_kept(st, a.y, b.z);
             t1 += pair_kept(st, a.x, b.y) + pair_kept(st, a.y, b.w);
             t2 += pair_kept(st, a.z, b.x) + pair_kept(st, a.w, b.z);
@@ -220,16 +235,29 @@ __device__ void tree_level_totals(const TreeStep& st, int64_t T) {
 constexpr int AGG_GROUP_LOG = 6;
 
 // Child pairs of the next level's pairs, per quadrant q, summed over the
-// wave (the rule of tree_count_node one level down): each lane holds at most
-// one pair (a, b) (valid: `has`); the totals are wave-uniform, kept in scalar
-// registers (popcounts of ballots).
-__device__ __forceinline__ void next_level_count(const TreeStep& st, bool has, int32_t a, int32_t b,
-                                                 uint32_t (&u)[4]) {
-    int4 x = make_int4(-1, -1, -1, -1), y = make_int4(-1, -1, -1, -1);
-    if (has) {
-        x = op_children(st.nAch, a, st.ta);
-        y = op_children(st.nBch, b, st.tb);
-    }
+// wave (the rule of tree_count_node one level down), into u: each lane
+// holds at most two pairs (a0, b0) and (a1, b1) (valid: has0, has1), whose
+// child tables x0, y0, x1, y1 were loaded by next_level_tables; the totals
+// are wave-uniform, kept in scalar registers (popcounts of ballots).
+__device__ __forceinline__ void next_level_tables(const TreeStep& st, bool has0, int32_t a0, int32_t b0, bool has1,
+                                                  int32_t a1, int32_t b1, int4& x0, int4& y0, int4& x1,
+                                                  int4& y1) {
+    // a lane without a pair reads node 0 (every level of a non-empty operand
+    // has one) and drops the value, so the loads need no branch
+    const int4 rx0 = *reinterpret_cast<const int4*>(st.nAch + 4 * (int64_t)(has0 ? a0 : 0));
+    const int4 ry0 = *reinterpret_cast<const int4*>(st.nBch + 4 * (int64_t)(has0 ? b0 : 0));
+    const int4 rx1 = *reinterpret_cast<const int4*>(st.nAch + 4 * (int64_t)(has1 ? a1 : 0));
+    const int4 ry1 = *reinterpret_cast<const int4*>(st.nBch + 4 * (int64_t)(has1 ? b1 : 0));
+    const int4 none = make_int4(-1, -1, -1, -1);
+    x0 = has0 ? rx0 : none;
+    y0 = has0 ? ry0 : none;
+    x1 = has1 ? rx1 : none;
+    y1 = has1 ? ry1 : none;
+}
+
+__device__ __forceinline__ void next_level_count(const TreeStep& st, int4 x, int4 y, uint32_t (&u)[4]) {
+    x = op_swap(x, st.ta);
+    y = op_swap(y, st.tb);
     auto kept = [&](int32_t p, int32_t q) {
         return p >= 0 && q >= 0 && (!st.nAn2 || st.nAn2[p] * st.nBn2[q] >= st.tau2);
     };
@@ -303,34 +331,50 @@ __device__ void tree_fill_node(const TreeStep& st, int32_t c, int lane, int64_t 
         int4 a = make_int4(-1, -1, -1, -1), b = make_int4(-1, -1, -1, -1);
         if (act) {
             const int32_t p = s0 + base + lane;
-            a = op_children(st.Ach, st.fa[p], st.ta);
-            b = op_children(st.Bch, st.fb[p], st.tb);
+            op_children2(st.Ach, st.fa[p], st.ta, st.Bch, st.fb[p], st.tb, a, b);
         }
         const int av[4] = {a.x, a.y, a.z, a.w};
         const int bv[4] = {b.x, b.y, b.z, b.w};
+        // per child quadrant mn: this lane's pairs (k' = 0 and 1) and where they go
+        bool e[4][2];
+        int out[4];
 #pragma unroll
         for (int mn = 0; mn < 4; ++mn) {
             const int m = mn >> 1, n = mn & 1;
             const bool keep = !(mn == 2 && drop_lower);
-            const bool e0 = keep && pair_kept(st, av[2 * m], bv[n]);           // k' = 0
-            const bool e1 = keep && pair_kept(st, av[2 * m + 1], bv[2 + n]);   // k' = 1
-            const uint64_t m0 = __ballot(e0), m1 = __ballot(e1);
-            int out = run[mn] + __popcll(m0 & below) + __popcll(m1 & below);
-            if (e0) {
-                if (out < st.np_next) {
-                    st.nfa[out] = av[2 * m];
-                    st.nfb[out] = bv[n];
-                }
-                ++out;
-            }
-            if (e1 && out < st.np_next) {
-                st.nfa[out] = av[2 * m + 1];
-                st.nfb[out] = bv[2 + n];
-            }
+            e[mn][0] = keep && pair_kept(st, av[2 * m], bv[n]);           // k' = 0
+            e[mn][1] = keep && pair_kept(st, av[2 * m + 1], bv[2 + n]);   // k' = 1
+            const uint64_t m0 = __ballot(e[mn][0]), m1 = __ballot(e[mn][1]);
+            out[mn] = run[mn] + __popcll(m0 & below) + __popcll(m1 & below);
             run[mn] += __popcll(m0) + __popcll(m1);
-            if (counts) {
-                next_level_count(st, e0, av[2 * m], bv[n], u[mn]);
-                next_level_count(st, e1, av[2 * m + 1], bv[2 + n], u[mn]);
+        }
+        // the next level's counts first, the chunk's pair stores after them: a
+        // wait for loads issued after stores would wait for the stores too
+        if (counts) {
+#pragma unroll
+            for (int mn = 0; mn < 4; ++mn) {
+                const int m = mn >> 1, n = mn & 1;
+                int4 x0, y0, x1, y1;
+                next_level_tables(st, e[mn][0], av[2 * m], bv[n], e[mn][1], av[2 * m + 1], bv[2 + n], x0, y0, x1,
+                                  y1);
+                next_level_count(st, x0, y0, u[mn]);
+                next_level_count(st, x1, y1, u[mn]);
+            }
+        }
+#pragma unroll
+        for (int mn = 0; mn < 4; ++mn) {
+            const int m = mn >> 1, n = mn & 1;
+            int w = out[mn];
+            if (e[mn][0]) {
+                if (w < st.np_next) {
+                    st.nfa[w] = av[2 * m];
+                    st.nfb[w] = bv[n];
+                }
+                ++w;
+            }
+            if (e[mn][1] && w < st.np_next) {
+                st.nfa[w] = av[2 * m + 1];
+                st.nfb[w] = bv[2 + n];
             }
         }
     }
@@ -667,6 +711,7 @@ __device__ void leaf_fill_node(const LeafStep& st, int32_t c, int lane, int64_t 
         st.cbkey[bidx] = (st.ckey[c] << (2 * st.lb_log)) | (uint64_t)lane;
         st.cbseg[bidx] = out;
     }
+    const bool plain = !st.amap && !st.bmap && !st.Abn2;
     for (int32_t base = 0; base < len; base += 64) {
         const int32_t nb = min(64, len - base);
         uint64_t ra = 0, cb = 0, amo = 0, bmo = 0;
@@ -692,6 +737,26 @@ __device__ void leaf_fill_node(const LeafStep& st, int32_t c, int lane, int64_t 
             const uint64_t bmot = lane_value(bmo, t);
             const int32_t abt = (int32_t)lane_value((uint32_t)ab, t);
             const int32_t bbt = (int32_t)lane_value((uint32_t)bb, t);
+            if (plain) {
+                // stored operands, no norm threshold: no loads in this loop, so
+                // no wait on memory (a wait here would also wait for the stores
+                // of the products before)
+                const uint32_t tra = st.ta ? PROD_TRANS : 0u, trb = st.tb ? PROD_TRANS : 0u;
+                while (m) {
+                    const int k = __ffs(m) - 1;
+                    m &= m - 1;
+                    uint32_t qa, qb;   // local Morton positions of A(i,k) / B(k,j) in the stored leaves
+                    leaf_positions(st, i, k, j, qa, qb);
+                    const int32_t ia = abt + __popcll(amot & ((1ull << qa) - 1));
+                    const int32_t ib = bbt + __popcll(bmot & ((1ull << qb) - 1));
+                    if (out < st.P) {
+                        st.prodA[out] = (int32_t)((uint32_t)ia | tra);
+                        st.prodB[out] = (int32_t)((uint32_t)ib | trb);
+                    }
+                    ++out;
+                }
+                continue;
+            }
             while (m) {
                 const int k = __ffs(m) - 1;
                 m &= m - 1;
