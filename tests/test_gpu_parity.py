@@ -207,6 +207,31 @@ def test_depth_mismatch_f64(qt):
     check_f64(qt, B, X, 64)                      # deep times shallow
 
 
+def test_wide_levels(qt):
+    """Levels wider than one workgroup per node allows: b = 16 blocks, one
+    block per leaf, 2048 x 2048 blocks at 1 % fill (11 levels). The deepest
+    tree levels and the leaf level hold 10^5 to 10^6 C nodes, so their
+    kernels run four nodes per workgroup, the widest fall back from workgroup
+    aggregates to a separate scan, and the level above the first wide one
+    does not make the next level's counts in its fill. Pattern, values, pair
+    counts and C's nodes per level against the oracle, for A*A and A^T*A."""
+    from tests._util import transpose
+    A = wl.random_blocks(2048, 2048, 41943, 16, seed=41)
+    ref, C = check_f64(qt, A, A, 16, same=True)
+    _say("wide levels: C blocks", C.nnz)
+    assert C.nnz > 300000    # the leaf level is past the aggregate path
+    At = transpose(A)
+    ref_t, ost_t = oracle.multiply(At, A, 16)
+    hA = qt.from_blockmatrix(A, 16)
+    hCt = qt.multiply_ex(hA, hA, trans_a=True)
+    I, J, V = hCt.to_blocks("f64")
+    got = wl.BlockMatrix(A.n_cols, A.n_cols, 16, I, J, V)
+    same_pat, _, e_f, _ = compare(ref_t, got)
+    assert same_pat and e_f <= TOL64
+    assert hCt.stats()["pairs"].tolist() == ost_t.mul_tasks.tolist()
+    assert hCt.levels().tolist() == ost_t.c_nodes.tolist()
+
+
 def test_leaf_size_independent_bitwise(qt):
     rng = np.random.default_rng(4)
     A = random_pattern(rng, 96, 96, 0.06, 32)
