@@ -102,6 +102,38 @@ def test_decay32768_full(qt):
     assert e["f64"] <= 1e-12
 
 
+def test_decay32768_every_block(qt):
+    """The headline workload with every C block against the oracle's
+    quadtree multiply (not a sample): FP64 componentwise within 1e-12 of
+    (|A||B|)_ij; FP32 and BF16X3 within their a-priori bounds with k the
+    largest number of block products of any C block."""
+    import scipy.sparse as sp
+    from tests._util import compare
+    A = wl.config("decay32768")
+    leaf = wl.CONFIGS["decay32768"]["leaf"]
+    ref, _ = oracle.multiply(A, A, leaf)
+    absAB, _ = oracle.multiply(A, A, leaf, use_abs=True)
+    # block products of every C block: the 0/1 pattern product, in C's (I, J) order
+    S = sp.csr_matrix((np.ones(A.nnz), (A.I, A.J)), shape=(A.nb_rows, A.nb_cols))
+    k = np.asarray((S @ S)[ref.I, ref.J]).ravel()[:, None, None]
+    h = qt.from_blockmatrix(A, leaf)
+    b = A.b
+    for prec in ("f64", "f32", "bf16x3"):
+        _say("decay32768 every block", prec)
+        C = qt.multiply(h, h, prec)
+        I, J, V = C.to_blocks("f32" if prec == "f32" else "f64")
+        got = wl.BlockMatrix(A.n_rows, A.n_cols, b, I, J, V.astype(np.float64))
+        same, _, e_f, e_cw = compare(ref, got, absAB)
+        assert same
+        if prec == "f64":
+            assert e_cw <= 1e-12 and e_f <= 1e-12, (e_cw, e_f)
+        else:
+            rel = (k * b + 2) * 2.0 ** -24 if prec == "f32" else 3 * 2.0 ** -16 + (3 * b + 4) * 2.0 ** -24
+            err = np.abs(got.V - ref.V)
+            assert np.all(err <= rel * absAB.V + 4 * 2.0 ** -126 * k * b), prec
+        C.free()
+
+
 def test_random65536_full(qt):
     e = _full_case(qt, "random65536", ["f64", "f32"])
     assert e["f64"] <= 1e-12
