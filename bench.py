@@ -333,6 +333,11 @@ def bench_rmat(args, qt, torch, wl):
 
 
 def bench_batch(args, qt, torch, wl):
+    """The batch64 workload as the line's main result."""
+    print(json.dumps(batch_result(args, qt, torch, wl)), flush=True)
+
+
+def batch_result(args, qt, torch, wl):
     """64 independent C = A*B (uneven size, fill and pattern) in one launch.
 
     Leaf size per pattern class from the leaf tuner; the plan's schedule from
@@ -429,7 +434,8 @@ def bench_batch(args, qt, torch, wl):
                        "numeric_tflops": flops / (seq_numeric_ms * 1e-3) / 1e12},
         "speedup_vs_sequential": t_seq * 1e3 / exec_ms,
     }
-    print(json.dumps(out), flush=True)
+    plan.destroy()
+    return out
 
 
 def main():
@@ -444,6 +450,8 @@ def main():
     ap.add_argument("--no-paths", action="store_true", help="time only --prec")
     ap.add_argument("--no-hbm-config", action="store_true",
                     help="leave out the random65536 fp64/fp32 entry of the default run")
+    ap.add_argument("--no-large-configs", action="store_true",
+                    help="leave out the decay131072 and batch64 entries of the default run")
     ap.add_argument("--ops", action="store_true",
                     help="time the other operations (transposes, symmetric square, add, truncate) on --workload")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -642,6 +650,17 @@ def main():
         hbm = hbm_config_entry(qt, torch, wl, "random65536", args.steps, args.warmup)
         failed += [msg for prec, e in hbm["paths"].items() for msg in check_path(e, prec)]
 
+    # the b = 64 decay workload (LDS-shared kernels) and the 64-problem batch,
+    # so that their figures come from the same run
+    large = batch = None
+    if not args.no_paths and not args.no_large_configs and args.workload == "decay32768":
+        large = large_config_entry(qt, torch, wl, "decay131072", max(5, args.steps // 2), max(3, args.warmup // 4))
+        failed += [msg for prec, e in large["paths"].items() for msg in check_path(e, prec)]
+        bargs = argparse.Namespace(**vars(args))
+        bargs.prec, bargs.batch_prec_explicit = "f32", True
+        bargs.steps, bargs.warmup = max(5, args.steps // 2), 3
+        batch = batch_result(bargs, qt, torch, wl)
+
     # the batched block GEMM's practical peak, shaped like the paper's Table 2
     # (64000 uniform b x b products, one operand pair reused)
     practical = None
@@ -682,6 +701,8 @@ def main():
             "what": "qt_build from host block lists + qt_multiply + qt_to_blocks to host (PCIe both ways)"},
         "paths": paths,
         "hbm_config": hbm,
+        "large_config": large,
+        "batch": batch,
         "practical_peak": practical,
         "checks": {"tolerance": TOLERANCE, "failed": failed,
                    "what": "C block pattern equal to the oracle's; errors against the fp64 oracle within "
@@ -745,6 +766,65 @@ def hbm_config_entry(qt, torch, wl, name, steps, warmup, samples=64):
             f"of the {entry['roofline']['bound']} roof)")
         paths[prec] = entry
     paths["f32"]["speedup_vs_f64"] = paths["f32"]["tflops"] / paths["f64"]["tflops"]
+    hA.free()
+    return {"workload": name, "n": A.n_rows, "b": b, "leaf": leaf, "nnz_A": A.nnz, "op": "C = A*A",
+            "paths": paths}
+
+
+def large_config_entry(qt, torch, wl, name, steps, warmup, samples=64):
+    """Timed FP64, FP32 and BF16X3 multiplies of workload `name` (C = A*A),
+    each numeric kernel against its MFMA roofline; the C pattern compared
+    whole with the boolean product of A's block pattern, `samples` C blocks
+    with the definition C(I,J) = sum_K A(I,K) A(K,J)."""
+    import numpy as np
+    import oracle
+    cfg = wl.CONFIGS[name]
+    log(f"bench: generating {name}")
+    A = wl.config(name)
+    b, leaf = A.b, cfg["leaf"]
+    hA = qt.from_blockmatrix(A, leaf)
+    ref_pos = oracle.pattern_by_definition(A, A)
+    rng = np.random.default_rng(12)
+    pick = np.sort(rng.choice(len(ref_pos), size=min(samples, len(ref_pos)), replace=False))
+    sI = (ref_pos[pick] // A.nb_cols).astype(np.int32)
+    sJ = (ref_pos[pick] % A.nb_cols).astype(np.int32)
+    index = oracle.make_index(A, A)
+    sref = np.stack([oracle.block_by_definition(A, A, i, j, index) for i, j in zip(sI, sJ)])
+    paths = {}
+    for prec in ("f64", "f32", "bf16x3"):
+        qt.prepare(hA, prec)
+        log(f"bench: {name} {prec}: {warmup} warmup + {steps} timed steps")
+        dt, prof, C = timed_steps(qt, torch, hA, prec, steps, warmup)
+        P = C.stats()["products"]
+        flops = 2.0 * b ** 3 * P
+        num_ms = prof["numeric_ms"] / max(prof["calls"], 1)
+        # operand bytes per element: fp64 A; fp32 A; bf16 hi and lo of A and of its transposed
+        # copy; C in fp32 for the FP32 path, else fp64
+        alg = (A.nnz * {"f64": 8, "f32": 4, "bf16x3": 8}[prec] + C.nblocks * (4 if prec == "f32" else 8)) * b * b
+        I, J = C.pattern()
+        pos = I.astype(np.int64) * A.nb_cols + J
+        if prec == "bf16x3":
+            # the split path's MFMAs are bf16: three per block product, against the bf16 rate
+            roof = roofline_bound(3 * flops, alg, num_ms, PEAK["bf16x3"])
+        else:
+            roof = roofline_bound(flops, alg, num_ms, PEAK[prec])
+        entry = {"tflops": flops * steps / dt / 1e12, "ms_per_step": dt / steps * 1e3, "numeric_ms": num_ms,
+                 "numeric_tflops": flops / (num_ms * 1e-3) / 1e12, "block_products": P, "nnz_C": C.nblocks,
+                 "roofline": roof, "pattern_matches_oracle": bool(np.array_equal(pos, ref_pos))}
+        if entry["pattern_matches_oracle"]:
+            V, F = C.get_blocks(sI, sJ, "f64")
+            d = V - sref
+            entry["e_max"] = float(np.abs(d).max())
+            entry["e_max_rel"] = float(np.abs(d).max() / np.abs(sref).max())
+            entry["e_F"] = float(np.linalg.norm(d) / np.linalg.norm(sref))
+            entry["error_sample"] = f"{len(sI)} C blocks drawn uniformly, against the definition"
+        C.free()
+        log(f"bench: {name} {prec}: {entry['tflops']:.2f} TFLOP/s end to end, numeric {num_ms:.3f} ms "
+            f"({entry['roofline']['frac']:.2f} of the {'bf16 ' if prec == 'bf16x3' else ''}"
+            f"{entry['roofline']['bound']} roof)")
+        paths[prec] = entry
+    for prec in ("f32", "bf16x3"):
+        paths[prec]["speedup_vs_f64"] = paths[prec]["tflops"] / paths["f64"]["tflops"]
     hA.free()
     return {"workload": name, "n": A.n_rows, "b": b, "leaf": leaf, "nnz_A": A.nnz, "op": "C = A*A",
             "paths": paths}
