@@ -818,6 +818,7 @@ def large_config_entry(qt, torch, wl, name, steps, warmup, samples=64):
             entry["e_max_rel"] = float(np.abs(d).max() / np.abs(sref).max())
             entry["e_F"] = float(np.linalg.norm(d) / np.linalg.norm(sref))
             entry["error_sample"] = f"{len(sI)} C blocks drawn uniformly, against the definition"
+        entry["roofline"]["traffic"] = measured_traffic(name, prec)
         C.free()
         log(f"bench: {name} {prec}: {entry['tflops']:.2f} TFLOP/s end to end, numeric {num_ms:.3f} ms "
             f"({entry['roofline']['frac']:.2f} of the {'bf16 ' if prec == 'bf16x3' else ''}"

@@ -326,7 +326,7 @@ void qt_free(qt_matrix* M);
  *               at once, each taking a contiguous run of work items that
  *               holds an equal share of the work (block products plus one per
  *               C block, summed when the plan is created; no counter);
- *   schedule 2  persistent, dynamic per XCD: each workgroup takes 4 items at
+ *   schedule 2  persistent, dynamic per XCD: each workgroup takes 2 items at
  *               a time from a counter of its XCD, over the flat grid's runs
  *               of neighbouring items per XCD;
  *   schedule 3  persistent, dynamic: 16 items at a time from a counter;

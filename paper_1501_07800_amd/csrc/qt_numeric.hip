@@ -952,7 +952,7 @@ void launch_numeric(const NumericArgs& a, hipStream_t s) {
 //                  equal share of the work (block products plus one per C
 //                  block, summed at plan creation), so no counter, no
 //                  dispatch per item and no tail of long items on few waves;
-//   xcd-dynamic:   a persistent grid whose workgroups take 4 items at a time
+//   xcd-dynamic:   a persistent grid whose workgroups take 2 items at a time
 //                  from a counter per XCD, over the flat grid's XCD runs;
 //   dynamic-16:    a persistent grid that takes 16 items at a time from one
 //                  counter until none are left.
@@ -1131,7 +1131,7 @@ __global__ __launch_bounds__(LDS ? 256 : 64) void k_batch_balanced(
 // free. The next grab is taken while the current items run. Every item is
 // taken exactly once wherever a workgroup really runs (the counters are
 // device-wide atomics); a workgroup leaves at its first position past the end.
-constexpr int XCD_GRAB = 4;
+constexpr int XCD_GRAB = 2;
 
 template <int KIND, int BS, bool LDS>
 __global__ __launch_bounds__(LDS ? 256 : 64) void k_batch_xcd(
