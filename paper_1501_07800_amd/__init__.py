@@ -144,58 +144,78 @@ def set_allocator(alloc, free_):
 class TorchAllocator:
     """Device memory from torch's caching allocator.
 
-    A buffer is a uint8 tensor allocated with ``stream`` current, so torch
-    ties it to that stream. At free time the tensor is marked as used on the
-    freeing stream (``record_stream``): torch then hands the memory out again
-    only after the work queued there so far has finished, which is the
-    ordering qt_set_allocator asks for.
+    A buffer is a raw block of torch's caching allocator, allocated on the
+    stream the library names, so torch ties it to that stream. A buffer freed
+    on the stream it was made on goes back to torch at once: torch hands it
+    out again only to later work on that stream. A buffer freed on another
+    stream (its last use was queued there) goes back once an event recorded
+    on that stream has completed, checked at every later alloc or free: that
+    is the ordering qt_set_allocator asks for. ``outstanding()`` counts the
+    buffers the library holds; ``pending()`` those freed but waiting for
+    their event.
     """
 
     def __init__(self):
+        import collections
         import threading
         import torch
         self._torch = torch
-        self._live = {}
+        self._raw_alloc = torch._C._cuda_cudaCachingAllocator_raw_alloc
+        self._raw_delete = torch._C._cuda_cudaCachingAllocator_raw_delete
+        self._live = {}                            # pointer -> stream it was made on
+        self._waiting = collections.deque()        # (event, pointer), in the order freed
+        self._events = []                          # completed events, for reuse
         self._streams = {}
         self._lock = threading.Lock()
 
     def _stream(self, ptr):
-        torch = self._torch
-        if not ptr:
-            return torch.cuda.default_stream()
-        with self._lock:
-            st = self._streams.get(ptr)
-            if st is None:
-                st = torch.cuda.ExternalStream(ptr)
-                self._streams[ptr] = st
+        st = self._streams.get(ptr)
+        if st is None:
+            torch = self._torch
+            st = torch.cuda.ExternalStream(ptr) if ptr else torch.cuda.default_stream()
+            self._streams[ptr] = st
         return st
 
+    def _drain(self):
+        # under the lock: give back the buffers whose last use has finished
+        while self._waiting and self._waiting[0][0].query():
+            ev, p = self._waiting.popleft()
+            self._raw_delete(p)
+            self._events.append(ev)
+
     def alloc(self, nbytes, stream):
-        torch = self._torch
-        try:
-            st = self._stream(stream)
-            with torch.cuda.stream(st):
-                t = torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=torch.cuda.current_device())
-        except Exception:
-            return None
-        p = t.data_ptr()
+        st = stream or 0
         with self._lock:
-            self._live[p] = (t, stream or 0)
+            self._drain()
+            try:
+                p = self._raw_alloc(max(int(nbytes), 1), st)
+            except Exception:
+                return None
+            self._live[p] = st
         return p
 
     def free(self, p, stream):
+        st = stream or 0
         with self._lock:
-            entry = self._live.pop(p, None)
-        if entry is None:
-            return
-        t, made_on = entry
-        if (stream or 0) != made_on:
-            t.record_stream(self._stream(stream))
-        del t
+            made_on = self._live.pop(p, None)
+            if made_on is None:
+                return
+            if st == made_on:
+                self._raw_delete(p)
+            else:
+                ev = self._events.pop() if self._events else self._torch.cuda.Event()
+                ev.record(self._stream(st))
+                self._waiting.append((ev, p))
+            self._drain()
 
     def outstanding(self) -> int:
         with self._lock:
             return len(self._live)
+
+    def pending(self) -> int:
+        with self._lock:
+            self._drain()
+            return len(self._waiting)
 
 
 def use_torch_allocator() -> TorchAllocator:

@@ -1064,13 +1064,44 @@ __global__ void k_publish(const int32_t* __restrict__ counts, int n, HostSlot* s
     if (threadIdx.x == 0) __hip_atomic_store(&slot->flag, seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
+// Events that order one stream after another (record on one, wait on the
+// other), kept for reuse per device: a wait already queued keeps the
+// recording it was queued after, so an event can be recorded again as soon as
+// the wait is queued.
+static std::mutex g_order_ev_mu;
+static std::map<int, std::vector<hipEvent_t>> g_order_ev;
+
+static void stream_after(hipStream_t waiter, hipStream_t first) {
+    int dev = 0;
+    QT_HIP(hipGetDevice(&dev));
+    hipEvent_t e = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(g_order_ev_mu);
+        auto& pool = g_order_ev[dev];
+        if (!pool.empty()) {
+            e = pool.back();
+            pool.pop_back();
+        }
+    }
+    if (!e) QT_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    const hipError_t r1 = hipEventRecord(e, first);
+    const hipError_t r2 = r1 == hipSuccess ? hipStreamWaitEvent(waiter, e, 0) : r1;
+    {
+        std::lock_guard<std::mutex> lk(g_order_ev_mu);
+        g_order_ev[dev].push_back(e);
+    }
+    QT_HIP(r1);
+    QT_HIP(r2);
+}
+
 static std::mutex g_slot_mu;
-static std::vector<HostSlot*> g_slot_free;
+static std::vector<std::pair<HostSlot*, HostSlot*>> g_slot_free;   // (host address, device address)
 static uint32_t g_slot_seq = 0;
 
 // A pinned slot for one read-back, returned to the free list on scope exit.
 struct SlotLease {
     HostSlot* slot = nullptr;
+    HostSlot* dslot = nullptr;
     uint32_t seq = 0;
     SlotLease() {
         std::lock_guard<std::mutex> lk(g_slot_mu);
@@ -1079,32 +1110,37 @@ struct SlotLease {
             HostSlot* chunk = nullptr;
             QT_HIP(hipHostMalloc((void**)&chunk, kChunk * sizeof(HostSlot),
                                  hipHostMallocCoherent | hipHostMallocPortable | hipHostMallocMapped));
+            HostSlot* dchunk = nullptr;
+            QT_HIP(hipHostGetDevicePointer((void**)&dchunk, chunk, 0));
             for (int i = 0; i < kChunk; ++i) {
                 chunk[i].flag = 0;
-                g_slot_free.push_back(chunk + i);
+                g_slot_free.emplace_back(chunk + i, dchunk + i);
             }
         }
-        slot = g_slot_free.back();
+        slot = g_slot_free.back().first;
+        dslot = g_slot_free.back().second;
         g_slot_free.pop_back();
         if (++g_slot_seq == 0) ++g_slot_seq;   // 0 never marks a publication
         seq = g_slot_seq;
     }
     ~SlotLease() {
         std::lock_guard<std::mutex> lk(g_slot_mu);
-        g_slot_free.push_back(slot);
+        g_slot_free.emplace_back(slot, dslot);
     }
     SlotLease(const SlotLease&) = delete;
     SlotLease& operator=(const SlotLease&) = delete;
 };
 
-static void read_back_counts(const int32_t* dcount, int n, hipStream_t s, int32_t* out) {
+// Reads n counts from the device after the work queued on s; when `waiter`
+// is given, work queued on it afterwards follows that work too (ordered while
+// the counts are still on their way).
+static void read_back_counts(const int32_t* dcount, int n, hipStream_t s, int32_t* out, hipStream_t waiter) {
     if (n > kPublishMax) fail(QT_ERR_UNSUPPORTED, "tree too deep for the count read-back");
     SlotLease lease;
     __atomic_store_n(&lease.slot->flag, 0u, __ATOMIC_RELAXED);
-    HostSlot* dslot = nullptr;
-    QT_HIP(hipHostGetDevicePointer((void**)&dslot, lease.slot, 0));
-    k_publish<<<1, 64, 0, s>>>(dcount, n, dslot, lease.seq);
+    k_publish<<<1, 64, 0, s>>>(dcount, n, lease.dslot, lease.seq);
     QT_LAUNCH("k_publish");
+    if (waiter) stream_after(waiter, s);
     const auto t0 = std::chrono::steady_clock::now();
     for (uint64_t it = 1;; ++it) {
         if (__atomic_load_n(&lease.slot->flag, __ATOMIC_ACQUIRE) == lease.seq) break;
@@ -1264,11 +1300,7 @@ void symbolic(qt_matrix* A, qt_matrix* B, qt_prec prec, hipStream_t s, SymbolicO
         // stream: made there, and the traversal waits for them
         build_norms(A, s);
         build_norms(B, s);
-        hipEvent_t ready = nullptr;
-        QT_HIP(hipEventCreateWithFlags(&ready, hipEventDisableTiming));
-        QT_HIP(hipEventRecord(ready, s));
-        QT_HIP(hipStreamWaitEvent(ss, ready, 0));
-        QT_HIP(hipEventDestroy(ready));
+        stream_after(ss, s);
     }
 
     // pair counts per level and block products: exact, or upper bounds when
@@ -1625,7 +1657,9 @@ void symbolic(qt_matrix* A, qt_matrix* B, qt_prec prec, hipStream_t s, SymbolicO
 
     // the one synchronization: node and block counts of C
     std::vector<int32_t> hc(3 * L + 4);
-    read_back_counts(dcount, (int)hc.size(), ss, hc.data());
+    // the caller's stream follows the traversal from here on (the numeric
+    // kernel first); a launch order built below adds a second wait
+    read_back_counts(dcount, (int)hc.size(), ss, hc.data(), s);
     for (int l = 0; l <= L; ++l) {
         if (hc[l] < 0 || hc[l] > ncap[l]) fail(QT_ERR_DEVICE, "symbolic phase: C node count out of range");
         if (hc[2 * L + 3 + l] < 0 || hc[2 * L + 3 + l] > hc[l])
@@ -1655,15 +1689,7 @@ void symbolic(qt_matrix* A, qt_matrix* B, qt_prec prec, hipStream_t s, SymbolicO
                                                                     (int32_t)kdim, (int32_t)nwg, knext, order);
         QT_LAUNCH("k_korder_place");
         if (prof) QT_HIP(hipEventRecord(ev.e1, ss));   // the symbolic phase ends here then
-    }
-    {
-        // work the caller queues on s from here on (the numeric kernel first)
-        // follows the traversal
-        hipEvent_t done = nullptr;
-        QT_HIP(hipEventCreateWithFlags(&done, hipEventDisableTiming));
-        QT_HIP(hipEventRecord(done, ss));
-        QT_HIP(hipStreamWaitEvent(s, done, 0));
-        QT_HIP(hipEventDestroy(done));
+        stream_after(s, ss);
     }
 
     // C's tree (NIL-normalised): views into its arena
