@@ -204,3 +204,33 @@ def test_operand_form_made_on_a_busy_stream(qt, prec):
     assert same
     assert e_cw <= 1e-4, e_cw          # far above either path's bound; unconverted values give O(1)
     del C1
+
+
+def test_torch_allocator_defers_cross_stream_frees(qt):
+    """torch's raw blocks behind qt_set_allocator: a buffer freed on the
+    stream it was made on goes back at once; one freed on another stream,
+    whose work is still running, waits for an event there and is not handed
+    out again before that work has finished."""
+    import torch
+    ta = qt.TorchAllocator()
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    n = 1 << 20
+    p = ta.alloc(n, s1.cuda_stream)
+    assert p and p % 256 == 0 and ta.outstanding() == 1
+    q = ta.alloc(n, s1.cuda_stream)
+    ta.free(q, s1.cuda_stream)                 # same stream: back to torch now
+    assert ta.outstanding() == 1 and ta.pending() == 0
+    with torch.cuda.stream(s2):
+        torch.cuda._sleep(200_000_000)          # s2 busy (a bounded spin) when p is freed there
+    ta.free(p, s2.cuda_stream)
+    assert ta.outstanding() == 0
+    assert ta.pending() == 1                    # its event on s2 has not completed
+    r = ta.alloc(n, s1.cuda_stream)
+    assert r != p                               # p is not reused while s2 may still use it
+    s2.synchronize()
+    assert ta.pending() == 0                    # returned to torch once s2's work is done
+    ta.free(r, s1.cuda_stream)
+    assert ta.outstanding() == 0 and ta.pending() == 0
+    # a failed allocation is reported as None (the library turns it into QT_ERR_OOM)
+    assert ta.alloc(1 << 60, s1.cuda_stream) is None
+    torch.cuda.synchronize()
