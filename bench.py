@@ -464,8 +464,8 @@ def main():
         import workloads as wl
         return traffic_from_counters(*args.traffic_from, args.workload, args.prec, wl.CONFIGS[args.workload]["b"])
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: the multiply has no multi-GPU path in this build "
-              "(see the sharding paragraph of the design notes).", file=sys.stderr)
+        print("bench.py runs on one GPU only: the multiply has no multi-GPU path; --gpus takes 1.",
+              file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

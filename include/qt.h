@@ -47,7 +47,7 @@ typedef enum {
     QT_ERR_DUPLICATE = 3,    /* the same (I, J) block given twice */
     QT_ERR_OOM = 4,          /* a device or host allocation failed */
     QT_ERR_DEVICE = 5,       /* a HIP call or a kernel reported an error */
-    QT_ERR_UNSUPPORTED = 6   /* a size or mode this build does not handle */
+    QT_ERR_UNSUPPORTED = 6   /* a size or mode the library does not handle */
 } qt_status;
 
 typedef enum {
@@ -91,7 +91,7 @@ qt_status qt_set_allocator(void* (*alloc)(size_t bytes, void* stream, void* ctx)
  * Build a matrix from a list of nonzero blocks (Sec. 3.1 and 4.1).
  *
  * n_rows, n_cols: scalar dimensions; both multiples of block_size.
- * block_size:     b, the side of a block. This build runs b in {16, 32, 64}.
+ * block_size:     b, the side of a block. The library runs b in {16, 32, 64}.
  * leaf_size:      side of a leaf; leaf_size / b must be a power of two <= 8.
  * nblocks:        number of blocks listed (0 gives an all-NIL matrix).
  * I, J:           block row / column of each block, 0 <= I < n_rows/b,
