@@ -312,11 +312,13 @@ void qt_free(qt_matrix* M);
  * Errors: ARG, SHAPE, OOM, DEVICE, UNSUPPORTED.
  *
  * qt_plan_execute computes every C_i: one kernel launch (plus a one-thread
- * counter reset for the dynamic schedules) that allocates nothing and does
- * not synchronize. With use_graph != 0 the first call captures that launch
- * sequence into a HIP graph and every call replays it on `stream`; with
- * use_graph == 0 the kernels are launched directly. Executions on one plan
- * must not overlap (they share the plan's work counter and the C_i).
+ * counter reset for the dynamic schedules, a kernel, not a memset) on
+ * `stream`, which allocates nothing and does not synchronize, so a caller may
+ * capture it into a HIP graph of its own. qt_plan_replay computes the same:
+ * its first call captures that launch sequence into a HIP graph the plan
+ * keeps, and every call replays the graph on `stream` (one launch from the
+ * host). Executions on one plan, by either call, must not overlap (they share
+ * the plan's work counter and the C_i). Errors: ARG (NULL plan), DEVICE.
  *
  * A plan runs in one of QT_PLAN_CONFIGS configurations, a schedule (0 .. 3)
  * plus option bits:
@@ -358,7 +360,8 @@ void qt_free(qt_matrix* M);
 #define QT_PLAN_CONFIGS 16
 qt_status qt_plan_create(int32_t count, const qt_matrix* const* A, const qt_matrix* const* B, qt_prec prec,
                          void* stream, qt_plan** plan);
-qt_status qt_plan_execute(qt_plan* plan, void* stream, int use_graph);
+qt_status qt_plan_execute(qt_plan* plan, void* stream);
+qt_status qt_plan_replay(qt_plan* plan, void* stream);
 qt_status qt_plan_tune(qt_plan* plan, void* stream, int reps, int32_t* schedule, float* ms);
 qt_status qt_plan_set_schedule(qt_plan* plan, int32_t schedule);   /* a configuration, 0 .. QT_PLAN_CONFIGS-1 */
 qt_status qt_plan_result(const qt_plan* plan, int32_t i, qt_matrix** C);

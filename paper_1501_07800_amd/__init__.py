@@ -84,7 +84,9 @@ def _load():
     lib.qt_plan_create.restype = ctypes.c_int
     lib.qt_plan_create.argtypes = [i32, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.c_int, vp, ctypes.POINTER(vp)]
     lib.qt_plan_execute.restype = ctypes.c_int
-    lib.qt_plan_execute.argtypes = [vp, vp, ctypes.c_int]
+    lib.qt_plan_execute.argtypes = [vp, vp]
+    lib.qt_plan_replay.restype = ctypes.c_int
+    lib.qt_plan_replay.argtypes = [vp, vp]
     lib.qt_plan_tune.restype = ctypes.c_int
     lib.qt_plan_tune.argtypes = [vp, vp, ctypes.c_int, i32p, ctypes.POINTER(ctypes.c_float)]
     lib.qt_plan_set_schedule.restype = ctypes.c_int
@@ -245,7 +247,7 @@ def _default_allocator():
 
 
 EXPORTS = ("qt_build", "qt_multiply", "qt_multiply_ex", "qt_multiply_tau", "qt_norms", "qt_add", "qt_truncate", "qt_sysq", "qt_info", "qt_to_blocks", "qt_to_blocks_noalloc", "qt_get_blocks", "qt_stats", "qt_levels", "qt_prepare", "qt_free",
-           "qt_plan_create", "qt_plan_execute", "qt_plan_tune", "qt_plan_set_schedule", "qt_plan_result", "qt_plan_info",
+           "qt_plan_create", "qt_plan_execute", "qt_plan_replay", "qt_plan_tune", "qt_plan_set_schedule", "qt_plan_result", "qt_plan_info",
            "qt_plan_destroy", "qt_tune_leaf", "qt_tune_cache", "qt_tune_leaf_cached", "qt_plan_tune_cached", "qt_profile", "qt_profile_read", "qt_probe_mfma", "qt_probe_batched", "qt_last_error", "qt_version",
            "qt_set_allocator")
 NOALLOC_MAX_BLOCKS = 1 << 20   # QT_NOALLOC_MAX_BLOCKS
@@ -450,7 +452,10 @@ class Plan:
         self._keep = (list(As), list(Bs))
 
     def execute(self, stream=None, graph: bool = True):
-        _check(lib.qt_plan_execute(self._h, _stream_ptr(stream), 1 if graph else 0))
+        """qt_plan_replay (graph=True: the plan's captured graph replayed) or
+        qt_plan_execute (graph=False: the kernels launched on `stream`)."""
+        fn = lib.qt_plan_replay if graph else lib.qt_plan_execute
+        _check(fn(self._h, _stream_ptr(stream)))
 
     def tune(self, reps: int = 3, stream=None):
         """qt_plan_tune: the fastest configuration's name and the mean time

@@ -414,13 +414,24 @@ qt_status qt_plan_create(int32_t count, const qt_matrix* const* A, const qt_matr
     QT_GUARD_END
 }
 
-qt_status qt_plan_execute(qt_plan* plan, void* stream, int use_graph) {
+qt_status qt_plan_execute(qt_plan* plan, void* stream) {
     if (!plan) {
         set_last_error("NULL plan");
         return QT_ERR_ARG;
     }
     QT_GUARD_BEGIN
-    plan_execute(plan, (hipStream_t)stream, use_graph);
+    plan_execute(plan, (hipStream_t)stream, 0);
+    return QT_OK;
+    QT_GUARD_END
+}
+
+qt_status qt_plan_replay(qt_plan* plan, void* stream) {
+    if (!plan) {
+        set_last_error("NULL plan");
+        return QT_ERR_ARG;
+    }
+    QT_GUARD_BEGIN
+    plan_execute(plan, (hipStream_t)stream, 1);
     return QT_OK;
     QT_GUARD_END
 }

@@ -8,9 +8,9 @@
 // (Morton order, whose neighbouring blocks share operand blocks in cache, or
 // grouped by inner index where C blocks average under two block products).
 // qt_plan_execute runs the numeric phase of the whole batch as one kernel
-// launch that allocates nothing and never synchronizes; the first graph
-// execution captures it (counter reset kernel + batch kernel) into a HIP
-// graph that later executions replay. qt_plan_tune times each configuration
+// launch that allocates nothing and never synchronizes (a caller may capture
+// it); the first qt_plan_replay captures it (counter reset kernel + batch
+// kernel) into a HIP graph that later replays launch. qt_plan_tune times each configuration
 // of the batch kernel (schedule, launch order, b = 64 tile shape) on the plan
 // itself and keeps the fastest.
 //

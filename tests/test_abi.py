@@ -81,7 +81,8 @@ def test_plan_and_tuner_argument_checks():
     assert qt.lib.qt_plan_create(0, None, None, 0, None, ctypes.byref(out)) == qt.QT_ERR_ARG
     assert out.value is None
     assert qt.lib.qt_plan_create(1, None, None, 0, None, None) == qt.QT_ERR_ARG
-    assert qt.lib.qt_plan_execute(None, None, 1) == qt.QT_ERR_ARG
+    assert qt.lib.qt_plan_execute(None, None) == qt.QT_ERR_ARG
+    assert qt.lib.qt_plan_replay(None, None) == qt.QT_ERR_ARG
     assert qt.lib.qt_plan_tune(None, None, 1, None, None) == qt.QT_ERR_ARG
     assert qt.lib.qt_plan_set_schedule(None, 0) == qt.QT_ERR_ARG
     assert qt.lib.qt_plan_result(None, 0, ctypes.byref(out)) == qt.QT_ERR_ARG

@@ -105,6 +105,66 @@ def test_plan_graph_replays(qt):
     plan.destroy()
 
 
+def test_plan_execute_captured_by_the_caller(qt):
+    """qt_plan_execute launches without allocating or synchronizing, so a
+    caller can capture it into a graph of its own: the C_i are computed by
+    the first replay (they were never computed before it), and every later
+    replay, with other GPU work between, gives them bit for bit again; with
+    a dynamic schedule the replays also re-run the counter reset (a replay
+    that skipped the work would take no time)."""
+    import torch
+    probs = _problems(seed=2)
+    hs = [(qt.from_blockmatrix(A, 64), qt.from_blockmatrix(B, 64)) for A, B in probs]
+    plan = qt.Plan([a for a, _ in hs], [b for _, b in hs], "f64")
+    plan.set_schedule("flat")
+    s = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        plan.execute(stream=s, graph=False)
+    # computed only now, while the plan's C_i exist, so no C_i can hold them
+    singles = [qt.multiply(a, b) for a, b in hs]
+    ref = [_blocks(h, A, B) for h, (A, B) in zip(singles, probs)]
+    other = qt.from_blockmatrix(probs[2][0], 64)
+    for rep in range(4):
+        _say("caller graph replay", rep)
+        junk = qt.multiply(other, other)
+        x = torch.ones(1 << 20, device="cuda")
+        x.mul_(2.0)
+        g.replay()
+        torch.cuda.synchronize()
+        for i, (A, B) in enumerate(probs):
+            assert np.array_equal(_blocks(plan.result(i), A, B).V, ref[i].V), (rep, i)
+        junk.free()
+    del g
+    # a dynamic schedule: warmed eagerly (its grid size is looked up once), then captured
+    plan.set_schedule("xcd-dynamic")
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    with torch.cuda.stream(s):
+        e0.record()
+        plan.execute(stream=s, graph=False)
+        e1.record()
+    torch.cuda.synchronize()
+    eager_ms = e0.elapsed_time(e1)
+    g2 = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g2, stream=s):
+        plan.execute(stream=s, graph=False)
+    for rep in range(3):
+        with torch.cuda.stream(s):
+            e0.record()
+            g2.replay()
+            e1.record()
+        torch.cuda.synchronize()
+        _say("dynamic replay", rep, "ms", e0.elapsed_time(e1), "eager", eager_ms)
+        assert e0.elapsed_time(e1) > 0.3 * eager_ms
+        for i, (A, B) in enumerate(probs):
+            assert np.array_equal(_blocks(plan.result(i), A, B).V, ref[i].V), (rep, i)
+    del g2
+    for h in singles:
+        h.free()
+    plan.destroy()
+
+
 @pytest.mark.parametrize("prec,b", [("f32", 32), ("bf16x3", 32), ("f64", 64), ("bf16x3", 64), ("f64", 16)])
 def test_plan_precisions_and_block_sizes(qt, prec, b):
     rng = np.random.default_rng(7)
