@@ -215,11 +215,20 @@ qt_status qt_truncate(const qt_matrix* M, double eps, void* stream, qt_matrix** 
 qt_status qt_sysq(const qt_matrix* A, qt_prec prec, void* stream, qt_matrix** C);
 
 /*
- * Describe a matrix. Any output pointer may be NULL. nblocks is the number
- * of stored (nonzero) blocks; value_type is QT_F64 or QT_F32.
+ * Describe a matrix (its shape as a quadtree over uniform blocks, Sec. 3.1).
+ * Any output pointer may be NULL; value_type is QT_F64 or QT_F32.
+ * Errors: ARG (NULL matrix).
  */
 qt_status qt_info(const qt_matrix* M, int64_t* n_rows, int64_t* n_cols, int32_t* block_size,
-                  int32_t* leaf_size, int64_t* nblocks, qt_prec* value_type);
+                  int32_t* leaf_size, qt_prec* value_type);
+
+/*
+ * The number of stored (nonzero) blocks of M; zero submatrices are not
+ * stored (Sec. 3.1). Known on the host for every handle the library returns
+ * (a multiply reads its count back before it returns), so this never
+ * synchronizes. Errors: ARG (NULL matrix or output).
+ */
+qt_status qt_nblocks(const qt_matrix* M, int64_t* nblocks);
 
 /*
  * Copy a matrix out as a block list sorted by (I, J), row-major.
@@ -268,13 +277,13 @@ qt_status qt_get_blocks(const qt_matrix* M, int64_t count, const int32_t* I, con
 /*
  * Counters of the multiply that produced C (Sec. 5): pairs[l] is the number
  * of (A node, B node) pairs with both present at quadtree level l
- * (0 = root .. n_levels-1 = leaf level), i.e. the multiply tasks of
- * Algorithm 1 at that level; *products is the number of block products.
- * At most max_levels entries are written. For a matrix from qt_build all
+ * (0 = root .. depth = leaf level, the levels qt_levels counts), i.e. the
+ * multiply tasks of Algorithm 1 at that level; *products (may be NULL) is the
+ * number of block products. At most max_levels entries are written; entries
+ * past the leaf level are not touched. For a matrix from qt_build all
  * counters are zero. Errors: ARG.
  */
-qt_status qt_stats(const qt_matrix* C, int64_t* pairs, int32_t max_levels, int32_t* n_levels,
-                   int64_t* products);
+qt_status qt_stats(const qt_matrix* C, int64_t* pairs, int32_t max_levels, int64_t* products);
 
 /*
  * Nodes of the quadtree per level (Sec. 3.1): nodes[l] is the number of

@@ -61,7 +61,9 @@ def _load():
     lib.qt_sysq.restype = ctypes.c_int
     lib.qt_sysq.argtypes = [vp, ctypes.c_int, vp, ctypes.POINTER(vp)]
     lib.qt_info.restype = ctypes.c_int
-    lib.qt_info.argtypes = [vp, i64p, i64p, i32p, i32p, i64p, ctypes.POINTER(ctypes.c_int)]
+    lib.qt_info.argtypes = [vp, i64p, i64p, i32p, i32p, ctypes.POINTER(ctypes.c_int)]
+    lib.qt_nblocks.restype = ctypes.c_int
+    lib.qt_nblocks.argtypes = [vp, i64p]
     lib.qt_to_blocks.restype = ctypes.c_int
     lib.qt_to_blocks.argtypes = [vp, vp, vp, vp, ctypes.c_int, ctypes.c_int, vp]
     lib.qt_to_blocks_noalloc.restype = ctypes.c_int
@@ -69,7 +71,7 @@ def _load():
     lib.qt_get_blocks.restype = ctypes.c_int
     lib.qt_get_blocks.argtypes = [vp, i64, vp, vp, vp, vp, ctypes.c_int, ctypes.c_int, vp]
     lib.qt_stats.restype = ctypes.c_int
-    lib.qt_stats.argtypes = [vp, i64p, i32, i32p, i64p]
+    lib.qt_stats.argtypes = [vp, i64p, i32, i64p]
     lib.qt_levels.restype = ctypes.c_int
     lib.qt_levels.argtypes = [vp, i64p, i32, i32p]
     lib.qt_prepare.restype = ctypes.c_int
@@ -246,7 +248,7 @@ def _default_allocator():
     return use_torch_allocator()
 
 
-EXPORTS = ("qt_build", "qt_multiply", "qt_multiply_ex", "qt_multiply_tau", "qt_norms", "qt_add", "qt_truncate", "qt_sysq", "qt_info", "qt_to_blocks", "qt_to_blocks_noalloc", "qt_get_blocks", "qt_stats", "qt_levels", "qt_prepare", "qt_free",
+EXPORTS = ("qt_build", "qt_multiply", "qt_multiply_ex", "qt_multiply_tau", "qt_norms", "qt_add", "qt_truncate", "qt_sysq", "qt_info", "qt_nblocks", "qt_to_blocks", "qt_to_blocks_noalloc", "qt_get_blocks", "qt_stats", "qt_levels", "qt_prepare", "qt_free",
            "qt_plan_create", "qt_plan_execute", "qt_plan_replay", "qt_plan_tune", "qt_plan_set_schedule", "qt_plan_result", "qt_plan_info",
            "qt_plan_destroy", "qt_tune_leaf", "qt_tune_cache", "qt_tune_leaf_cached", "qt_plan_tune_cached", "qt_profile", "qt_profile_read", "qt_probe_mfma", "qt_probe_batched", "qt_last_error", "qt_version",
            "qt_set_allocator")
@@ -319,7 +321,8 @@ class Matrix:
         r, c, n = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
         b, leaf, vt = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int()
         _check(lib.qt_info(self._h, ctypes.byref(r), ctypes.byref(c), ctypes.byref(b), ctypes.byref(leaf),
-                           ctypes.byref(n), ctypes.byref(vt)))
+                           ctypes.byref(vt)))
+        _check(lib.qt_nblocks(self._h, ctypes.byref(n)))
         return {"n_rows": r.value, "n_cols": c.value, "b": b.value, "leaf": leaf.value, "nblocks": n.value,
                 "value_type": PREC_NAME[vt.value]}
 
@@ -329,8 +332,10 @@ class Matrix:
 
     def stats(self) -> dict:
         pairs = (ctypes.c_int64 * 64)()
-        nl, prods = ctypes.c_int32(), ctypes.c_int64()
-        _check(lib.qt_stats(self._h, pairs, 64, ctypes.byref(nl), ctypes.byref(prods)))
+        prods = ctypes.c_int64()
+        _check(lib.qt_stats(self._h, pairs, 64, ctypes.byref(prods)))
+        nl = ctypes.c_int32()
+        _check(lib.qt_levels(self._h, None, 0, ctypes.byref(nl)))   # the depth + 1
         return {"pairs": np.array(pairs[:nl.value], np.int64), "products": prods.value}
 
     def levels(self) -> np.ndarray:

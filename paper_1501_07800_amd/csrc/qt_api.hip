@@ -250,7 +250,7 @@ qt_status qt_sysq(const qt_matrix* A, qt_prec prec, void* stream, qt_matrix** C)
 }
 
 qt_status qt_info(const qt_matrix* M, int64_t* n_rows, int64_t* n_cols, int32_t* block_size, int32_t* leaf_size,
-                  int64_t* nblocks, qt_prec* value_type) {
+                  qt_prec* value_type) {
     if (!M) {
         set_last_error("NULL matrix");
         return QT_ERR_ARG;
@@ -259,8 +259,16 @@ qt_status qt_info(const qt_matrix* M, int64_t* n_rows, int64_t* n_cols, int32_t*
     if (n_cols) *n_cols = M->n_cols;
     if (block_size) *block_size = M->b;
     if (leaf_size) *leaf_size = M->leaf;
-    if (nblocks) *nblocks = M->nblocks;
     if (value_type) *value_type = M->vtype;
+    return QT_OK;
+}
+
+qt_status qt_nblocks(const qt_matrix* M, int64_t* nblocks) {
+    if (!M || !nblocks) {
+        set_last_error("NULL matrix or output");
+        return QT_ERR_ARG;
+    }
+    *nblocks = M->nblocks;
     return QT_OK;
 }
 
@@ -300,13 +308,12 @@ qt_status qt_get_blocks(const qt_matrix* M, int64_t count, const int32_t* I, con
     QT_GUARD_END
 }
 
-qt_status qt_stats(const qt_matrix* C, int64_t* pairs, int32_t max_levels, int32_t* n_levels, int64_t* products) {
+qt_status qt_stats(const qt_matrix* C, int64_t* pairs, int32_t max_levels, int64_t* products) {
     if (!C || max_levels < 0 || (max_levels > 0 && !pairs)) {
         set_last_error("bad argument");
         return QT_ERR_ARG;
     }
     const int32_t nl = C->L + 1;
-    if (n_levels) *n_levels = nl;
     for (int32_t l = 0; l < nl && l < max_levels; ++l) pairs[l] = (l < (int32_t)C->pairs.size()) ? C->pairs[l] : 0;
     if (products) *products = C->products;
     return QT_OK;

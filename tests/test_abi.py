@@ -42,8 +42,9 @@ def test_null_handles_rejected():
     out = ctypes.c_void_p()
     assert qt.lib.qt_multiply(None, None, 0, None, ctypes.byref(out)) == qt.QT_ERR_ARG
     assert out.value is None
-    assert qt.lib.qt_info(None, None, None, None, None, None, None) == qt.QT_ERR_ARG
-    assert qt.lib.qt_stats(None, None, 0, None, None) == qt.QT_ERR_ARG
+    assert qt.lib.qt_info(None, None, None, None, None, None) == qt.QT_ERR_ARG
+    assert qt.lib.qt_nblocks(None, None) == qt.QT_ERR_ARG
+    assert qt.lib.qt_stats(None, None, 0, None) == qt.QT_ERR_ARG
     assert qt.lib.qt_build(0, 0, 32, 32, 0, None, None, None, 0, None, None) == qt.QT_ERR_ARG
     assert qt.lib.qt_probe_mfma(0, None, None) == qt.QT_ERR_ARG
     assert qt.lib.qt_to_blocks_noalloc(None, None, None, None, 0, None) == qt.QT_ERR_ARG
