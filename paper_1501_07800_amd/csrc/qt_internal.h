@@ -255,6 +255,7 @@ struct NumericArgs {
     int32_t nseg;
     const int32_t* order;     // launch slot q computes C block order[q] (a permutation
                               // of 0 .. nseg-1); nullptr: block q, i.e. Morton order
+    int by_k;                 // order groups C blocks by inner index (their first product's)
     void* C;                  // fp64 or fp32 C blocks, one per segment
 };
 void launch_numeric(const NumericArgs& a, hipStream_t s);

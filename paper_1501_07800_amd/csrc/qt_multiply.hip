@@ -1719,6 +1719,7 @@ void symbolic(qt_matrix* A, qt_matrix* B, qt_prec prec, hipStream_t s, SymbolicO
     na.prodB = ls.prodB;
     na.seg = ls.cbseg;
     na.order = (leafrow || korder) ? order : nullptr;
+    na.by_k = korder ? 1 : 0;
     na.nseg = nnzC;
     na.C = (prec == QT_F32) ? (void*)C->v32.p : (void*)C->v64.p;
     out.na = na;

@@ -101,8 +101,12 @@ static unsigned xcd_grid(int64_t tiles) {
     return (unsigned)g;
 }
 
-// One wave: tile `sub` of a C block, over the products t0 .. t1-1.
-template <class T, int BS>
+// One wave: tile `sub` of a C block, over the products t0 .. t1-1. BUF: the
+// C tile is written with buffer stores instead of global stores (the same
+// non-temporal policy); measured faster when C blocks are launched grouped by
+// inner index (about one block product per C block, so the kernel is bound
+// by writing C), slower for the FP32 kernel in Morton order.
+template <class T, int BS, bool BUF = false>
 __device__ __forceinline__ void wave_block(const T* __restrict__ A, const T* __restrict__ B,
                                            const int32_t* __restrict__ prodA, const int32_t* __restrict__ prodB,
                                            int32_t t0, int32_t t1, T* __restrict__ c, int sub, int32_t ia0,
@@ -182,7 +186,27 @@ __device__ __forceinline__ void wave_block(const T* __restrict__ A, const T* __r
                         acc[mt][nt] = Mfma<T>::step(ar[mt][ks], br[nt][ks], acc[mt][nt]);
         }
     }
-    if constexpr (G::MT == 2) {
+    if constexpr (G::MT == 2 && BUF) {
+        // a buffer over this C block (BS * BS elements; an offset past it
+        // would be dropped, none is), non-temporal stores (policy bit 1)
+        constexpr int kBufferWord3 = 0x00020000;   // gfx9 raw buffer: 32-bit data format
+        constexpr int kNonTemporal = 2;
+        const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(c, 0, BS * BS * (int)sizeof(T), kBufferWord3);
+#pragma unroll
+        for (int mt = 0; mt < G::MT; ++mt)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const pair_t v = {acc[mt][0][i], acc[mt][1][i]};
+                const int off = (int)sizeof(T) * ((wm + mt * 16 + Mfma<T>::row(g, i)) * BS + wn + 2 * r16);
+                if constexpr (sizeof(T) == 8) {
+                    typedef unsigned int u4 __attribute__((ext_vector_type(4)));
+                    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u4, v), rs, off, 0, kNonTemporal);
+                } else {
+                    typedef unsigned int u2 __attribute__((ext_vector_type(2)));
+                    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, v), rs, off, 0, kNonTemporal);
+                }
+            }
+    } else if constexpr (G::MT == 2) {
 #pragma unroll
         for (int mt = 0; mt < G::MT; ++mt)
 #pragma unroll
@@ -442,6 +466,27 @@ __global__ __launch_bounds__(64, (MinWaves<T, BS>::value)) void k_numeric(const 
     const int32_t t0 = seg[s];
     wave_block<T, BS>(A, B, prodA, prodB, t0, seg[s + 1], C + (size_t)s * (BS * BS), (int)(tile % G::WPB),
                       prodA[t0], prodB[t0]);
+}
+
+// k_numeric for C blocks launched grouped by inner index (`order` is that
+// order), writing C with buffer stores.
+template <class T, int BS>
+__global__ __launch_bounds__(64, (MinWaves<T, BS>::value)) void k_numeric_byk(const T* __restrict__ A,
+                                                                             const T* __restrict__ B,
+                                                                             const int32_t* __restrict__ prodA,
+                                                                             const int32_t* __restrict__ prodB,
+                                                                             const int32_t* __restrict__ seg,
+                                                                             int32_t nseg,
+                                                                             const int32_t* __restrict__ order,
+                                                                             T* __restrict__ C) {
+    typedef Geo<BS> G;
+    const int64_t tile = xcd_logical<>(blockIdx.x);
+    const int64_t q = tile / G::WPB;
+    if (q >= nseg) return;
+    const int64_t s = order[q];
+    const int32_t t0 = seg[s];
+    wave_block<T, BS, true>(A, B, prodA, prodB, t0, seg[s + 1], C + (size_t)s * (BS * BS), (int)(tile % G::WPB),
+                            prodA[t0], prodB[t0]);
 }
 
 template <int BS>
@@ -730,6 +775,12 @@ static void launch_t(const NumericArgs& a, hipStream_t s) {
     }
     typedef Geo<BS> G;
     const unsigned grid = xcd_grid<>((int64_t)a.nseg * G::WPB);
+    if (a.by_k && a.order) {
+        k_numeric_byk<T, BS><<<grid, 64, 0, s>>>((const T*)a.A, (const T*)a.B, a.prodA, a.prodB, a.seg, a.nseg,
+                                                 a.order, (T*)a.C);
+        QT_LAUNCH("k_numeric_byk");
+        return;
+    }
     k_numeric<T, BS><<<grid, 64, 0, s>>>((const T*)a.A, (const T*)a.B, a.prodA, a.prodB, a.seg, a.nseg, a.order,
                                          (T*)a.C);
     QT_LAUNCH("k_numeric");
