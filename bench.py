@@ -164,16 +164,25 @@ def _pmc_mean_kib(csv_path, counter, name_part):
     return sum(vals) / len(vals), len(vals)
 
 
-def traffic_from_counters(fetch_csv, write_csv, copy_fetch_csv, copy_write_csv, workload, prec, b):
+def _has_rows(csv_path, counter, name_part):
+    import csv
+    return any(r["Counter_Name"] == counter and name_part in r["Kernel_Name"] for r in csv.DictReader(open(csv_path)))
+
+
+def traffic_from_counters(fetch_csv, write_csv, copy_fetch_csv, copy_write_csv, workload, prec, b, out_dir=None):
     """Writes profiles/traffic_<prec>_<workload>.json: HBM-side bytes per
     launch of the numeric kernel from rocprofv3 --pmc FETCH_SIZE and
     WRITE_SIZE (KiB per dispatch), each scaled so that the plain copy of
     COPY_BYTES reads as COPY_BYTES."""
     if b == 64:   # the LDS-shared kernels of the 64-wide blocks
-        kname = {"f64": "k_numeric_f64_b64", "f32": "k_numeric<float, 64>", "bf16x3": "k_numeric_bf16x3_b64"}[prec]
+        kname = {"f64": "k_numeric_f64_b64", "f32": "k_numeric_f32_b64", "bf16x3": "k_numeric_bf16x3_b64"}[prec]
     else:
         kname = {"f64": f"k_numeric<double, {b}>", "f32": f"k_numeric<float, {b}>",
                  "bf16x3": f"k_numeric_bf16x3<{b}>"}[prec]
+        # C blocks launched grouped by inner index run in the by-k kernel
+        byk = kname.replace("k_numeric<", "k_numeric_byk<")
+        if byk != kname and _has_rows(fetch_csv, "FETCH_SIZE", byk):
+            kname = byk
     cf, _ = _pmc_mean_kib(copy_fetch_csv, "FETCH_SIZE", "copyBuffer")
     cw, _ = _pmc_mean_kib(copy_write_csv, "WRITE_SIZE", "copyBuffer")
     f_scale = COPY_BYTES / (cf * 1024.0)
@@ -187,9 +196,10 @@ def traffic_from_counters(fetch_csv, write_csv, copy_fetch_csv, copy_write_csv, 
            "copy_fetch_kib": cf, "copy_write_kib": cw, "fetch_scale": f_scale, "write_scale": w_scale,
            "fetch_bytes": fetch, "write_bytes": write, "traffic_bytes": fetch + write,
            "code_sha256": code_digest(*TRAFFIC_SOURCES)}
-    out = os.path.join(ROOT, "profiles", f"traffic_{prec}_{workload}.json")
+    out = os.path.join(out_dir or os.path.join(ROOT, "profiles"), f"traffic_{prec}_{workload}.json")
     json.dump(rec, open(out, "w"), indent=1)
     print(json.dumps(rec), flush=True)
+    return rec
 
 
 def timed_steps(qt, torch, hA, prec, steps, warmup):

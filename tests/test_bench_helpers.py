@@ -92,3 +92,42 @@ def test_row_sample_takes_leading_block_rows():
     # block products of the sampled rows: sum over their blocks (i, k) of the blocks in row k
     assert P_o == int(sum(rowcnt[k] for i, k in zip(I, J) if i < R))
     assert 2.0 * 4 ** 3 * P_o >= flops_half
+
+
+def _pmc_csv(path, counter, rows):
+    import csv
+    with open(path, "w", newline="") as f:
+        w = csv.DictWriter(f, fieldnames=["Kernel_Name", "Counter_Name", "Counter_Value"])
+        w.writeheader()
+        for name, v in rows:
+            w.writerow({"Kernel_Name": name, "Counter_Name": counter, "Counter_Value": v})
+    return str(path)
+
+
+def test_traffic_from_counters_scales_and_picks_the_kernel(tmp_path):
+    """The copy calibration scales each counter so that the 2 GiB copy reads
+    as 2 GiB; the numeric kernel's rows are averaged over its dispatches; a
+    workload launched by inner index is read from the by-k kernel's rows (not
+    from another kernel of the same block size in the run)."""
+    gib2 = bench.COPY_BYTES / 1024.0            # the copy's bytes in KiB
+    cf = _pmc_csv(tmp_path / "cf.csv", "FETCH_SIZE", [("__amd_rocclr_copyBuffer", gib2 / 2)] * 3)
+    cw = _pmc_csv(tmp_path / "cw.csv", "WRITE_SIZE", [("__amd_rocclr_copyBuffer", gib2)] * 3)
+    plain, byk = "void qt::k_numeric<double, 32>(double const*)", "void qt::k_numeric_byk<double, 32>(double const*)"
+    f = _pmc_csv(tmp_path / "f.csv", "FETCH_SIZE", [(plain, 999.0), (byk, 100.0), (byk, 300.0)])
+    w = _pmc_csv(tmp_path / "w.csv", "WRITE_SIZE", [(plain, 999.0), (byk, 50.0), (byk, 50.0)])
+    rec = bench.traffic_from_counters(f, w, cf, cw, "random65536", "f64", 32, out_dir=str(tmp_path))
+    assert rec["kernel"] == "k_numeric_byk<double, 32>" and rec["dispatches"] == [2, 2]
+    assert rec["fetch_scale"] == pytest.approx(2.0) and rec["write_scale"] == pytest.approx(1.0)
+    assert rec["fetch_bytes"] == pytest.approx(200.0 * 1024 * 2.0)
+    assert rec["write_bytes"] == pytest.approx(50.0 * 1024)
+    assert os.path.exists(tmp_path / "traffic_f64_random65536.json")
+    # without by-k rows: the plain kernel
+    f2 = _pmc_csv(tmp_path / "f2.csv", "FETCH_SIZE", [(plain, 400.0)])
+    w2 = _pmc_csv(tmp_path / "w2.csv", "WRITE_SIZE", [(plain, 100.0)])
+    rec = bench.traffic_from_counters(f2, w2, cf, cw, "decay32768", "f64", 32, out_dir=str(tmp_path))
+    assert rec["kernel"] == "k_numeric<double, 32>" and rec["traffic_bytes"] == pytest.approx((800.0 + 100.0) * 1024)
+    # the LDS-shared kernels of 64-wide blocks
+    f3 = _pmc_csv(tmp_path / "f3.csv", "FETCH_SIZE", [("qt::k_numeric_f32_b64(float const*)", 10.0)])
+    w3 = _pmc_csv(tmp_path / "w3.csv", "WRITE_SIZE", [("qt::k_numeric_f32_b64(float const*)", 10.0)])
+    assert bench.traffic_from_counters(f3, w3, cf, cw, "decay131072", "f32", 64,
+                                       out_dir=str(tmp_path))["kernel"] == "k_numeric_f32_b64"
