@@ -1034,7 +1034,7 @@ __device__ __forceinline__ int32_t batch_problem(const int64_t* __restrict__ ite
     return lo;
 }
 
-template <class T, int BS>
+template <class T, int BS, bool BUF>
 __device__ __forceinline__ void batch_item(const BatchProblem* __restrict__ probs, const char* __restrict__ base,
                                            const int64_t* __restrict__ item_base, int32_t nprob, int64_t it) {
     constexpr int WPB = Geo<BS>::WPB;
@@ -1048,8 +1048,8 @@ __device__ __forceinline__ void batch_item(const BatchProblem* __restrict__ prob
     const int32_t* seg = at<const int32_t>(base, P.seg);
     const int64_t s = P.order >= 0 ? at<const int32_t>(base, P.order)[q] : q;
     const int32_t t0 = seg[s];
-    wave_block<T, BS>(at<const T>(base, P.A), at<const T>(base, P.B), prodA, prodB, t0, seg[s + 1],
-                      at<T>(base, P.C) + (size_t)s * (BS * BS), sub, prodA[t0], prodB[t0]);
+    wave_block<T, BS, BUF>(at<const T>(base, P.A), at<const T>(base, P.B), prodA, prodB, t0, seg[s + 1],
+                           at<T>(base, P.C) + (size_t)s * (BS * BS), sub, prodA[t0], prodB[t0]);
 }
 
 template <int BS>
@@ -1096,17 +1096,21 @@ __device__ __forceinline__ void batch_item_lds(const BatchProblem* __restrict__ 
 }
 
 // Item dispatch for one (precision, block size, LDS sharing) instance; the
-// LDS instances exist at b = 64 only and run 256-thread workgroups.
+// LDS instances exist at b = 64 only and run 256-thread workgroups. BUF: the
+// per-wave fp64 / fp32 tiles write C through buffer stores (the flat grid:
+// batch64 FP32 6.60 instead of 6.91 ms, FP64 unchanged; the persistent
+// schedules are slower with them).
 template <int KIND, int BS, bool LDS> struct Item {
     static constexpr int THREADS = LDS ? 256 : 64;
+    template <bool BUF = false>
     static __device__ __forceinline__ void run(const BatchProblem* p, const char* base, const int64_t* ib, int32_t n,
                                                int64_t it) {
         if constexpr (LDS)
             batch_item_lds<KIND>(p, base, ib, n, it);
         else if constexpr (KIND == 0)
-            batch_item<double, BS>(p, base, ib, n, it);
+            batch_item<double, BS, BUF>(p, base, ib, n, it);
         else if constexpr (KIND == 1)
-            batch_item<float, BS>(p, base, ib, n, it);
+            batch_item<float, BS, BUF>(p, base, ib, n, it);
         else
             batch_item_bf16x3<BS>(p, base, ib, n, it);
     }
@@ -1119,7 +1123,7 @@ __global__ __launch_bounds__(LDS ? 256 : 64) void k_batch_flat(const BatchProble
                                                                  int32_t nprob) {
     const int64_t it = LDS ? xcd_logical<8>(blockIdx.x) : xcd_logical<>(blockIdx.x);
     if (it >= item_base[nprob]) return;
-    Item<KIND, BS, LDS>::run(probs, base, item_base, nprob, it);
+    Item<KIND, BS, LDS>::template run<true>(probs, base, item_base, nprob, it);
 }
 
 // Work of every item, for the balanced schedule: the block products of its
