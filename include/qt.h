@@ -231,8 +231,9 @@ qt_status qt_info(const qt_matrix* M, int64_t* n_rows, int64_t* n_cols, int32_t*
 qt_status qt_nblocks(const qt_matrix* M, int64_t* nblocks);
 
 /*
- * Copy a matrix out as a block list sorted by (I, J), row-major.
- * I, J: nblocks int32 each; values: nblocks*b*b entries of out_type
+ * Copy a matrix out as a block list sorted by (I, J), row-major: the nonzero
+ * blocks of the uniform block partition, zero blocks being absent (Sec. 3.1),
+ * the form qt_build takes them in. I, J: nblocks int32 each; values: nblocks*b*b entries of out_type
  * (QT_F64 -> double, QT_F32 -> float; rounding to nearest even when the
  * stored type is wider). `where` says whether the three arrays are host or
  * device memory. values may be NULL to copy out the block pattern only.
@@ -263,7 +264,8 @@ qt_status qt_to_blocks_noalloc(const qt_matrix* M, int32_t* I, int32_t* J, void*
                                void* stream);
 
 /*
- * Fetch chosen blocks: for t < count, block (I[t], J[t]) is looked up by
+ * Fetch chosen blocks (a zero block is NIL and not stored, Sec. 3.1): for
+ * t < count, block (I[t], J[t]) is looked up by
  * binary search over the matrix's Morton-ordered block keys and copied to
  * values + t*b*b (as out_type, like qt_to_blocks); found[t] is 1, or 0 with
  * a zero block when the block is not stored (a NIL block). I, J, values and
@@ -299,13 +301,15 @@ qt_status qt_levels(const qt_matrix* M, int64_t* nodes, int32_t max_levels, int3
 
 /*
  * Prepare the operand forms a multiply at `prec` reads (fp32 copy, bf16
- * hi/lo split) so that a later timed multiply does not build them. Optional:
+ * hi/lo split; the leaf products run in single or double precision as in
+ * Sec. 6.1) so that a later timed multiply does not build them. Optional:
  * qt_multiply builds them on first use. Thread-safe. Errors: OOM, DEVICE.
  */
 qt_status qt_prepare(const qt_matrix* M, qt_prec prec, void* stream);
 
-/* Release a handle (NULL is ignored). Its device memory is released in
- * order on the stream that created it. */
+/* Release a handle (NULL is ignored): a matrix, like a registered chunk
+ * (Sec. 2), belongs to the library from its creation until it is released.
+ * Its device memory is released in order on the stream that created it. */
 void qt_free(qt_matrix* M);
 
 /*
@@ -391,7 +395,8 @@ qt_status qt_tune_leaf(const qt_matrix* A, const qt_matrix* B, qt_prec prec, voi
                        int32_t* best_leaf, int32_t* leaves, float* ms, int32_t max_out, int32_t* n_tried);
 
 /*
- * Tuning cache: the choices of the tuners kept in a text file (one line per
+ * Tuning cache (the leaf size trades the quadtree's overhead against the
+ * leaf multiplies', Sec. 5): the choices of the tuners kept in a text file (one line per
  * choice, "key<TAB>value") and reused instead of timing again. The key is
  * the GPU architecture (e.g. gfx950), the block size, the precision, the
  * tuner and a class the caller names: for qt_tune_leaf_cached a pattern class
@@ -413,8 +418,9 @@ qt_status qt_tune_leaf_cached(const qt_matrix* A, const qt_matrix* B, qt_prec pr
 qt_status qt_plan_tune_cached(qt_plan* plan, void* stream, int reps, const char* batch_class, int32_t* schedule,
                               int32_t* cached);
 
-/* Per-phase GPU timing of qt_multiply, from HIP events recorded on the
- * multiply's stream. qt_profile(1) starts recording (and clears totals),
+/* Per-phase GPU timing of qt_multiply (the two phases of Algorithm 1's
+ * multiply: the quadtree traversal, Sec. 3.2, and the leaf products, Sec. 4.1),
+ * from HIP events recorded on the multiply's stream. qt_profile(1) starts recording (and clears totals),
  * qt_profile(0) stops. qt_profile_read synchronizes on the recorded events
  * and returns the summed milliseconds of the symbolic phase (traversal and
  * product lists) and of the numeric kernel, the number of multiplies timed,
@@ -445,10 +451,11 @@ qt_status qt_probe_mfma(qt_prec prec, void* stream, double* tflops);
  * not 16, 32 or 64), UNSUPPORTED (BF16X3 at b = 16), OOM, DEVICE. */
 qt_status qt_probe_batched(qt_prec prec, int32_t block_size, int64_t count, void* stream, double* tflops);
 
-/* Text of the last error on this thread ("" if none). */
+/* Text of the last error on this thread ("" if none). A library utility, no
+ * operation of the paper. */
 const char* qt_last_error(void);
 
-/* Library version string. */
+/* Library version string. A library utility, no operation of the paper. */
 const char* qt_version(void);
 
 #ifdef __cplusplus
