@@ -469,7 +469,21 @@ __global__ __launch_bounds__(64, (MinWaves<T, BS>::value)) void k_numeric(const 
 }
 
 // k_numeric for C blocks launched grouped by inner index (`order` is that
-// order), writing C with buffer stores.
+// order), writing C with buffer stores. Such C blocks average about one block
+// product, so the kernel is bound by writing C; fewer waves in flight then
+// contend less for HBM and leave slots to the next multiply's traversal. The
+// FP32 instance (registers for seven waves per SIMD) is held to five by LDS
+// it never touches (ByKCap): random65536 FP32 steps 1.350 instead of 1.402 ms
+// in a loop, lone launches 0.96-0.98 instead of 1.00-1.02 ms. At four waves,
+// or with the FP64 instance held below its five, it was slower.
+template <class T, int BS> struct ByKCap { static constexpr int waves = 0; };
+template <> struct ByKCap<float, 32> { static constexpr int waves = 5; };
+constexpr int kLdsPerCU = 160 * 1024;   // gfx950
+
+// Dynamic LDS per one-wave workgroup that holds the kernel to `waves` waves
+// per SIMD (four SIMDs per CU); 0: no cap.
+constexpr size_t occupancy_cap_lds(int waves) { return waves > 0 ? (size_t)(kLdsPerCU / (4 * waves)) : 0; }
+
 template <class T, int BS>
 __global__ __launch_bounds__(64, (MinWaves<T, BS>::value)) void k_numeric_byk(const T* __restrict__ A,
                                                                              const T* __restrict__ B,
@@ -776,8 +790,9 @@ static void launch_t(const NumericArgs& a, hipStream_t s) {
     typedef Geo<BS> G;
     const unsigned grid = xcd_grid<>((int64_t)a.nseg * G::WPB);
     if (a.by_k && a.order) {
-        k_numeric_byk<T, BS><<<grid, 64, 0, s>>>((const T*)a.A, (const T*)a.B, a.prodA, a.prodB, a.seg, a.nseg,
-                                                 a.order, (T*)a.C);
+        const size_t cap = occupancy_cap_lds(ByKCap<T, BS>::waves);
+        k_numeric_byk<T, BS><<<grid, 64, cap, s>>>((const T*)a.A, (const T*)a.B, a.prodA, a.prodB, a.seg, a.nseg,
+                                                   a.order, (T*)a.C);
         QT_LAUNCH("k_numeric_byk");
         return;
     }
